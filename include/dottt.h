@@ -1,0 +1,176 @@
+/*
+ * dottt.h — C ABI of an MI355X (gfx950) library that counts (delta13, delta12, delta23)-temporal
+ * triangles of a directed temporal multigraph exactly, per triangle type, after Pashanasangi &
+ * Seshadhri, "Faster and Generalized Temporal Triangle Counting, via Degeneracy Ordering"
+ * (KDD 2021).
+ *
+ * Conventions for every call:
+ *   - The return value is DT_OK (0) or a negative DT_E* code; nothing is thrown across the ABI.
+ *     dt_last_error() gives a human-readable message for the calling thread's last failure.
+ *   - Pointers documented as "host" are ordinary host memory; "device" pointers are HIP device
+ *     memory of the context's device (for example torch.cuda tensors' data_ptr()).
+ *   - Inputs are copied; the library never keeps a caller pointer after a call returns.
+ *   - Outputs go to caller-owned buffers.  Handles (dt_ctx, dt_graph, dt_server) own the device
+ *     memory they allocate until the matching *_destroy / *_free / *_stop call.
+ *   - Counts are exact int64.  out[k] is the count of type T(k+1) of Figure 2 (Section 1.1).
+ *   - A dt_ctx and the graphs made from it are used by one host thread at a time; the dt_server_*
+ *     calls are safe to call from any number of threads.
+ *
+ * Reading of the paper fixed by this library (the paper assumes distinct timestamps, Section 1.1
+ * and Section 3, and says equal ones are allowed without defining them):
+ *   - edges are ordered by the key (t, input index): equal timestamps follow input order;
+ *     delta limits compare timestamps t;
+ *   - self-loops (src == dst) are dropped at load; identical (u, v, t) edges are distinct edges;
+ *   - a window [t_lo, t_hi] (inclusive) restricts all three edges of a triangle to it, which is
+ *     the same as counting the graph filtered to the window.
+ */
+#ifndef DOTTT_H
+#define DOTTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DT_OK         0
+#define DT_EINVAL   (-22)   /* bad argument: null pointer, node id >= n, negative delta, t_lo > t_hi */
+#define DT_ENOMEM   (-12)   /* device allocation failed or would exceed the context's HBM budget   */
+#define DT_EOVERFLOW (-75)  /* a size limit of this version, or a count that may not fit in int64   */
+#define DT_EBUSY    (-16)   /* server full / graph busy                                             */
+#define DT_ETIMEDOUT (-110) /* dt_server_wait timed out                                             */
+#define DT_EDEVICE   (-5)   /* a HIP runtime error                                                  */
+#define DT_ENOTBUILT (-38)  /* the graph has not been through dt_graph_build                        */
+
+#define DT_INF INT64_MAX    /* a delta that behaves as infinity (any delta >= the graph's span does) */
+
+typedef struct dt_ctx dt_ctx;
+typedef struct dt_graph dt_graph;
+typedef struct dt_server dt_server;
+
+/* A count query (Definition 1, Section 1.1): a triple (e1, e2, e3) with e1 < e2 < e3 counts when
+ * t2 - t1 <= d12, t3 - t2 <= d23 and t3 - t1 <= d13.  Deltas must be >= 0; the library rewrites
+ * them to the equivalent triple d12' = min(d12, d13), d23' = min(d23, d13),
+ * d13' = min(d13, d12' + d23'), which defines the same triangles and is what the per-ordering
+ * counting procedures (Section 5, Appendix A) assume.  [t_lo, t_hi] is an inclusive window;
+ * INT64_MIN..INT64_MAX is the whole graph. */
+typedef struct {
+    int64_t d13, d12, d23;
+    int64_t t_lo, t_hi;
+} dt_query;
+
+/* Graph statistics; the first block mirrors the columns of Table 1 (Section 6). */
+typedef struct {
+    uint64_t n;                    /* vertices (ids 0..n-1)                                       */
+    uint64_t m;                    /* temporal edges passed to dt_graph_load                      */
+    uint64_t m_loaded;             /* temporal edges kept (self-loops dropped)                    */
+    uint64_t self_loops_dropped;
+    uint64_t m_static;             /* pairs joined by at least one temporal edge (Section 3)     */
+    uint64_t n_static_triangles;   /* after dt_graph_build, else 0                                */
+    uint32_t degeneracy;           /* after dt_graph_build: max core number (Definition, Sec. 3) */
+    uint32_t max_multiplicity;     /* most temporal edges on one pair, both directions           */
+    int64_t  t_min, t_max;         /* over kept edges                                             */
+    /* build products (after dt_graph_build) */
+    uint32_t max_out_degree;       /* of the orientation; at most the degeneracy                  */
+    uint32_t peel_rounds;          /* removal rounds of the parallel core peel                    */
+    uint64_t sum_sigma3_lo, sum_sigma3_hi; /* sum over static triangles of the product of the
+                                              three pair multiplicities, 128-bit                  */
+    uint64_t n_light_triangles, n_heavy_triangles; /* split chosen by the scheduler               */
+    uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count (see DESIGN)     */
+    double   ms_load, ms_peel, ms_orient, ms_triangles, ms_schedule; /* phase wall times          */
+} dt_stats;
+
+/* Tuning of the count scheduler.  A static triangle whose two source-incident pairs carry
+ * sigma_uv * sigma_uw <= light_pair_cap temporal-edge pairs is counted by one lane enumerating
+ * those pairs (the pairwise form of Lemma 1); larger ones go to the prefix-count path of
+ * Algorithms 1-3 split into chunks of `heavy_chunk` source edges.  Zero fields keep the default. */
+typedef struct {
+    uint32_t light_pair_cap;       /* default 64                                                  */
+    uint32_t heavy_chunk;          /* default 256, a multiple of 64, at most 1024                 */
+    uint32_t light_block;          /* threads per block of the light kernel, default 256          */
+    uint32_t force_path;           /* 0: split by light_pair_cap; 1: every triangle light;
+                                      2: every triangle heavy (diagnostics and tests)             */
+} dt_tuning;
+
+const char *dt_strerror(int code);
+/* Message of the calling thread's last failed call ("" if none). */
+const char *dt_last_error(void);
+
+/* Context on HIP device `hip_device`.  hbm_budget_bytes caps the device memory the context's
+ * graphs may hold (0 = no cap beyond the device).  Creates one HIP stream that all synchronous
+ * calls use. */
+int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out);
+int dt_ctx_destroy(dt_ctx *ctx);
+/* Device memory currently held by the context's graphs and scratch. */
+int dt_ctx_memory(const dt_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* Load a temporal graph (Section 3: a collection of m directed temporal edges (u, v, t)).
+ * src, dst (uint32, < n) and t (int64) are host arrays of m entries; input position is the
+ * tie-break of equal timestamps.  Extracts the static graph G (its pairs, Section 3) and groups
+ * the temporal edges by pair and direction in key order (the CSR store of Section 4).
+ * Limits of this version: m < 2^31, and (t_max - t_min) < 2^(64 - ceil(log2 m)) - 1 (so that a
+ * timestamp and an input index pack into one 64-bit key); otherwise DT_EOVERFLOW. */
+int dt_graph_load(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                  const int64_t *t, dt_graph **out);
+/* The same with src, dst and t already in device memory of the context's device. */
+int dt_graph_load_device(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src_dev,
+                         const uint32_t *dst_dev, const int64_t *t_dev, dt_graph **out);
+
+/* Degeneracy ordering by a parallel k-core peel (Section 3, Definitions of degeneracy and of the
+ * degeneracy ordering), orientation of G into the DAG G_prec (Section 3), static triangle
+ * enumeration in G_prec (Section 5, and the proof of Theorem 1), and the count schedule.  The
+ * triangle list stays resident for every later count.  May be called again to rebuild. */
+int dt_graph_build(dt_graph *g);
+int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tuning);
+int dt_graph_stats(const dt_graph *g, dt_stats *out);
+
+/* Per-type counts of (d13, d12, d23)-temporal triangles (Algorithm 4, Section 5): for every
+ * static triangle <u, v, w> with u first in the ordering, every temporal ordering (Figure 3) and
+ * orientation (Figure 4) is counted (Algorithms 1-3) and added to the type given by Table 2.
+ * out: host int64[8].  Synchronous on the context's stream. */
+int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]);
+/* The same, enqueued on `hip_stream` (a hipStream_t; NULL = the context's stream).  out8 is
+ * device memory or pinned host memory that stays valid until the stream reaches the work. */
+int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream);
+/* Diagnostic: the 48 per-(ordering, orientation) counts, out[(pi-1)*8 + (rho-1)], with u, v, w
+ * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
+int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);
+
+/* Batched counting: query i on graphs[i] for i < k (graphs may repeat), all in one persistent
+ * launch over a shared work table.  out: host int64[k][8]. */
+int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
+                   int64_t (*out)[8]);
+
+/* Diagnostics of the build products, for tests.  Host outputs.
+ * dt_graph_order: core[v] (core number) and rank[v] (position of v in the ordering) for all n.
+ * dt_graph_triangles: the static triangles as node-id triples (a < b < c), in no fixed order;
+ * writes min(count, cap) triples and sets *count. */
+int dt_graph_order(const dt_graph *g, uint32_t *core, uint32_t *rank);
+int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t *count);
+
+int dt_graph_free(dt_graph *g);
+
+/* Serving: a request loop that keeps graphs resident in HBM and batches count queries of
+ * differing deltas and windows into running device work (continuous batching). */
+typedef struct {
+    uint64_t hbm_budget_bytes;     /* memory the served graphs may hold (0 = the context's)        */
+    uint32_t max_inflight_queries; /* queries admitted to the device at once (0 = 4096)            */
+    uint32_t max_batch;            /* queries per device launch (0 = 512)                          */
+    int64_t  deadline_ns;          /* per-query deadline; 0 = none                                 */
+} dt_server_cfg;
+
+int dt_server_start(dt_ctx *ctx, const dt_server_cfg *cfg, dt_server **out);
+/* Admit a built graph; DT_ENOMEM if it does not fit the server's budget.  The server does not
+ * take ownership: free the graph only after dt_server_stop. */
+int dt_server_add_graph(dt_server *s, dt_graph *g, uint32_t *graph_id);
+int dt_server_submit(dt_server *s, uint32_t graph_id, const dt_query *q, uint64_t *ticket);
+/* Wait for a ticket's counts; timeout_ns < 0 waits forever.  DT_ETIMEDOUT leaves the ticket
+ * pending.  Each ticket can be waited for once. */
+int dt_server_wait(dt_server *s, uint64_t ticket, int64_t out[8], int64_t timeout_ns);
+int dt_server_stop(dt_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOTTT_H */

@@ -1,0 +1,396 @@
+// The C ABI (include/dottt.h): contexts, graph load / build / statistics, counts.
+#include <cstring>
+
+#include "internal.h"
+
+namespace dt {
+const char *last_error();
+
+namespace {
+
+constexpr unsigned kBlock = 256;
+
+struct DeviceGuard {   // make the context's device current for the duration of a call
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// node ids (a < b < c) of every resident triangle
+__global__ void k_tri_vertices(uint64_t nt, const uint32_t *__restrict__ tri, uint32_t n,
+                               const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
+                               const uint32_t *__restrict__ order, uint32_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nt) return;
+    const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1];
+    // tail of e_uv: the last u with dag_row[u] <= e_uv
+    uint32_t lo = 0, len = n;
+    while (len > 0) {
+        uint32_t half = len >> 1;
+        if (dag_row[lo + half + 1] <= e_uv) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    uint32_t a = order[lo], b = order[dag_col[e_uv]], c = order[dag_col[e_uw]];
+    uint32_t x = min(a, min(b, c)), z = max(a, max(b, c));
+    uint32_t y = a ^ b ^ c ^ x ^ z;
+    out[3 * i] = x;
+    out[3 * i + 1] = y;
+    out[3 * i + 2] = z;
+}
+
+int check_graph(const dt_graph *g, bool need_built) {
+    if (!g) return fail(DT_EINVAL, "null graph");
+    if (need_built && !g->built) return fail(DT_ENOTBUILT, "graph not built (call dt_graph_build)");
+    return DT_OK;
+}
+
+int load_common(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                const int64_t *t, bool on_device, dt_graph **out) {
+    if (!ctx || !out) return fail(DT_EINVAL, "null context or output handle");
+    *out = nullptr;
+    if (m && (!src || !dst || !t)) return fail(DT_EINVAL, "null edge array");
+    if (m >= (1ull << 31)) return fail(DT_EOVERFLOW, "m = %llu edges; this version takes m < 2^31",
+                                       (unsigned long long)m);
+    DeviceGuard dg(ctx->device);
+    double t0 = now_ms();
+    dt_graph *g = new dt_graph();
+    g->ctx = ctx;
+    g->n = n;
+    g->m_in = m;
+    int rc = DT_OK;
+    if (on_device || m == 0) {
+        rc = load_graph(g, src, dst, t);
+    } else {
+        DevMem ds, dd, dtm;
+        rc = dev_alloc(ctx, ds, m * 4);
+        if (rc == DT_OK) rc = dev_alloc(ctx, dd, m * 4);
+        if (rc == DT_OK) rc = dev_alloc(ctx, dtm, m * 8);
+        if (rc == DT_OK) {
+            hipError_t e = hipMemcpy(ds.ptr, src, m * 4, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(dd.ptr, dst, m * 4, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(dtm.ptr, t, m * 8, hipMemcpyHostToDevice);
+            if (e != hipSuccess) rc = fail(DT_EDEVICE, "copy of the edge arrays failed: %s", hipGetErrorString(e));
+        }
+        if (rc == DT_OK) rc = load_graph(g, ds.as<uint32_t>(), dd.as<uint32_t>(), dtm.as<int64_t>());
+    }
+    if (rc != DT_OK) {
+        delete g;
+        return rc;
+    }
+    g->ms_load = now_ms() - t0;
+    *out = g;
+    return DT_OK;
+}
+
+}  // namespace
+}  // namespace dt
+
+using namespace dt;
+
+extern "C" {
+
+const char *dt_strerror(int code) {
+    switch (code) {
+        case DT_OK: return "ok";
+        case DT_EINVAL: return "invalid argument";
+        case DT_ENOMEM: return "out of device memory or over the HBM budget";
+        case DT_EOVERFLOW: return "size limit exceeded or count may overflow int64";
+        case DT_EBUSY: return "busy";
+        case DT_ETIMEDOUT: return "timed out";
+        case DT_EDEVICE: return "HIP runtime error";
+        case DT_ENOTBUILT: return "graph not built";
+        default: return "unknown error";
+    }
+}
+
+const char *dt_last_error(void) { return dt::last_error(); }
+
+int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
+    clear_error();
+    if (!out) return fail(DT_EINVAL, "null output handle");
+    *out = nullptr;
+    int ndev = 0;
+    DT_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev)
+        return fail(DT_EINVAL, "device %d not present (%d devices)", hip_device, ndev);
+    DeviceGuard dg(hip_device);
+    dt_ctx *c = new dt_ctx();
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, hip_device);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned_out, 64 * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+        if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return fail(DT_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
+    }
+    if (c->num_cus <= 0) c->num_cus = 256;
+    int rc = dev_alloc(c, c->out8, 64 * sizeof(int64_t));
+    if (rc != DT_OK) {
+        (void)hipStreamDestroy(c->stream);
+        (void)hipHostFree(c->pinned_out);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return DT_OK;
+}
+
+int dt_ctx_destroy(dt_ctx *ctx) {
+    clear_error();
+    if (!ctx) return fail(DT_EINVAL, "null context");
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->partials.reset();
+    ctx->out8.reset();
+    ctx->heavy_vals.reset();
+    if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
+    (void)hipEventDestroy(ctx->ev_a);
+    (void)hipEventDestroy(ctx->ev_b);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return DT_OK;
+}
+
+int dt_ctx_memory(const dt_ctx *ctx, uint64_t *used, uint64_t *budget) {
+    clear_error();
+    if (!ctx) return fail(DT_EINVAL, "null context");
+    if (used) *used = ctx->used.load();
+    if (budget) *budget = ctx->budget;
+    return DT_OK;
+}
+
+int dt_graph_load(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                  const int64_t *t, dt_graph **out) {
+    clear_error();
+    return load_common(ctx, n, m, src, dst, t, false, out);
+}
+
+int dt_graph_load_device(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
+                         const int64_t *t, dt_graph **out) {
+    clear_error();
+    return load_common(ctx, n, m, src, dst, t, true, out);
+}
+
+int dt_graph_build(dt_graph *g) {
+    clear_error();
+    DT_TRY(check_graph(g, false));
+    DeviceGuard dg(g->ctx->device);
+    g->built = false;
+    double t0 = now_ms();
+    DT_TRY(peel(g));
+    double t1 = now_ms();
+    DT_TRY(orient(g));
+    double t2 = now_ms();
+    DevMem tri;
+    DT_TRY(enumerate_triangles(g, tri));
+    double t3 = now_ms();
+    DT_TRY(make_schedule(g, tri));
+    double t4 = now_ms();
+    g->ms_peel = t1 - t0;
+    g->ms_orient = t2 - t1;
+    g->ms_tri = t3 - t2;
+    g->ms_sched = t4 - t3;
+    g->built = true;
+    return DT_OK;
+}
+
+int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
+    clear_error();
+    DT_TRY(check_graph(g, false));
+    if (!tu) return fail(DT_EINVAL, "null tuning");
+    dt_tuning nt = g->tuning;
+    if (tu->light_pair_cap) nt.light_pair_cap = tu->light_pair_cap;
+    if (tu->heavy_chunk) nt.heavy_chunk = tu->heavy_chunk;
+    if (tu->light_block) nt.light_block = tu->light_block;
+    if (tu->force_path > 2) return fail(DT_EINVAL, "force_path must be 0, 1 or 2");
+    nt.force_path = tu->force_path;
+    if (nt.heavy_chunk != 256) return fail(DT_EINVAL, "heavy_chunk must be 256 in this version");
+    if (nt.light_block != 256) return fail(DT_EINVAL, "light_block must be 256 in this version");
+    g->tuning = nt;
+    if (!g->built) return DT_OK;
+    // re-split the resident triangles under the new tuning
+    DeviceGuard dg(g->ctx->device);
+    Schedule &S = g->sched;
+    DevMem tri;
+    DT_TRY(dev_alloc(g->ctx, tri, g->n_tri * 12));
+    if (S.n_light) DT_HIP(hipMemcpy(tri.ptr, S.light.ptr, S.n_light * 12, hipMemcpyDeviceToDevice));
+    if (S.n_heavy)
+        DT_HIP(hipMemcpy(tri.as<uint8_t>() + S.n_light * 12, S.heavy.ptr, S.n_heavy * 12, hipMemcpyDeviceToDevice));
+    return make_schedule(g, tri);
+}
+
+int dt_graph_stats(const dt_graph *g, dt_stats *out) {
+    clear_error();
+    DT_TRY(check_graph(g, false));
+    if (!out) return fail(DT_EINVAL, "null output");
+    memset(out, 0, sizeof(*out));
+    out->n = g->n;
+    out->m = g->m_in;
+    out->m_loaded = g->m;
+    out->self_loops_dropped = g->self_loops;
+    out->m_static = g->m_s;
+    out->max_multiplicity = g->max_mult;
+    out->t_min = g->m ? g->t_min : INT64_MAX;
+    out->t_max = g->m ? g->t_max : INT64_MIN;
+    out->ms_load = g->ms_load;
+    if (g->built) {
+        out->n_static_triangles = g->n_tri;
+        out->degeneracy = g->kappa;
+        out->max_out_degree = g->max_outdeg;
+        out->peel_rounds = g->peel_rounds;
+        out->sum_sigma3_lo = (uint64_t)g->sum_sigma3;
+        out->sum_sigma3_hi = (uint64_t)(g->sum_sigma3 >> 64);
+        out->n_light_triangles = g->sched.n_light;
+        out->n_heavy_triangles = g->sched.n_heavy;
+        out->alg_bytes = g->alg_bytes;
+        out->ms_peel = g->ms_peel;
+        out->ms_orient = g->ms_orient;
+        out->ms_triangles = g->ms_tri;
+        out->ms_schedule = g->ms_sched;
+    }
+    return DT_OK;
+}
+
+static int count_guarded(dt_graph *g, const dt_query *q, DQuery *dq, bool *empty) {
+    DT_TRY(check_graph(g, true));
+    DT_TRY(normalise_query(g, q, dq, empty));
+    if ((g->sum_sigma3 >> 63) != 0)
+        return fail(DT_EOVERFLOW, "the sum of multiplicity products exceeds 2^63; counts may not fit int64");
+    return DT_OK;
+}
+
+int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]) {
+    clear_error();
+    if (!out) return fail(DT_EINVAL, "null output");
+    DQuery dq;
+    bool empty = false;
+    DT_TRY(count_guarded(g, q, &dq, &empty));
+    if (empty || g->n_tri == 0) {
+        for (int i = 0; i < 8; ++i) out[i] = 0;
+        return DT_OK;
+    }
+    dt_ctx *ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    DT_TRY(count_enqueue(g, dq, ctx->out8.as<int64_t>(), ctx->stream, false, nullptr));
+    DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    DT_HIP(hipStreamSynchronize(ctx->stream));
+    memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
+    return DT_OK;
+}
+
+int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream) {
+    clear_error();
+    if (!out8) return fail(DT_EINVAL, "null output");
+    DQuery dq;
+    bool empty = false;
+    DT_TRY(count_guarded(g, q, &dq, &empty));
+    dt_ctx *ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    if (empty || g->n_tri == 0) {
+        DT_HIP(hipMemsetAsync(out8, 0, 8 * sizeof(int64_t), s));
+        return DT_OK;
+    }
+    // the scratch (partials, heavy prefixes) belongs to the context: a foreign stream waits for
+    // the context's stream before the count and the context's stream waits for it afterwards
+    if (s != ctx->stream) {
+        DT_HIP(hipEventRecord(ctx->ev_a, ctx->stream));
+        DT_HIP(hipStreamWaitEvent(s, ctx->ev_a, 0));
+    }
+    DT_TRY(count_enqueue(g, dq, out8, s, false, nullptr));
+    if (s != ctx->stream) {
+        DT_HIP(hipEventRecord(ctx->ev_b, s));
+        DT_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
+    }
+    return DT_OK;
+}
+
+int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]) {
+    clear_error();
+    if (!out) return fail(DT_EINVAL, "null output");
+    DQuery dq;
+    bool empty = false;
+    DT_TRY(count_guarded(g, q, &dq, &empty));
+    if (empty || g->n_tri == 0) {
+        for (int i = 0; i < 48; ++i) out[i] = 0;
+        return DT_OK;
+    }
+    dt_ctx *ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    DevMem cells;
+    DT_TRY(dev_alloc(ctx, cells, 48 * sizeof(int64_t)));
+    DT_TRY(count_enqueue(g, dq, nullptr, ctx->stream, true, cells.as<int64_t>()));
+    DT_HIP(hipMemcpyAsync(out, cells.ptr, 48 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    DT_HIP(hipStreamSynchronize(ctx->stream));
+    return DT_OK;
+}
+
+int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
+                   int64_t (*out)[8]) {
+    clear_error();
+    if (!ctx) return fail(DT_EINVAL, "null context");
+    if (k && (!graphs || !queries || !out)) return fail(DT_EINVAL, "null batch array");
+    DeviceGuard dg(ctx->device);
+    return count_batch(ctx, k, graphs, queries, out);
+}
+
+int dt_graph_order(const dt_graph *g, uint32_t *core, uint32_t *rank) {
+    clear_error();
+    DT_TRY(check_graph(g, true));
+    DeviceGuard dg(g->ctx->device);
+    if (core && g->n) DT_HIP(hipMemcpy(core, g->core.ptr, (uint64_t)g->n * 4, hipMemcpyDeviceToHost));
+    if (rank && g->n) DT_HIP(hipMemcpy(rank, g->rank.ptr, (uint64_t)g->n * 4, hipMemcpyDeviceToHost));
+    return DT_OK;
+}
+
+int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t *count) {
+    clear_error();
+    DT_TRY(check_graph(g, true));
+    if (!count) return fail(DT_EINVAL, "null count");
+    *count = g->n_tri;
+    if (!out || cap == 0 || g->n_tri == 0) return DT_OK;
+    DeviceGuard dg(g->ctx->device);
+    const Schedule &S = g->sched;
+    DevMem buf;
+    DT_TRY(dev_alloc(g->ctx, buf, g->n_tri * 12));
+    hipStream_t st = g->ctx->stream;
+    if (S.n_light)
+        k_tri_vertices<<<grid_for(S.n_light, kBlock), kBlock, 0, st>>>(S.n_light, S.light.as<uint32_t>(), g->n,
+            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(), buf.as<uint32_t>());
+    if (S.n_heavy)
+        k_tri_vertices<<<grid_for(S.n_heavy, kBlock), kBlock, 0, st>>>(S.n_heavy, S.heavy.as<uint32_t>(), g->n,
+            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(),
+            buf.as<uint32_t>() + 3 * S.n_light);
+    DT_HIP(hipGetLastError());
+    uint64_t k = cap < g->n_tri ? cap : g->n_tri;
+    DT_HIP(hipMemcpyAsync(out, buf.ptr, k * 12, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    return DT_OK;
+}
+
+int dt_graph_free(dt_graph *g) {
+    clear_error();
+    if (!g) return fail(DT_EINVAL, "null graph");
+    DeviceGuard dg(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    delete g;
+    return DT_OK;
+}
+
+}  // extern "C"

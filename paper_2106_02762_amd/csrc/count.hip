@@ -1,0 +1,630 @@
+// Per-triangle temporal counting (Algorithm 4 with Algorithms 1-3, Section 5 and Appendix A) and
+// the per-type reduction.
+//
+// Every static triangle <u, v, w> (u first in the degeneracy ordering, v before w) owns six
+// key-sorted edge lists: uv+ (u->v), uv- (v->u), uw+, uw-, vw+, vw-.  A cell (pi, rho) of the
+// paper is an ordering pi (Figure 3) and one direction per pair rho (Figure 4); its count goes to
+// type psi(pi, rho) (Table 2).  Only the lists on the two pairs at u are ever walked; the {v,w}
+// lists are only searched (Section 5, "source vertex").
+//
+// Two paths, chosen per triangle by the scheduler:
+//  - light: one lane walks every pair (x, y) of edges from the uv and uw lists (the pairwise form
+//    of Lemma 1).  With x, y fixed and ordered, the third edge z on {v,w} is first, middle or last,
+//    and each case is one key range of the vw list found by binary search; that is cells
+//    (pi5|pi6), (pi3|pi4) and (pi1|pi2) respectively.
+//  - heavy: the prefix-count procedures.  For every edge on a uv or uw list a prefix pass stores
+//    the cumulative counts that Algorithms 1-3 need (CEC of Section 5), and a second pass walks
+//    the same edges as e2 (Algorithm 1: pi1/pi2), e1 (Algorithm 2: pi3/pi4) and e2 (Algorithm 3:
+//    pi5/pi6), each with a constant number of binary searches, split into chunks across
+//    workgroups.  The formulas are the paper's, restated for keys (t, input index) so that equal
+//    timestamps are handled, with the region bounds written as max/min clamps.
+//
+// Counts are int64 and summed per lane, per wave, per block, then per launch, with no atomics on
+// the result (cells mode, a diagnostic, uses atomics).
+#include "internal.h"
+
+namespace dt {
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// cell and type tables
+// ---------------------------------------------------------------------------------------------
+// Figure 4: orientation number from the direction bit of each pair (0 = from the earlier vertex
+// of the ordering u < v < w, 1 = towards it).
+__host__ __device__ constexpr int rho_of(int d_uv, int d_uw, int d_vw) {
+    constexpr int tab[8] = {/*000*/ 1, /*001*/ 3, /*010*/ 4, /*011*/ 2,
+                            /*100*/ 5, /*101*/ 7, /*110*/ 8, /*111*/ 6};
+    return tab[(d_uv << 2) | (d_uw << 1) | d_vw];
+}
+
+// Table 2: psi[pi - 1][rho - 1] = type.
+__host__ __device__ constexpr int psi_of(int pi, int rho) {
+    constexpr int tab[6][8] = {
+        {7, 6, 5, 8, 3, 2, 4, 1},
+        {5, 3, 7, 4, 6, 1, 8, 2},
+        {3, 2, 1, 4, 7, 6, 8, 5},
+        {1, 7, 3, 8, 2, 5, 4, 6},
+        {6, 1, 2, 8, 5, 3, 4, 7},
+        {2, 5, 6, 4, 1, 7, 8, 3},
+    };
+    return tab[pi - 1][rho - 1];
+}
+
+// 0-based type index and cell index of (pi, direction bits)
+template <int PI, int DUV, int DUW, int DVW> struct Cell {
+    static constexpr int rho = rho_of(DUV, DUW, DVW);
+    static constexpr int type = psi_of(PI, rho) - 1;
+    static constexpr int cell = (PI - 1) * 8 + (rho - 1);
+};
+
+// accumulators: per-lane type counts, or (diagnostic) global atomics per cell
+template <bool CELLS> struct Acc;
+template <> struct Acc<false> {
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t *cells = nullptr;
+    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
+        t[CA::type] += first ? v : 0;
+        t[CB::type] += first ? 0 : v;
+    }
+    template <class C> __device__ __forceinline__ void add(int64_t v) { t[C::type] += v; }
+};
+template <> struct Acc<true> {
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t *cells = nullptr;
+    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
+        if (v) atomicAdd((unsigned long long *)(cells + (first ? CA::cell : CB::cell)),
+                         (unsigned long long)v);
+    }
+    template <class C> __device__ __forceinline__ void add(int64_t v) {
+        if (v) atomicAdd((unsigned long long *)(cells + C::cell), (unsigned long long)v);
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// searches on key-sorted lists
+// ---------------------------------------------------------------------------------------------
+// first index in [lo, hi) whose key is >= K (hi if none)
+__device__ __forceinline__ uint32_t lower(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi,
+                                          uint64_t K) {
+    uint32_t len = hi - lo;
+    while (len > 0) {
+        uint32_t half = len >> 1;
+        if (key[lo + half] < K) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
+}
+
+// key bound of "t < x" for a relative time x
+__device__ __forceinline__ uint64_t before_time(int64_t x, const DQuery &q) {
+    return x <= 0 ? 0ull : (x > q.span ? ~0ull : ((uint64_t)x << q.shift));
+}
+
+struct Lists {
+    uint32_t lo[6], hi[6];   // uv+, uv-, uw+, uw-, vw+, vw- (clipped to the window)
+};
+
+__device__ __forceinline__ void load_lists(const uint32_t *__restrict__ eoff, uint32_t e_uv,
+                                           uint32_t e_uw, uint32_t e_vw, const uint64_t *__restrict__ key,
+                                           const DQuery &q, Lists &L) {
+    const uint32_t es[3] = {e_uv, e_uw, e_vw};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1], c = eoff[2 * es[p] + 2];
+        L.lo[2 * p] = a;
+        L.hi[2 * p] = b;
+        L.lo[2 * p + 1] = b;
+        L.hi[2 * p + 1] = c;
+    }
+    if (q.windowed) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            uint32_t lo = L.lo[i], hi = L.hi[i];
+            L.lo[i] = lower(key, lo, hi, q.klo);
+            L.hi[i] = lower(key, L.lo[i], hi, q.khi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// light path: one lane per triangle, every (uv edge, uw edge) pair
+// ---------------------------------------------------------------------------------------------
+template <bool CELLS, int A, int B, int C>
+__device__ __forceinline__ void light_third(const uint64_t *__restrict__ key, const Lists &L,
+                                            const DQuery &q, bool uv_first, uint64_t k_lo,
+                                            uint64_t k_hi, int64_t t_lo, int64_t t_hi, int64_t gap,
+                                            Acc<CELLS> &acc) {
+    const uint32_t zb = L.lo[4 + C], ze = L.hi[4 + C];
+    if (zb == ze) return;
+    const uint32_t below_lo = lower(key, zb, ze, k_lo);   // z with key < k_lo
+    const uint32_t below_hi = lower(key, below_lo, ze, k_hi);
+    // z first: e1 = z, e2 = earlier of x, y, e3 = later
+    if (gap <= q.d23) {
+        int64_t from = t_lo - q.d12 > t_hi - q.d13 ? t_lo - q.d12 : t_hi - q.d13;
+        uint32_t s = lower(key, zb, below_lo, before_time(from, q));
+        acc.template add2<Cell<5, A, B, C>, Cell<6, A, B, C>>(uv_first, (int64_t)(below_lo - s));
+    }
+    // z in the middle: t_hi - d23 <= t_z <= t_lo + d12, key between k_lo and k_hi
+    {
+        uint32_t a = lower(key, below_lo, below_hi, before_time(t_hi - q.d23, q));
+        uint32_t b = lower(key, below_lo, below_hi, before_time(t_lo + q.d12 + 1, q));
+        if (b > a) acc.template add2<Cell<3, A, B, C>, Cell<4, A, B, C>>(uv_first, (int64_t)(b - a));
+    }
+    // z last: t_z <= min(t_hi + d23, t_lo + d13), key after k_hi
+    if (gap <= q.d12) {
+        int64_t until = t_hi + q.d23 < t_lo + q.d13 ? t_hi + q.d23 : t_lo + q.d13;
+        uint32_t e = lower(key, below_hi, ze, before_time(until + 1, q));
+        acc.template add2<Cell<1, A, B, C>, Cell<2, A, B, C>>(uv_first, (int64_t)(e - below_hi));
+    }
+}
+
+template <bool CELLS, int A, int B>
+__device__ __forceinline__ void light_pairs(const uint64_t *__restrict__ key, const Lists &L,
+                                            const DQuery &q, Acc<CELLS> &acc) {
+    const uint32_t xb = L.lo[A], xe = L.hi[A], yb = L.lo[2 + B], ye = L.hi[2 + B];
+    for (uint32_t ix = xb; ix < xe; ++ix) {
+        const uint64_t kx = key[ix];
+        for (uint32_t iy = yb; iy < ye; ++iy) {
+            const uint64_t ky = key[iy];
+            const bool uv_first = kx < ky;
+            const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
+            const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
+            const int64_t gap = t_hi - t_lo;
+            if (gap > q.d13) continue;   // d12, d23 <= d13: no z completes this pair
+            light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+            light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+        }
+    }
+}
+
+// XCD-aware block order: blocks are dispatched round-robin over the 8 XCDs, so block b runs on
+// XCD b % 8; give each XCD a contiguous range of work so that triangles sharing u (adjacent in
+// the list) share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
+    if (nblk % 8) return b;
+    return (b % 8) * (nblk / 8) + b / 8;
+}
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// reduce the block's 8 per-lane counters into out8 (block slot of the partials)
+template <unsigned BLOCK>
+__device__ __forceinline__ void block_store(const int64_t (&t)[8], int64_t *__restrict__ out8) {
+    __shared__ int64_t s[BLOCK / 64][8];
+    const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int64_t v = wave_sum((long long)t[i]);
+        if (lane == 0) s[wave][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        int64_t v = 0;
+#pragma unroll
+        for (unsigned w = 0; w < BLOCK / 64; ++w) v += s[w][threadIdx.x];
+        out8[threadIdx.x] = v;
+    }
+}
+
+template <bool CELLS, unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_light(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+        const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
+        int64_t *__restrict__ cells) {
+    Acc<CELLS> acc;
+    acc.cells = cells;
+    const uint32_t nblk = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nblk);
+    const uint64_t per = (n_tri + nblk - 1) / nblk;
+    const uint64_t beg = (uint64_t)b * per;
+    const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) {
+        Lists L;
+        load_lists(eoff, tri[3 * i], tri[3 * i + 1], tri[3 * i + 2], key, q, L);
+        light_pairs<CELLS, 0, 0>(key, L, q, acc);
+        light_pairs<CELLS, 0, 1>(key, L, q, acc);
+        light_pairs<CELLS, 1, 0>(key, L, q, acc);
+        light_pairs<CELLS, 1, 1>(key, L, q, acc);
+    }
+    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------------
+// heavy path
+// ---------------------------------------------------------------------------------------------
+// window-clipped bounds of the six lists of every heavy triangle
+__global__ void k_heavy_clip(uint64_t n_heavy, const uint32_t *__restrict__ tri,
+                             const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
+                             DQuery q, uint32_t *__restrict__ clip) {
+    uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n_heavy) return;
+    Lists L;
+    load_lists(eoff, tri[3 * h], tri[3 * h + 1], tri[3 * h + 2], key, q, L);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        clip[12 * h + 2 * i] = L.lo[i];
+        clip[12 * h + 2 * i + 1] = L.hi[i];
+    }
+}
+
+// full (unclipped) start of the six lists, from the DAG edge offsets
+__device__ __forceinline__ void full_lists(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ t3,
+                                           uint32_t (&beg)[7]) {
+    // beg[i], beg[i+1] delimit list i for i = 0..3 (uv+, uv-, uw+, uw-)
+    beg[0] = eoff[2 * t3[0]];
+    beg[1] = eoff[2 * t3[0] + 1];
+    beg[2] = eoff[2 * t3[0] + 2];
+    beg[3] = eoff[2 * t3[1]];
+    beg[4] = eoff[2 * t3[1] + 1];
+    beg[5] = eoff[2 * t3[1] + 2];
+    beg[6] = 0;
+}
+
+// Prefix values per source edge (the cumulative edge counts of Algorithms 1-3), for
+// list X of heavy triangle h, against the two vw lists (c = 0, 1):
+//   E_c = #{z in vw_c : t_z <= t + d13}                  (Algorithm 1, prefix over S1)
+//   A_c = #{z in vw_c : key_z < key}                     (Algorithm 2, prefix over S3)
+//   B_c = #{z in vw_c : t_z < t - d23}                   (Algorithm 2, prefix over S3)
+//   C_c = #{z in vw_c : t_z < t - d13}                   (Algorithm 3, prefix over S3)
+// stored as exclusive prefix sums P_v[r] over the clipped list, r = 0..len.
+constexpr unsigned kPrefixBlock = 256;
+constexpr int kVals = 8;   // E0, E1, A0, A1, B0, B1, C0, C1
+
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v, unsigned lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(v, o, 64);
+        if (lane >= (unsigned)o) v += y;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kPrefixBlock)
+k_heavy_prefix(uint64_t n_heavy, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+               const uint64_t *__restrict__ key, const uint32_t *__restrict__ clip,
+               const uint64_t *__restrict__ hslot, uint64_t n_slots, DQuery q,
+               int64_t *__restrict__ P) {
+    const uint64_t h = blockIdx.x / 4;
+    const int X = blockIdx.x % 4;
+    if (h >= n_heavy) return;
+    const uint32_t *t3 = tri + 3 * h;
+    uint32_t beg[7];
+    full_lists(eoff, t3, beg);
+    // slots of the four source lists follow each other, sized by the unclipped lengths
+    const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
+    uint64_t base = hslot[h];
+    for (int Y = 0; Y < X; ++Y) base += len_full[Y] + 1;
+    const uint32_t lo = clip[12 * h + 2 * X], hi = clip[12 * h + 2 * X + 1];
+    const uint32_t z0 = clip[12 * h + 8], z0e = clip[12 * h + 9];
+    const uint32_t z1 = clip[12 * h + 10], z1e = clip[12 * h + 11];
+    const uint32_t len = hi - lo;
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    __shared__ int64_t s_tot[kPrefixBlock / 64][kVals];
+    int64_t carry[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t c0 = 0; c0 < len; c0 += kPrefixBlock) {
+        const uint32_t r = c0 + threadIdx.x;
+        int64_t v[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r < len) {
+            const uint64_t k = key[lo + r];
+            const int64_t t = (int64_t)(k >> q.shift);
+            v[0] = lower(key, z0, z0e, before_time(t + q.d13 + 1, q)) - z0;
+            v[1] = lower(key, z1, z1e, before_time(t + q.d13 + 1, q)) - z1;
+            v[2] = lower(key, z0, z0e, k) - z0;
+            v[3] = lower(key, z1, z1e, k) - z1;
+            v[4] = lower(key, z0, z0e, before_time(t - q.d23, q)) - z0;
+            v[5] = lower(key, z1, z1e, before_time(t - q.d23, q)) - z1;
+            v[6] = lower(key, z0, z0e, before_time(t - q.d13, q)) - z0;
+            v[7] = lower(key, z1, z1e, before_time(t - q.d13, q)) - z1;
+        }
+        int64_t incl[kVals];
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) incl[i] = wave_incl_scan((long long)v[i], lane);
+        if (lane == 63) {
+#pragma unroll
+            for (int i = 0; i < kVals; ++i) s_tot[wave][i] = incl[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) {
+            int64_t before = carry[i];
+            int64_t total = 0;
+            for (unsigned w = 0; w < kPrefixBlock / 64; ++w) {
+                if (w < wave) before += s_tot[w][i];
+                total += s_tot[w][i];
+            }
+            if (r < len) P[(uint64_t)i * n_slots + base + r] = before + incl[i] - v[i];
+            carry[i] += total;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) P[(uint64_t)i * n_slots + base + len] = carry[i];
+    }
+}
+
+// One source edge e (key k, time t) on list X of heavy triangle h, as e2 of Algorithm 1, e1 of
+// Algorithm 2 and e2 of Algorithm 3, against both directions of the other source pair (b) and of
+// {v,w} (c).
+struct HeavyCtx {
+    const uint64_t *key;
+    const int64_t *P;
+    uint64_t n_slots;
+    uint64_t slot[4];          // first slot of the prefix arrays of lists 0..3
+    uint32_t lo[6], hi[6];     // clipped bounds
+};
+
+template <bool CELLS, int X, int B, int C>
+__device__ __forceinline__ void heavy_cell(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
+                                           Acc<CELLS> &acc, const uint32_t (&o)[8]) {
+    // element's pair: uv for X = 0, 1 and uw for X = 2, 3; direction a = X & 1
+    constexpr bool kUv = X < 2;
+    constexpr int a = X & 1;
+    constexpr int OL = kUv ? 2 + B : B;            // other source list
+    constexpr int DUV = kUv ? a : B, DUW = kUv ? B : a;
+    const uint32_t zb = H.lo[4 + C], ze = H.hi[4 + C];
+    const uint32_t olo = H.lo[OL];
+    // searches into the vw list of direction C
+    const uint64_t *key = H.key;
+    const int64_t r_lt = (int64_t)(lower(key, zb, ze, k) - zb);                          // key < k
+    const int64_t r_d23 = (int64_t)(lower(key, zb, ze, before_time(t + q.d23 + 1, q)) - zb); // t <= t + d23
+    const int64_t r_d12 = (int64_t)(lower(key, zb, ze, before_time(t + q.d12 + 1, q)) - zb); // t <= t + d12
+    const int64_t r_m12 = (int64_t)(lower(key, zb, ze, before_time(t - q.d12, q)) - zb);     // t < t - d12
+    const int64_t *P = H.P;
+    const uint64_t ns = H.n_slots;
+    const uint64_t sb = H.slot[OL] - olo;   // P index of absolute position p in list OL: sb + p
+    const int64_t *PE = P + (uint64_t)(0 + C) * ns + sb;
+    const int64_t *PA = P + (uint64_t)(2 + C) * ns + sb;
+    const int64_t *PB = P + (uint64_t)(4 + C) * ns + sb;
+    const int64_t *PC = P + (uint64_t)(6 + C) * ns + sb;
+    // o[]: searches into the other list (absolute indices), shared by the C = 0, 1 calls
+    const uint32_t o_m12 = o[0], o_lt = o[1], o_mid = o[2], o_p12 = o[3], o_p23 = o[4],
+                   o_p13 = o[5], o_p1312 = o[6];
+    // Algorithm 1 (e = e2 on S2; S1 = other list, S3 = vw_C): pi1 when e is on uw, pi2 on uv
+    if (o_lt > o_m12) {
+        uint32_t lo1 = o_m12, hi1 = o_lt;
+        uint32_t mid = o_mid < lo1 ? lo1 : (o_mid > hi1 ? hi1 : o_mid);
+        int64_t c = (PE[mid] - PE[lo1]) - (int64_t)(mid - lo1) * r_lt +
+                    (int64_t)(hi1 - mid) * (r_d23 - r_lt);
+        if (kUv) acc.template add<Cell<2, DUV, DUW, C>>(c);
+        else acc.template add<Cell<1, DUV, DUW, C>>(c);
+    }
+    // Algorithm 2 (e = e1 on S1; S2 = vw_C, S3 = other list): pi3 when e is on uv, pi4 on uw
+    {
+        const bool d12_first = q.d12 <= q.d23;
+        uint32_t f = o_lt;
+        uint32_t x1 = d12_first ? o_p12 : o_p23;
+        uint32_t x2 = d12_first ? o_p23 : o_p12;
+        x1 = x1 < f ? f : x1;
+        x2 = x2 < x1 ? x1 : x2;
+        uint32_t x3 = o_p13 < x2 ? x2 : o_p13;
+        int64_t c = (PA[x1] - PA[f]) - (int64_t)(x1 - f) * r_lt;
+        if (d12_first) c += (int64_t)(x2 - x1) * (r_d12 - r_lt);
+        else c += (PA[x2] - PA[x1]) - (PB[x2] - PB[x1]);
+        c += (int64_t)(x3 - x2) * r_d12 - (PB[x3] - PB[x2]);
+        if (kUv) acc.template add<Cell<3, DUV, DUW, C>>(c);
+        else acc.template add<Cell<4, DUV, DUW, C>>(c);
+    }
+    // Algorithm 3 (e = e2 on S2; S3 = other list, S1 = vw_C): pi5 when e is on uv, pi6 on uw
+    {
+        uint32_t f = o_lt;
+        uint32_t s = o_p1312 < f ? f : o_p1312;
+        uint32_t e = o_p23 < s ? s : o_p23;
+        int64_t c = (int64_t)(s - f) * (r_lt - r_m12) + (int64_t)(e - s) * r_lt - (PC[e] - PC[s]);
+        if (kUv) acc.template add<Cell<5, DUV, DUW, C>>(c);
+        else acc.template add<Cell<6, DUV, DUW, C>>(c);
+    }
+}
+
+template <bool CELLS, int X, int B>
+__device__ __forceinline__ void heavy_other(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
+                                            Acc<CELLS> &acc) {
+    constexpr int OL = X < 2 ? 2 + B : B;
+    const uint32_t ob = H.lo[OL], oe = H.hi[OL];
+    const uint64_t *key = H.key;
+    uint32_t o[8];
+    o[0] = lower(key, ob, oe, before_time(t - q.d12, q));              // t < t - d12
+    o[1] = lower(key, ob, oe, k);                                     // key < k
+    o[2] = lower(key, ob, oe, before_time(t - q.d13 + q.d23 + 1, q)); // t <= t - d13 + d23
+    o[3] = lower(key, ob, oe, before_time(t + q.d12 + 1, q));         // t <= t + d12
+    o[4] = lower(key, ob, oe, before_time(t + q.d23 + 1, q));         // t <= t + d23
+    o[5] = lower(key, ob, oe, before_time(t + q.d13 + 1, q));         // t <= t + d13
+    o[6] = lower(key, ob, oe, before_time(t + q.d13 - q.d12 + 1, q)); // t <= t + d13 - d12
+    o[7] = 0;
+    heavy_cell<CELLS, X, B, 0>(H, q, k, t, acc, o);
+    heavy_cell<CELLS, X, B, 1>(H, q, k, t, acc, o);
+}
+
+template <bool CELLS, int X>
+__device__ __forceinline__ void heavy_elem(const HeavyCtx &H, const DQuery &q, uint32_t p,
+                                           Acc<CELLS> &acc) {
+    const uint64_t k = H.key[p];
+    const int64_t t = (int64_t)(k >> q.shift);
+    heavy_other<CELLS, X, 0>(H, q, k, t, acc);
+    heavy_other<CELLS, X, 1>(H, q, k, t, acc);
+}
+
+template <bool CELLS, unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_heavy_count(uint64_t n_chunks, const uint32_t *__restrict__ chunks, const uint32_t *__restrict__ tri,
+              const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
+              const uint32_t *__restrict__ clip, const uint64_t *__restrict__ hslot,
+              uint64_t n_slots, const int64_t *__restrict__ P, DQuery q,
+              int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
+    Acc<CELLS> acc;
+    acc.cells = cells;
+    for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        const uint32_t h = chunks[2 * ch], first = chunks[2 * ch + 1];
+        const uint32_t *t3 = tri + 3 * (uint64_t)h;
+        uint32_t beg[7];
+        full_lists(eoff, t3, beg);
+        const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
+        const uint32_t start_full[4] = {beg[0], beg[1], beg[3], beg[4]};
+        HeavyCtx H;
+        H.key = key;
+        H.P = P;
+        H.n_slots = n_slots;
+        uint64_t s = hslot[h];
+#pragma unroll
+        for (int Y = 0; Y < 4; ++Y) {
+            H.slot[Y] = s;
+            s += len_full[Y] + 1;
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            H.lo[i] = clip[12 * (uint64_t)h + 2 * i];
+            H.hi[i] = clip[12 * (uint64_t)h + 2 * i + 1];
+        }
+        uint32_t ei = first + threadIdx.x;
+        const uint32_t total = len_full[0] + len_full[1] + len_full[2] + len_full[3];
+        if (ei < total) {
+            int X = 0;
+            while (ei >= len_full[X]) {
+                ei -= len_full[X];
+                ++X;
+            }
+            const uint32_t p = start_full[X] + ei;
+            if (p >= H.lo[X] && p < H.hi[X]) {
+                switch (X) {
+                    case 0: heavy_elem<CELLS, 0>(H, q, p, acc); break;
+                    case 1: heavy_elem<CELLS, 1>(H, q, p, acc); break;
+                    case 2: heavy_elem<CELLS, 2>(H, q, p, acc); break;
+                    default: heavy_elem<CELLS, 3>(H, q, p, acc); break;
+                }
+            }
+        }
+    }
+    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+}
+
+// final reduction of the per-block partials into out8 (deterministic order)
+__global__ void __launch_bounds__(256)
+k_reduce(uint64_t n_part, const int64_t *__restrict__ partial, int64_t *__restrict__ out8) {
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint64_t i = threadIdx.x; i < n_part; i += 256) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] += partial[8 * i + j];
+    }
+    block_store<256>(t, out8);
+}
+
+__global__ void k_zero(uint64_t n, int64_t *__restrict__ p) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+constexpr unsigned kLightBlock = 256;
+
+}  // namespace
+
+int normalise_query(const dt_graph *g, const dt_query *qq, DQuery *out, bool *empty) {
+    if (!qq) return fail(DT_EINVAL, "null query");
+    if (qq->d13 < 0 || qq->d12 < 0 || qq->d23 < 0)
+        return fail(DT_EINVAL, "deltas must be >= 0 (got %lld, %lld, %lld)", (long long)qq->d13,
+                    (long long)qq->d12, (long long)qq->d23);
+    if (qq->t_lo > qq->t_hi) return fail(DT_EINVAL, "window t_lo > t_hi");
+    DQuery q{};
+    const int64_t span = g->span;
+    auto clampd = [&](int64_t d) { return d > span ? span : d; };
+    int64_t d13 = clampd(qq->d13), d12 = clampd(qq->d12), d23 = clampd(qq->d23);
+    // the same constraint set: t2-t1 <= t3-t1 and t3-t2 <= t3-t1, and t3-t1 = (t3-t2)+(t2-t1)
+    d12 = d12 < d13 ? d12 : d13;
+    d23 = d23 < d13 ? d23 : d13;
+    d13 = d13 < d12 + d23 ? d13 : d12 + d23;
+    q.d13 = d13;
+    q.d12 = d12;
+    q.d23 = d23;
+    q.span = span;
+    q.shift = g->shift;
+    *empty = (g->m == 0);
+    if (qq->t_lo <= g->t_min && qq->t_hi >= g->t_max) {
+        q.windowed = 0;
+        q.klo = 0;
+        q.khi = ~0ull;
+    } else {
+        q.windowed = 1;
+        if (qq->t_hi < g->t_min || qq->t_lo > g->t_max) {
+            *empty = true;
+            q.klo = q.khi = 0;
+        } else {
+            int64_t lo = qq->t_lo < g->t_min ? 0 : qq->t_lo - g->t_min;
+            int64_t hi = qq->t_hi > g->t_max ? span : qq->t_hi - g->t_min;   // inclusive
+            q.klo = (uint64_t)lo << g->shift;
+            q.khi = (uint64_t)(hi + 1) << g->shift;
+        }
+    }
+    *out = q;
+    return DT_OK;
+}
+
+// Enqueue one count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the 48
+// cells into cells_dev (zeroed here) instead.
+int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
+                  int64_t *cells_dev) {
+    dt_ctx *ctx = g->ctx;
+    Schedule &S = g->sched;
+    const unsigned light_grid = S.n_light ? (unsigned)std::min<uint64_t>(
+        (S.n_light + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
+    const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
+    const unsigned hg = S.n_chunks ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
+    const uint64_t n_part = (uint64_t)lg + hg;
+    DT_TRY(ensure(ctx, ctx->partials, (n_part + 1) * 8 * sizeof(int64_t)));
+    int64_t *part = ctx->partials.as<int64_t>();
+    if (cells) {
+        k_zero<<<1, 64, 0, s>>>(48, cells_dev);
+        DT_HIP(hipGetLastError());
+    }
+    if (lg) {
+        if (cells)
+            k_light<true, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
+                g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
+        else
+            k_light<false, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
+                g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
+        DT_HIP(hipGetLastError());
+    }
+    if (S.n_heavy) {
+        DT_TRY(ensure(ctx, ctx->heavy_vals, S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256));
+        int64_t *P = ctx->heavy_vals.as<int64_t>();
+        uint32_t *clip = reinterpret_cast<uint32_t *>(P + S.n_slots * kVals);
+        k_heavy_clip<<<grid_for(S.n_heavy, 256), 256, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
+            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, clip);
+        DT_HIP(hipGetLastError());
+        k_heavy_prefix<<<(unsigned)(4 * S.n_heavy), kPrefixBlock, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
+            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip, S.hslot.as<uint64_t>(), S.n_slots, q, P);
+        DT_HIP(hipGetLastError());
+        const unsigned cb = g->tuning.heavy_chunk;
+        if (cells) {
+            if (cb == 256)
+                k_heavy_count<true, 256><<<hg, 256, 0, s>>>(S.n_chunks, S.chunks.as<uint32_t>(),
+                    S.heavy.as<uint32_t>(), g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip,
+                    S.hslot.as<uint64_t>(), S.n_slots, P, q, part + 8 * (uint64_t)lg, cells_dev);
+            else
+                return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
+        } else {
+            if (cb == 256)
+                k_heavy_count<false, 256><<<hg, 256, 0, s>>>(S.n_chunks, S.chunks.as<uint32_t>(),
+                    S.heavy.as<uint32_t>(), g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip,
+                    S.hslot.as<uint64_t>(), S.n_slots, P, q, part + 8 * (uint64_t)lg, nullptr);
+            else
+                return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
+        }
+        DT_HIP(hipGetLastError());
+    }
+    if (!cells) {
+        k_reduce<<<1, 256, 0, s>>>(n_part, part, out8_dev);
+        DT_HIP(hipGetLastError());
+    }
+    return DT_OK;
+}
+
+}  // namespace dt

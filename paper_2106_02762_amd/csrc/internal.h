@@ -1,0 +1,171 @@
+// Internal declarations of the MI355X temporal-triangle library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <cstdio>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dottt.h"
+
+namespace dt {
+
+// ------------------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------------------
+int fail(int code, const char *fmt, ...);   // records the thread's message, returns code
+void clear_error();
+
+#define DT_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::dt::fail(DT_EDEVICE, "%s failed: %s (%s:%d)", #expr,                 \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+#define DT_TRY(expr)                  \
+    do {                              \
+        int rc_ = (expr);             \
+        if (rc_ != DT_OK) return rc_; \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------------
+// context and device memory with a budget
+// ------------------------------------------------------------------------------------------------
+// A device allocation owned by a context; released by reset() or the destructor.
+struct DevMem {
+    dt_ctx *ctx = nullptr;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    DevMem(DevMem &&o) noexcept { *this = std::move(o); }
+    DevMem &operator=(DevMem &&o) noexcept;
+    ~DevMem() { reset(); }
+    void reset();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace dt
+
+struct dt_ctx {
+    int device = 0;
+    uint64_t budget = 0;                 // 0 = no cap
+    std::atomic<uint64_t> used{0};
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    // scratch reused by counts issued on the context's stream
+    dt::DevMem partials, out8, heavy_vals;
+    int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
+};
+
+namespace dt {
+
+int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes);   // DT_ENOMEM on budget or HIP failure
+int ensure(dt_ctx *ctx, DevMem &m, size_t bytes);      // grow-only
+
+// ------------------------------------------------------------------------------------------------
+// query as the kernels see it: deltas rewritten and clamped, window in key space
+// ------------------------------------------------------------------------------------------------
+struct DQuery {
+    int64_t d13, d12, d23;   // 0 <= d12, d23 <= d13 <= d12 + d23 <= 2 * span
+    uint64_t klo, khi;       // window as keys: kept iff klo <= key < khi
+    int64_t span;            // t_max - t_min (relative times lie in [0, span])
+    int shift;               // key = (t - t_min) << shift | input index
+    int windowed;            // 0: klo = 0, khi = ~0
+};
+
+// ------------------------------------------------------------------------------------------------
+// build products of one graph (all device arrays unless noted)
+// ------------------------------------------------------------------------------------------------
+struct Schedule {
+    uint64_t n_light = 0, n_heavy = 0;
+    DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
+    DevMem heavy;       // uint32[3 * n_heavy]
+    DevMem hslot;       // uint64[n_heavy + 1]: first scratch slot of each heavy triangle
+    uint64_t n_slots = 0;
+    DevMem chunks;      // uint32[2 * n_chunks]: (heavy triangle, first element) per work item
+    uint64_t n_chunks = 0;
+    DevMem lists;       // uint32[4 * n_heavy]: heavy triangle, list id pairs for the prefix pass
+};
+
+}  // namespace dt
+
+struct dt_graph {
+    dt_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m_in = 0, m = 0, self_loops = 0, m_s = 0;
+    int64_t t_min = 0, t_max = 0, span = 0;
+    int shift = 0;
+    uint32_t max_mult = 0;
+    // load products
+    dt::DevMem sx, sy;          // uint32[m_s]: pair endpoints x < y
+    dt::DevMem row;             // uint32[n + 1]: undirected CSR of G
+    dt::DevMem col, ceid;       // uint32[2 m_s]: neighbour, pair id
+    dt::DevMem psid;            // uint32[m]: pair of each temporal edge (pair-major, key order)
+    dt::DevMem pdir;            // uint8[m]: 0 if the edge goes x -> y
+    dt::DevMem pkey;            // uint64[m]: key of each temporal edge (same order)
+    // build products
+    bool built = false;
+    uint32_t kappa = 0, max_outdeg = 0, peel_rounds = 0;
+    dt::DevMem core, rank, order;  // uint32[n]: core number, position in the ordering, vertex at position
+    dt::DevMem dag_row;         // uint32[n + 1]: out-CSR of G_prec in rank space
+    dt::DevMem dag_col;         // uint32[m_s]: head rank of each DAG edge
+    dt::DevMem eoff;            // uint32[2 m_s + 1]: DAG edge d: tail->head edges [eoff[2d], eoff[2d+1]),
+                                //                    head->tail edges [eoff[2d+1], eoff[2d+2])
+    dt::DevMem key;             // uint64[m]: keys in that layout
+    uint64_t n_tri = 0;
+    unsigned __int128 sum_sigma3 = 0;
+    uint64_t alg_bytes = 0;
+    dt::Schedule sched;
+    dt_tuning tuning{64, 256, 256, 0};
+    double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
+};
+
+namespace dt {
+
+// build phases (each returns a DT_* code)
+int load_graph(dt_graph *g, const uint32_t *src_dev, const uint32_t *dst_dev, const int64_t *t_dev);
+int peel(dt_graph *g);
+int orient(dt_graph *g);
+int enumerate_triangles(dt_graph *g, DevMem &tri);
+int make_schedule(dt_graph *g, DevMem &tri);
+
+// counting
+int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *empty);
+int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
+                  int64_t *cells_dev);
+int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
+                int64_t (*out)[8]);
+
+// library primitives (rocPRIM), out of place, enqueued on stream s; temporary storage is taken
+// from the context's budget and released before returning
+int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
+                       uint32_t *vout, size_t n, int end_bit, hipStream_t s);
+int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
+                       uint64_t *vout, size_t n, int end_bit, hipStream_t s);
+int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
+int exclusive_scan_u64(dt_ctx *ctx, const uint64_t *in, uint64_t *out, size_t n, hipStream_t s);
+
+// timing helper
+double now_ms();
+
+inline unsigned grid_for(uint64_t n, unsigned block) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    if (g > 0x7fffffffull) g = 0x7fffffffull;
+    return (unsigned)g;
+}
+
+}  // namespace dt
