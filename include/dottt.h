@@ -76,20 +76,30 @@ typedef struct {
     uint64_t sum_sigma3_lo, sum_sigma3_hi; /* sum over static triangles of the product of the
                                               three pair multiplicities, 128-bit                  */
     uint64_t n_light_triangles, n_heavy_triangles; /* split chosen by the scheduler               */
-    uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count (see DESIGN)     */
+    uint64_t n_medium_triangles;
+    uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count: per triangle
+                                      12 + 36 + 8 (s_uv + s_uw) + 8 min(s_vw, 2 ceil(log2(s_vw+1)))  */
+    uint64_t alg_bytes_light;      /* the part of alg_bytes on light triangles                    */
+    uint64_t alg_bytes_medium;     /* the part of alg_bytes on medium triangles                   */
+    uint64_t alg_bytes_peel;       /* 16 n + 16 m_static: CSR and state read once, one update per pair */
+    uint64_t alg_bytes_triangles;  /* 4 (m_static + candidates) + 12 per triangle written         */
+    uint64_t tri_candidates;       /* (v, w) candidates tested: sum over v of d-(v) d+(v)          */
+    uint64_t heavy_slots;          /* prefix-array slots of the heavy path                        */
     double   ms_load, ms_peel, ms_orient, ms_triangles, ms_schedule; /* phase wall times          */
 } dt_stats;
 
 /* Tuning of the count scheduler.  A static triangle whose two source-incident pairs carry
- * sigma_uv * sigma_uw <= light_pair_cap temporal-edge pairs is counted by one lane enumerating
- * those pairs (the pairwise form of Lemma 1); larger ones go to the prefix-count path of
+ * P = sigma_uv * sigma_uw temporal-edge pairs is counted by one lane enumerating those pairs (the
+ * pairwise form of Lemma 1) when P <= light_pair_cap, by one wavefront with the pairs spread over
+ * its lanes when P <= medium_pair_cap, and otherwise by the prefix-count procedures of
  * Algorithms 1-3 split into chunks of `heavy_chunk` source edges.  Zero fields keep the default. */
 typedef struct {
     uint32_t light_pair_cap;       /* default 64                                                  */
-    uint32_t heavy_chunk;          /* default 256, a multiple of 64, at most 1024                 */
-    uint32_t light_block;          /* threads per block of the light kernel, default 256          */
-    uint32_t force_path;           /* 0: split by light_pair_cap; 1: every triangle light;
-                                      2: every triangle heavy (diagnostics and tests)             */
+    uint32_t heavy_chunk;          /* default 256 (the only compiled value)                       */
+    uint32_t medium_pair_cap;      /* default 65536                                               */
+    uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;
+                                      2: every triangle heavy; 3: every triangle medium
+                                      (diagnostics and tests)                                     */
 } dt_tuning;
 
 const char *dt_strerror(int code);
@@ -149,6 +159,16 @@ int dt_graph_order(const dt_graph *g, uint32_t *core, uint32_t *rank);
 int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t *count);
 
 int dt_graph_free(dt_graph *g);
+
+/* Diagnostics: when profiling is on, the library records HIP events on the stream each kernel is
+ * launched on, around the main kernels of the last build and the last count of the context:
+ *   ms[0] core peel, ms[1] store re-layout, ms[2] triangle count pass, ms[3] triangle fill pass,
+ *   ms[4] light count, ms[5] heavy prefix pass, ms[6] heavy count pass, ms[7] final reduction,
+ *   ms[8] medium count.
+ * dt_ctx_last_profile waits for those events and reports their elapsed times (0 if not run). */
+#define DT_PROFILE_SLOTS 9
+int dt_ctx_set_profiling(dt_ctx *ctx, int enable);
+int dt_ctx_last_profile(dt_ctx *ctx, float ms[DT_PROFILE_SLOTS]);
 
 /* Serving: a request loop that keeps graphs resident in HBM and batches count queries of
  * differing deltas and windows into running device work (continuous batching). */

@@ -61,6 +61,7 @@ int load_common(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const 
     if (m && (!src || !dst || !t)) return fail(DT_EINVAL, "null edge array");
     if (m >= (1ull << 31)) return fail(DT_EOVERFLOW, "m = %llu edges; this version takes m < 2^31",
                                        (unsigned long long)m);
+    if (n >= (1u << 31)) return fail(DT_EOVERFLOW, "n = %u vertices; this version takes n < 2^31", n);
     DeviceGuard dg(ctx->device);
     double t0 = now_ms();
     dt_graph *g = new dt_graph();
@@ -160,6 +161,8 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     ctx->out8.reset();
     ctx->heavy_vals.reset();
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
+    for (auto &e : ctx->prof_ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipEventDestroy(ctx->ev_a);
     (void)hipEventDestroy(ctx->ev_b);
     (void)hipStreamDestroy(ctx->stream);
@@ -217,11 +220,11 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     dt_tuning nt = g->tuning;
     if (tu->light_pair_cap) nt.light_pair_cap = tu->light_pair_cap;
     if (tu->heavy_chunk) nt.heavy_chunk = tu->heavy_chunk;
-    if (tu->light_block) nt.light_block = tu->light_block;
-    if (tu->force_path > 2) return fail(DT_EINVAL, "force_path must be 0, 1 or 2");
+    if (tu->medium_pair_cap) nt.medium_pair_cap = tu->medium_pair_cap;
+    if (tu->force_path > 3) return fail(DT_EINVAL, "force_path must be 0, 1, 2 or 3");
     nt.force_path = tu->force_path;
     if (nt.heavy_chunk != 256) return fail(DT_EINVAL, "heavy_chunk must be 256 in this version");
-    if (nt.light_block != 256) return fail(DT_EINVAL, "light_block must be 256 in this version");
+    if (nt.medium_pair_cap > (1u << 30)) return fail(DT_EINVAL, "medium_pair_cap must be at most 2^30");
     g->tuning = nt;
     if (!g->built) return DT_OK;
     // re-split the resident triangles under the new tuning
@@ -230,8 +233,11 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     DevMem tri;
     DT_TRY(dev_alloc(g->ctx, tri, g->n_tri * 12));
     if (S.n_light) DT_HIP(hipMemcpy(tri.ptr, S.light.ptr, S.n_light * 12, hipMemcpyDeviceToDevice));
+    if (S.n_medium)
+        DT_HIP(hipMemcpy(tri.as<uint8_t>() + S.n_light * 12, S.medium.ptr, S.n_medium * 12, hipMemcpyDeviceToDevice));
     if (S.n_heavy)
-        DT_HIP(hipMemcpy(tri.as<uint8_t>() + S.n_light * 12, S.heavy.ptr, S.n_heavy * 12, hipMemcpyDeviceToDevice));
+        DT_HIP(hipMemcpy(tri.as<uint8_t>() + (S.n_light + S.n_medium) * 12, S.heavy.ptr, S.n_heavy * 12,
+                         hipMemcpyDeviceToDevice));
     return make_schedule(g, tri);
 }
 
@@ -258,7 +264,14 @@ int dt_graph_stats(const dt_graph *g, dt_stats *out) {
         out->sum_sigma3_hi = (uint64_t)(g->sum_sigma3 >> 64);
         out->n_light_triangles = g->sched.n_light;
         out->n_heavy_triangles = g->sched.n_heavy;
+        out->n_medium_triangles = g->sched.n_medium;
         out->alg_bytes = g->alg_bytes;
+        out->alg_bytes_light = g->alg_bytes_light;
+        out->alg_bytes_medium = g->alg_bytes_medium;
+        out->alg_bytes_peel = g->alg_bytes_peel;
+        out->alg_bytes_triangles = g->alg_bytes_tri;
+        out->tri_candidates = g->tri_candidates;
+        out->heavy_slots = g->sched.n_slots;
         out->ms_peel = g->ms_peel;
         out->ms_orient = g->ms_orient;
         out->ms_triangles = g->ms_tri;
@@ -350,6 +363,30 @@ int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_qu
     return count_batch(ctx, k, graphs, queries, out);
 }
 
+int dt_ctx_set_profiling(dt_ctx *ctx, int enable) {
+    clear_error();
+    if (!ctx) return fail(DT_EINVAL, "null context");
+    DeviceGuard dg(ctx->device);
+    if (enable && !ctx->prof_ev[0])
+        for (auto &e : ctx->prof_ev) DT_HIP(hipEventCreate(&e));
+    ctx->prof = enable != 0;
+    for (auto &u : ctx->prof_used) u = false;
+    return DT_OK;
+}
+
+int dt_ctx_last_profile(dt_ctx *ctx, float ms[DT_PROFILE_SLOTS]) {
+    clear_error();
+    if (!ctx || !ms) return fail(DT_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
+    for (int i = 0; i < DT_PROFILE_SLOTS; ++i) {
+        ms[i] = 0.f;
+        if (!ctx->prof_used[i]) continue;
+        DT_HIP(hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+        DT_HIP(hipEventElapsedTime(&ms[i], ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+    }
+    return DT_OK;
+}
+
 int dt_graph_order(const dt_graph *g, uint32_t *core, uint32_t *rank) {
     clear_error();
     DT_TRY(check_graph(g, true));
@@ -373,10 +410,14 @@ int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t 
     if (S.n_light)
         k_tri_vertices<<<grid_for(S.n_light, kBlock), kBlock, 0, st>>>(S.n_light, S.light.as<uint32_t>(), g->n,
             g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(), buf.as<uint32_t>());
+    if (S.n_medium)
+        k_tri_vertices<<<grid_for(S.n_medium, kBlock), kBlock, 0, st>>>(S.n_medium, S.medium.as<uint32_t>(), g->n,
+            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(),
+            buf.as<uint32_t>() + 3 * S.n_light);
     if (S.n_heavy)
         k_tri_vertices<<<grid_for(S.n_heavy, kBlock), kBlock, 0, st>>>(S.n_heavy, S.heavy.as<uint32_t>(), g->n,
             g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(),
-            buf.as<uint32_t>() + 3 * S.n_light);
+            buf.as<uint32_t>() + 3 * (S.n_light + S.n_medium));
     DT_HIP(hipGetLastError());
     uint64_t k = cap < g->n_tri ? cap : g->n_tri;
     DT_HIP(hipMemcpyAsync(out, buf.ptr, k * 12, hipMemcpyDeviceToHost, st));

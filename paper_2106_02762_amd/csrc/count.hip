@@ -239,6 +239,54 @@ k_light(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__rest
 }
 
 // ---------------------------------------------------------------------------------------------
+// medium path: one wavefront per triangle, the (uv edge, uw edge) pairs spread over the lanes
+// ---------------------------------------------------------------------------------------------
+template <bool CELLS, int A, int B>
+__device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, const Lists &L,
+                                            const DQuery &q, uint32_t ix, uint32_t iy, Acc<CELLS> &acc) {
+    const uint64_t kx = key[ix], ky = key[iy];
+    const bool uv_first = kx < ky;
+    const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
+    const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
+    const int64_t gap = t_hi - t_lo;
+    if (gap > q.d13) return;
+    light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+    light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+}
+
+// triangles sorted by pair count, largest first; wave w takes w, w + W, w + 2W, ...
+template <bool CELLS, unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_medium(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+         const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
+         int64_t *__restrict__ cells) {
+    Acc<CELLS> acc;
+    acc.cells = cells;
+    const unsigned lane = threadIdx.x & 63;
+    const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
+    for (uint64_t i = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; i < n_tri; i += W) {
+        Lists L;
+        load_lists(eoff, tri[3 * i], tri[3 * i + 1], tri[3 * i + 2], key, q, L);
+        const uint32_t su0 = L.hi[0] - L.lo[0], su = su0 + (L.hi[1] - L.lo[1]);
+        const uint32_t sw0 = L.hi[2] - L.lo[2], sw = sw0 + (L.hi[3] - L.lo[3]);
+        const uint32_t np = su * sw;   // at most the medium cap
+        for (uint32_t p = lane; p < np; p += 64) {
+            const uint32_t a = p / sw, b = p - a * sw;
+            const int A = a < su0 ? 0 : 1, B = b < sw0 ? 0 : 1;
+            const uint32_t ix = A ? L.lo[1] + (a - su0) : L.lo[0] + a;
+            const uint32_t iy = B ? L.lo[3] + (b - sw0) : L.lo[2] + b;
+            switch (A * 2 + B) {
+                case 0: medium_pair<CELLS, 0, 0>(key, L, q, ix, iy, acc); break;
+                case 1: medium_pair<CELLS, 0, 1>(key, L, q, ix, iy, acc); break;
+                case 2: medium_pair<CELLS, 1, 0>(key, L, q, ix, iy, acc); break;
+                default: medium_pair<CELLS, 1, 1>(key, L, q, ix, iy, acc); break;
+            }
+        }
+    }
+    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------------
 // heavy path
 // ---------------------------------------------------------------------------------------------
 // window-clipped bounds of the six lists of every heavy triangle
@@ -576,7 +624,8 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         (S.n_light + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
     const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
     const unsigned hg = S.n_chunks ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    const uint64_t n_part = (uint64_t)lg + hg;
+    const unsigned mg = S.n_medium ? (unsigned)std::min<uint64_t>((S.n_medium + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
+    const uint64_t n_part = (uint64_t)lg + hg + mg;
     DT_TRY(ensure(ctx, ctx->partials, (n_part + 1) * 8 * sizeof(int64_t)));
     int64_t *part = ctx->partials.as<int64_t>();
     if (cells) {
@@ -584,12 +633,25 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         DT_HIP(hipGetLastError());
     }
     if (lg) {
+        prof_begin(ctx, kProfLight, s);
         if (cells)
             k_light<true, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
         else
             k_light<false, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
+        prof_end(ctx, kProfLight, s);
+        DT_HIP(hipGetLastError());
+    }
+    if (mg) {
+        prof_begin(ctx, kProfMedium, s);
+        if (cells)
+            k_medium<true, 256><<<mg, 256, 0, s>>>(S.n_medium, S.medium.as<uint32_t>(), g->eoff.as<uint32_t>(),
+                g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
+        else
+            k_medium<false, 256><<<mg, 256, 0, s>>>(S.n_medium, S.medium.as<uint32_t>(), g->eoff.as<uint32_t>(),
+                g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
+        prof_end(ctx, kProfMedium, s);
         DT_HIP(hipGetLastError());
     }
     if (S.n_heavy) {
@@ -599,10 +661,13 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         k_heavy_clip<<<grid_for(S.n_heavy, 256), 256, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, clip);
         DT_HIP(hipGetLastError());
+        prof_begin(ctx, kProfHeavyPrefix, s);
         k_heavy_prefix<<<(unsigned)(4 * S.n_heavy), kPrefixBlock, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip, S.hslot.as<uint64_t>(), S.n_slots, q, P);
+        prof_end(ctx, kProfHeavyPrefix, s);
         DT_HIP(hipGetLastError());
         const unsigned cb = g->tuning.heavy_chunk;
+        prof_begin(ctx, kProfHeavyCount, s);
         if (cells) {
             if (cb == 256)
                 k_heavy_count<true, 256><<<hg, 256, 0, s>>>(S.n_chunks, S.chunks.as<uint32_t>(),
@@ -618,10 +683,13 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
             else
                 return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
         }
+        prof_end(ctx, kProfHeavyCount, s);
         DT_HIP(hipGetLastError());
     }
     if (!cells) {
+        prof_begin(ctx, kProfReduce, s);
         k_reduce<<<1, 256, 0, s>>>(n_part, part, out8_dev);
+        prof_end(ctx, kProfReduce, s);
         DT_HIP(hipGetLastError());
     }
     return DT_OK;

@@ -68,11 +68,25 @@ struct dt_ctx {
     dt::DevMem partials, out8, heavy_vals;
     int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
+    // optional per-kernel timing (dt_ctx_set_profiling)
+    bool prof = false;
+    hipEvent_t prof_ev[2 * DT_PROFILE_SLOTS] = {};
+    bool prof_used[DT_PROFILE_SLOTS] = {};
 };
 
 namespace dt {
 
 int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes);   // DT_ENOMEM on budget or HIP failure
+
+// profiling marks around one kernel launch (no-ops unless profiling is on)
+enum ProfSlot { kProfPeel = 0, kProfRelayout, kProfTriCount, kProfTriFill, kProfLight,
+                kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium };
+inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
+    if (c->prof) { (void)hipEventRecord(c->prof_ev[2 * slot], s); c->prof_used[slot] = true; }
+}
+inline void prof_end(dt_ctx *c, int slot, hipStream_t s) {
+    if (c->prof) (void)hipEventRecord(c->prof_ev[2 * slot + 1], s);
+}
 int ensure(dt_ctx *ctx, DevMem &m, size_t bytes);      // grow-only
 
 // ------------------------------------------------------------------------------------------------
@@ -90,8 +104,9 @@ struct DQuery {
 // build products of one graph (all device arrays unless noted)
 // ------------------------------------------------------------------------------------------------
 struct Schedule {
-    uint64_t n_light = 0, n_heavy = 0;
+    uint64_t n_light = 0, n_medium = 0, n_heavy = 0;
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
+    DevMem medium;      // uint32[3 * n_medium], largest pair count first
     DevMem heavy;       // uint32[3 * n_heavy]
     DevMem hslot;       // uint64[n_heavy + 1]: first scratch slot of each heavy triangle
     uint64_t n_slots = 0;
@@ -116,6 +131,8 @@ struct dt_graph {
     dt::DevMem psid;            // uint32[m]: pair of each temporal edge (pair-major, key order)
     dt::DevMem pdir;            // uint8[m]: 0 if the edge goes x -> y
     dt::DevMem pkey;            // uint64[m]: key of each temporal edge (same order)
+    dt::DevMem pstart;          // uint32[m_s + 1]: first edge of each pair in that order
+    dt::DevMem c1;              // uint32[m + 1]: edges with pdir = 1 before each position
     // build products
     bool built = false;
     uint32_t kappa = 0, max_outdeg = 0, peel_rounds = 0;
@@ -127,9 +144,10 @@ struct dt_graph {
     dt::DevMem key;             // uint64[m]: keys in that layout
     uint64_t n_tri = 0;
     unsigned __int128 sum_sigma3 = 0;
-    uint64_t alg_bytes = 0;
+    uint64_t alg_bytes = 0, alg_bytes_light = 0, alg_bytes_medium = 0, alg_bytes_peel = 0, alg_bytes_tri = 0;
+    uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{64, 256, 256, 0};
+    dt_tuning tuning{64, 256, 65536, 0};
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 

@@ -106,6 +106,11 @@ __global__ void k_fill_pairs(uint64_t m, const uint64_t *__restrict__ pk, const 
     pdir[k] = src[i] > dst[i] ? 1 : 0;
 }
 
+__global__ void k_dir_flags(uint64_t m, const uint8_t *__restrict__ pdir, uint32_t *__restrict__ f) {
+    uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < m) f[k] = pdir[k];
+}
+
 __global__ void k_max_mult(uint64_t ms, uint64_t m, const uint32_t *__restrict__ pstart,
                            unsigned int *__restrict__ out) {
     __shared__ unsigned s_max[kBlock];
@@ -225,7 +230,7 @@ int load_graph(dt_graph *g, const uint32_t *src, const uint32_t *dst, const int6
     jv.reset();
 
     // 4. pair ids, endpoints, per-edge key and direction
-    DevMem head, excl, pstart;
+    DevMem head, excl;
     DT_TRY(dev_alloc(ctx, head, m * 4));
     DT_TRY(dev_alloc(ctx, excl, m * 4));
     uint64_t ms = 0;
@@ -242,7 +247,7 @@ int load_graph(dt_graph *g, const uint32_t *src, const uint32_t *dst, const int6
     g->m_s = ms;
     DT_TRY(dev_alloc(ctx, g->sx, ms * 4));
     DT_TRY(dev_alloc(ctx, g->sy, ms * 4));
-    DT_TRY(dev_alloc(ctx, pstart, ms * 4));
+    DT_TRY(dev_alloc(ctx, g->pstart, (ms + 1) * 4));
     DT_TRY(dev_alloc(ctx, g->psid, m * 4));
     DT_TRY(dev_alloc(ctx, g->pkey, m * 8));
     DT_TRY(dev_alloc(ctx, g->pdir, m));
@@ -252,17 +257,32 @@ int load_graph(dt_graph *g, const uint32_t *src, const uint32_t *dst, const int6
             m, pk2.as<uint64_t>(), jv2.as<uint32_t>(), head.as<uint32_t>(), excl.as<uint32_t>(),
             tk2.as<uint64_t>(), tidx2.as<uint32_t>(), src, dst, g->psid.as<uint32_t>(),
             g->pkey.as<uint64_t>(), g->pdir.as<uint8_t>(), g->sx.as<uint32_t>(), g->sy.as<uint32_t>(),
-            pstart.as<uint32_t>());
+            g->pstart.as<uint32_t>());
         DT_HIP(hipGetLastError());
+        uint32_t mm = (uint32_t)m;
+        DT_HIP(hipMemcpyAsync(g->pstart.as<uint32_t>() + ms, &mm, 4, hipMemcpyHostToDevice, st));
         DT_HIP(hipMemsetAsync(scal.ptr, 0, 4, st));
         unsigned grid = grid_for(ms, kBlock);
         if (grid > 4096) grid = 4096;
-        k_max_mult<<<grid, kBlock, 0, st>>>(ms, m, pstart.as<uint32_t>(), scal.as<unsigned>());
+        k_max_mult<<<grid, kBlock, 0, st>>>(ms, m, g->pstart.as<uint32_t>(), scal.as<unsigned>());
         DT_HIP(hipGetLastError());
         DT_HIP(hipMemcpyAsync(&g->max_mult, scal.ptr, 4, hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
     }
-    pk2.reset(); jv2.reset(); head.reset(); excl.reset(); tk2.reset(); tidx2.reset(); pstart.reset();
+    pk2.reset(); jv2.reset(); head.reset(); excl.reset(); tk2.reset(); tidx2.reset();
+
+    // count of head -> tail edges (pdir = 1) before every position, for the re-layout by direction
+    {
+        DevMem flag;
+        DT_TRY(dev_alloc(ctx, flag, (m + 1) * 4));
+        DT_TRY(dev_alloc(ctx, g->c1, (m + 1) * 4));
+        DT_HIP(hipMemsetAsync(flag.ptr, 0, (m + 1) * 4, st));
+        if (m) {
+            k_dir_flags<<<grid_for(m, kBlock), kBlock, 0, st>>>(m, g->pdir.as<uint8_t>(), flag.as<uint32_t>());
+            DT_HIP(hipGetLastError());
+        }
+        DT_TRY(exclusive_scan_u32(ctx, flag.as<uint32_t>(), g->c1.as<uint32_t>(), m + 1, st));
+    }
 
     // 5. undirected CSR of G with pair ids, neighbours sorted by id
     DevMem ak, av, ak2, deg;

@@ -33,7 +33,10 @@ ENTRY_POINTS = (
     "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_cells", "dt_count_batch",
     "dt_graph_order", "dt_graph_triangles", "dt_graph_free", "dt_server_start",
     "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stop",
+    "dt_ctx_set_profiling", "dt_ctx_last_profile",
 )
+PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
+                 "heavy_count", "reduce", "medium")
 
 
 class DtError(RuntimeError):
@@ -56,7 +59,12 @@ class dt_stats(ctypes.Structure):
         ("max_out_degree", ctypes.c_uint32), ("peel_rounds", ctypes.c_uint32),
         ("sum_sigma3_lo", ctypes.c_uint64), ("sum_sigma3_hi", ctypes.c_uint64),
         ("n_light_triangles", ctypes.c_uint64), ("n_heavy_triangles", ctypes.c_uint64),
-        ("alg_bytes", ctypes.c_uint64), ("ms_load", ctypes.c_double), ("ms_peel", ctypes.c_double),
+        ("n_medium_triangles", ctypes.c_uint64),
+        ("alg_bytes", ctypes.c_uint64), ("alg_bytes_light", ctypes.c_uint64),
+        ("alg_bytes_medium", ctypes.c_uint64),
+        ("alg_bytes_peel", ctypes.c_uint64), ("alg_bytes_triangles", ctypes.c_uint64),
+        ("tri_candidates", ctypes.c_uint64), ("heavy_slots", ctypes.c_uint64),
+        ("ms_load", ctypes.c_double), ("ms_peel", ctypes.c_double),
         ("ms_orient", ctypes.c_double), ("ms_triangles", ctypes.c_double),
         ("ms_schedule", ctypes.c_double),
     ]
@@ -64,7 +72,7 @@ class dt_stats(ctypes.Structure):
 
 class dt_tuning(ctypes.Structure):
     _fields_ = [("light_pair_cap", ctypes.c_uint32), ("heavy_chunk", ctypes.c_uint32),
-                ("light_block", ctypes.c_uint32), ("force_path", ctypes.c_uint32)]
+                ("medium_pair_cap", ctypes.c_uint32), ("force_path", ctypes.c_uint32)]
 
 
 class dt_server_cfg(ctypes.Structure):
@@ -108,6 +116,8 @@ def library():
         "dt_server_submit": (I, [P, U32, ctypes.POINTER(dt_query), ctypes.POINTER(U64)]),
         "dt_server_wait": (I, [P, U64, P, I64]),
         "dt_server_stop": (I, [P]),
+        "dt_ctx_set_profiling": (I, [P, I]),
+        "dt_ctx_last_profile": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -193,9 +203,9 @@ def dt_graph_build(g):
     _check(library().dt_graph_build(g), "dt_graph_build")
 
 
-def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, light_block=0, force_path=0):
-    """force_path: 0 split by light_pair_cap, 1 all light, 2 all heavy."""
-    tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(light_block), int(force_path))
+def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0):
+    """force_path: 0 split by the caps, 1 all light, 2 all heavy, 3 all medium."""
+    tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path))
     _check(library().dt_graph_set_tuning(g, ctypes.byref(tu)), "dt_graph_set_tuning")
 
 
@@ -255,6 +265,17 @@ def dt_graph_triangles(g):
 
 def dt_graph_free(g):
     _check(library().dt_graph_free(g), "dt_graph_free")
+
+
+def dt_ctx_set_profiling(ctx, enable=True):
+    _check(library().dt_ctx_set_profiling(ctx, 1 if enable else 0), "dt_ctx_set_profiling")
+
+
+def dt_ctx_last_profile(ctx):
+    """{slot: ms} of the event-timed kernels of the last build and count (0 if not run)."""
+    ms = np.zeros(len(PROFILE_SLOTS), dtype=np.float32)
+    _check(library().dt_ctx_last_profile(ctx, ms.ctypes.data), "dt_ctx_last_profile")
+    return {k: float(v) for k, v in zip(PROFILE_SLOTS, ms)}
 
 
 def dt_server_start(ctx, hbm_budget_bytes=0, max_inflight_queries=0, max_batch=0, deadline_ns=0):

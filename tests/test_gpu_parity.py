@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2106_02762_amd as dt  # noqa: E402
 
-CAPS = [0, 1, 2]   # split by the default cap, all light, all heavy
+CAPS = [0, 1, 2, 3]   # split by the default caps, all light, all heavy, all medium
 
 
 @pytest.fixture(scope="module")
