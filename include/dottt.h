@@ -90,13 +90,13 @@ typedef struct {
 
 /* Tuning of the count scheduler.  A static triangle whose two source-incident pairs carry
  * P = sigma_uv * sigma_uw temporal-edge pairs is counted by one lane enumerating those pairs (the
- * pairwise form of Lemma 1) when P <= light_pair_cap, by one wavefront with the pairs spread over
- * its lanes when P <= medium_pair_cap, and otherwise by the prefix-count procedures of
+ * pairwise form of Lemma 1) when P <= light_pair_cap, by wavefronts taking the pairs in chunks of
+ * 4096 spread over their lanes when P <= medium_pair_cap, and otherwise by the prefix-count procedures of
  * Algorithms 1-3 split into chunks of `heavy_chunk` source edges.  Zero fields keep the default. */
 typedef struct {
     uint32_t light_pair_cap;       /* default 64                                                  */
     uint32_t heavy_chunk;          /* default 256 (the only compiled value)                       */
-    uint32_t medium_pair_cap;      /* default 65536                                               */
+    uint32_t medium_pair_cap;      /* default 2^27, at most 2^30                                  */
     uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;
                                       2: every triangle heavy; 3: every triangle medium
                                       (diagnostics and tests)                                     */

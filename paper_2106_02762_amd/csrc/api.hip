@@ -157,9 +157,11 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     if (!ctx) return fail(DT_EINVAL, "null context");
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    ctx->partials.reset();
+    if (ctx->batch) destroy_batch_runner(ctx->batch);
+    ctx->batch = nullptr;
+    ctx->scratch.partials.reset();
+    ctx->scratch.heavy_vals.reset();
     ctx->out8.reset();
-    ctx->heavy_vals.reset();
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
     for (auto &e : ctx->prof_ev)
         if (e) (void)hipEventDestroy(e);
@@ -300,7 +302,7 @@ int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]) {
     }
     dt_ctx *ctx = g->ctx;
     DeviceGuard dg(ctx->device);
-    DT_TRY(count_enqueue(g, dq, ctx->out8.as<int64_t>(), ctx->stream, false, nullptr));
+    DT_TRY(count_enqueue(g, dq, ctx->out8.as<int64_t>(), ctx->stream, false, nullptr, ctx->scratch));
     DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     DT_HIP(hipStreamSynchronize(ctx->stream));
     memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
@@ -326,7 +328,7 @@ int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stre
         DT_HIP(hipEventRecord(ctx->ev_a, ctx->stream));
         DT_HIP(hipStreamWaitEvent(s, ctx->ev_a, 0));
     }
-    DT_TRY(count_enqueue(g, dq, out8, s, false, nullptr));
+    DT_TRY(count_enqueue(g, dq, out8, s, false, nullptr, ctx->scratch));
     if (s != ctx->stream) {
         DT_HIP(hipEventRecord(ctx->ev_b, s));
         DT_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_b, 0));
@@ -348,7 +350,7 @@ int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]) {
     DeviceGuard dg(ctx->device);
     DevMem cells;
     DT_TRY(dev_alloc(ctx, cells, 48 * sizeof(int64_t)));
-    DT_TRY(count_enqueue(g, dq, nullptr, ctx->stream, true, cells.as<int64_t>()));
+    DT_TRY(count_enqueue(g, dq, nullptr, ctx->stream, true, cells.as<int64_t>(), ctx->scratch));
     DT_HIP(hipMemcpyAsync(out, cells.ptr, 48 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     DT_HIP(hipStreamSynchronize(ctx->stream));
     return DT_OK;

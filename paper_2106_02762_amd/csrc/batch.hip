@@ -1,29 +1,310 @@
-// Batched counting: many (graph, query) pairs in one call.
-#include "internal.h"
+// Batched counting: many (graph, query) pairs in one persistent launch.
+//
+// The batch becomes one table of work items, each a bounded piece of one query's work: a run of
+// light triangles (one lane per triangle) or a run of medium-path items (one wavefront per item).
+// A persistent grid strides over the table, so graphs of very different sizes and queries with
+// different deltas and windows share the device evenly, and one launch serves the whole batch
+// whatever its composition.  Every item writes its own 8 partial sums (no atomics); a second
+// kernel adds each query's items.  The two kernels and the copy of the results to pinned host
+// memory are captured once in a HIP graph and replayed: only the item table, uploaded before the
+// replay, changes between batches.  The rare triangles beyond the medium path's reach (the
+// prefix-count path) are enqueued per query ahead of the replay and deliver their sums into a
+// reserved item slot.  The run length of light items is chosen by timing candidates on the first
+// batch of a context (autotuning); results never depend on it.
+#include <cstring>
+#include <memory>
+
+#include "count_dev.h"
 
 namespace dt {
+
+using namespace cdev;
+
+namespace {
+
+constexpr unsigned kBB = 256;
+constexpr uint32_t kMediumGroup = 16;   // medium items per table entry
+
+struct BQuery {
+    const uint32_t *light, *medium, *mitems, *eoff;
+    const uint64_t *key;
+    DQuery q;
+};
+
+struct BItem {
+    uint32_t q, kind, b, e;   // kind 0: light triangles [b, e); 1: medium items [b, e); 2: heavy sums
+};
+
+__global__ void __launch_bounds__(kBB)
+k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
+        const BQuery *__restrict__ qs, int64_t *__restrict__ part) {
+    const uint32_t n_items = *n_items_p;
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BItem I = items[it];
+        if (I.kind == 2) continue;
+        const BQuery Q = qs[I.q];
+        Acc<false> acc;
+        if (I.kind == 0) {
+            for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri<false>(Q.light, i, Q.eoff, Q.key, Q.q, acc);
+        } else {
+            for (uint64_t j = I.b + wave; j < I.e; j += kBB / 64)
+                medium_item<false>(Q.medium, Q.mitems, j, Q.eoff, Q.key, Q.q, acc, lane);
+        }
+        block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
+        __syncthreads();
+    }
+}
+
+// out[i] = sum of the partials of query i's items [qfirst[i], qfirst[i+1])
+__global__ void k_batch_reduce(const uint32_t *__restrict__ nq_p, const uint32_t *__restrict__ qfirst,
+                               const int64_t *__restrict__ part, int64_t *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nq_p) return;
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t it = qfirst[i]; it < qfirst[i + 1]; ++it)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] += part[8 * (uint64_t)it + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) out[8 * (uint64_t)i + j] = t[j];
+}
+
+template <class T> int host_grow(T *&p, uint64_t &cap, uint64_t want) {
+    if (p && cap >= want) return DT_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    uint64_t c = want + want / 2 + 16;
+    hipError_t e = hipHostMalloc((void **)&p, c * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(DT_ENOMEM, "pinned allocation of %llu bytes failed", (unsigned long long)(c * sizeof(T)));
+    cap = c;
+    return DT_OK;
+}
+
+}  // namespace
+
+struct BatchRunner {
+    dt_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
+    Scratch sc;
+    // pinned host tables
+    BItem *h_items = nullptr;
+    BQuery *h_q = nullptr;
+    uint32_t *h_qfirst = nullptr, *h_counts = nullptr;
+    int64_t *h_out = nullptr;
+    uint64_t cap_h_items = 0, cap_h_q = 0, cap_h_qfirst = 0, cap_h_out = 0, cap_h_counts = 0;
+    // device tables
+    DevMem d_items, d_q, d_qfirst, d_counts, d_part, d_out;
+    uint64_t cap_items = 0, cap_q = 0;
+    // captured graph for the current capacities
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_items = 0, g_q = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> heavy;   // (query, item slot)
+    uint64_t n_items = 0, nq = 0;
+
+    int init(dt_ctx *c) {
+        ctx = c;
+        DT_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        DT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        DT_HIP(hipEventCreate(&t0));
+        DT_HIP(hipEventCreate(&t1));
+        return DT_OK;
+    }
+
+    ~BatchRunner() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (h_items) (void)hipHostFree(h_items);
+        if (h_q) (void)hipHostFree(h_q);
+        if (h_qfirst) (void)hipHostFree(h_qfirst);
+        if (h_counts) (void)hipHostFree(h_counts);
+        if (h_out) (void)hipHostFree(h_out);
+        if (done) (void)hipEventDestroy(done);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    // Build the item table for k queries (empty[i]: the query's window holds no edge).
+    int plan(uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty, uint32_t light_chunk) {
+        nq = k;
+        heavy.clear();
+        uint64_t total = 0;
+        for (uint64_t i = 0; i < k; ++i) {
+            if (empty[i]) continue;
+            const Schedule &S = graphs[i]->sched;
+            total += (S.n_light + light_chunk - 1) / light_chunk + (S.n_mitems + kMediumGroup - 1) / kMediumGroup +
+                     (S.n_heavy ? 1 : 0);
+        }
+        if (total >= 0xffffffffull) return fail(DT_EOVERFLOW, "batch table too large");
+        DT_TRY(host_grow(h_items, cap_h_items, total + 1));
+        DT_TRY(host_grow(h_q, cap_h_q, k + 1));
+        DT_TRY(host_grow(h_qfirst, cap_h_qfirst, k + 2));
+        DT_TRY(host_grow(h_counts, cap_h_counts, 4));
+        uint64_t n = 0;
+        for (uint64_t i = 0; i < k; ++i) {
+            h_qfirst[i] = (uint32_t)n;
+            dt_graph *g = graphs[i];
+            const Schedule &S = g->sched;
+            h_q[i] = BQuery{S.light.as<uint32_t>(), S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+                            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), qs[i]};
+            if (empty[i]) continue;
+            for (uint64_t b = 0; b < S.n_light; b += light_chunk)
+                h_items[n++] = BItem{(uint32_t)i, 0, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + light_chunk, S.n_light)};
+            for (uint64_t b = 0; b < S.n_mitems; b += kMediumGroup)
+                h_items[n++] = BItem{(uint32_t)i, 1, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + kMediumGroup, S.n_mitems)};
+            if (S.n_heavy) {
+                heavy.emplace_back((uint32_t)i, (uint32_t)n);
+                h_items[n++] = BItem{(uint32_t)i, 2, 0, 0};
+            }
+        }
+        h_qfirst[k] = (uint32_t)n;
+        h_counts[0] = (uint32_t)n;
+        h_counts[1] = (uint32_t)k;
+        n_items = n;
+        return DT_OK;
+    }
+
+    int ensure_device() {
+        bool regrow = false;
+        if (!d_items.ptr || cap_items < n_items + 1) {
+            cap_items = n_items + n_items / 2 + 64;
+            DT_TRY(dev_alloc(ctx, d_items, cap_items * sizeof(BItem)));
+            DT_TRY(dev_alloc(ctx, d_part, cap_items * 8 * sizeof(int64_t)));
+            regrow = true;
+        }
+        if (!d_q.ptr || cap_q < nq + 1) {
+            cap_q = nq + nq / 2 + 64;
+            DT_TRY(dev_alloc(ctx, d_q, cap_q * sizeof(BQuery)));
+            DT_TRY(dev_alloc(ctx, d_qfirst, (cap_q + 1) * 4));
+            DT_TRY(dev_alloc(ctx, d_out, cap_q * 8 * sizeof(int64_t)));
+            regrow = true;
+        }
+        if (!d_counts.ptr) DT_TRY(dev_alloc(ctx, d_counts, 256));
+        if (regrow || cap_h_out < 8 * cap_q) {
+            DT_TRY(host_grow(h_out, cap_h_out, 8 * cap_q));
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+        return DT_OK;
+    }
+
+    int capture() {
+        if (gexec) return DT_OK;
+        const unsigned grid = (unsigned)ctx->num_cus * 8;
+        hipGraph_t graph = nullptr;
+        DT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        k_batch<<<grid, kBB, 0, stream>>>(d_items.as<BItem>(), d_counts.as<uint32_t>(), d_q.as<BQuery>(),
+                                          d_part.as<int64_t>());
+        k_batch_reduce<<<grid_for(cap_q, 256), 256, 0, stream>>>(d_counts.as<uint32_t>() + 1, d_qfirst.as<uint32_t>(),
+                                                                 d_part.as<int64_t>(), d_out.as<int64_t>());
+        (void)hipMemcpyAsync(h_out, d_out.ptr, cap_q * 8 * sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+        hipError_t e = hipStreamEndCapture(stream, &graph);
+        if (e != hipSuccess) return fail(DT_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            gexec = nullptr;
+            return fail(DT_EDEVICE, "batch graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        g_items = cap_items;
+        g_q = cap_q;
+        return DT_OK;
+    }
+
+    // Enqueue the planned batch on the runner's stream; results land in h_out when `done` fires.
+    int launch(dt_graph *const *graphs, const DQuery *qs) {
+        DT_TRY(ensure_device());
+        DT_TRY(capture());
+        DT_HIP(hipMemcpyAsync(d_items.ptr, h_items, n_items * sizeof(BItem), hipMemcpyHostToDevice, stream));
+        DT_HIP(hipMemcpyAsync(d_q.ptr, h_q, nq * sizeof(BQuery), hipMemcpyHostToDevice, stream));
+        DT_HIP(hipMemcpyAsync(d_qfirst.ptr, h_qfirst, (nq + 1) * 4, hipMemcpyHostToDevice, stream));
+        DT_HIP(hipMemcpyAsync(d_counts.ptr, h_counts, 8, hipMemcpyHostToDevice, stream));
+        for (auto &hq : heavy)
+            DT_TRY(count_enqueue(graphs[hq.first], qs[hq.first], d_part.as<int64_t>() + 8 * (uint64_t)hq.second,
+                                 stream, false, nullptr, sc, 4));
+        DT_HIP(hipGraphLaunch(gexec, stream));
+        DT_HIP(hipEventRecord(done, stream));
+        return DT_OK;
+    }
+};
+
+void destroy_batch_runner(BatchRunner *r) { delete r; }
+
+int make_batch_runner(dt_ctx *ctx, BatchRunner **out) {
+    BatchRunner *r = new BatchRunner();
+    int rc = r->init(ctx);
+    if (rc != DT_OK) {
+        delete r;
+        return rc;
+    }
+    *out = r;
+    return DT_OK;
+}
+
+int batch_plan_and_launch(BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty,
+                          uint32_t light_chunk) {
+    DT_TRY(r->plan(k, graphs, qs, empty, light_chunk));
+    return r->launch(graphs, qs);
+}
+
+int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]) {
+    DT_HIP(hipEventSynchronize(r->done));
+    for (uint64_t i = 0; i < k; ++i)
+        for (int j = 0; j < 8; ++j) out[i][j] = empty[i] ? 0 : r->h_out[8 * i + j];
+    return DT_OK;
+}
+
+bool batch_ready(BatchRunner *r) { return hipEventQuery(r->done) == hipSuccess; }
+
+int batch_sync(BatchRunner *r) {
+    DT_HIP(hipEventSynchronize(r->done));
+    return DT_OK;
+}
 
 int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
                 int64_t (*out)[8]) {
     if (k == 0) return DT_OK;
-    DevMem outs;
-    DT_TRY(dev_alloc(ctx, outs, k * 8 * sizeof(int64_t)));
-    hipStream_t s = ctx->stream;
-    DT_HIP(hipMemsetAsync(outs.ptr, 0, k * 8 * sizeof(int64_t), s));
+    std::vector<DQuery> qs(k);
+    std::unique_ptr<bool[]> empty(new bool[k]);
     for (uint64_t i = 0; i < k; ++i) {
         dt_graph *g = graphs[i];
         if (!g || g->ctx != ctx) return fail(DT_EINVAL, "batch entry %llu: graph of another context", (unsigned long long)i);
         if (!g->built) return fail(DT_ENOTBUILT, "batch entry %llu: graph not built", (unsigned long long)i);
-        DQuery dq;
-        bool empty = false;
-        DT_TRY(normalise_query(g, &queries[i], &dq, &empty));
+        bool e = false;
+        DT_TRY(normalise_query(g, &queries[i], &qs[i], &e));
         if ((g->sum_sigma3 >> 63) != 0) return fail(DT_EOVERFLOW, "batch entry %llu may overflow", (unsigned long long)i);
-        if (empty || g->n_tri == 0) continue;
-        DT_TRY(count_enqueue(g, dq, outs.as<int64_t>() + 8 * i, s, false, nullptr));
+        empty[i] = e || g->n_tri == 0;
     }
-    DT_HIP(hipMemcpyAsync(out, outs.ptr, k * 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    DT_HIP(hipStreamSynchronize(s));
-    return DT_OK;
+    if (!ctx->batch) DT_TRY(make_batch_runner(ctx, &ctx->batch));
+    BatchRunner *r = ctx->batch;
+    // the context's own stream and the runner's stream must not overlap on the graphs' scratch
+    DT_HIP(hipStreamSynchronize(ctx->stream));
+    if (!ctx->batch_light_chunk) {
+        // autotune: time each candidate run length on this batch and keep the fastest
+        const uint32_t cands[3] = {2048, 8192, 32768};
+        float best = 1e30f;
+        uint32_t best_c = cands[1];
+        for (uint32_t c : cands) {
+            DT_TRY(r->plan(k, graphs, qs.data(), empty.get(), c));
+            DT_TRY(r->ensure_device());
+            DT_TRY(r->capture());
+            DT_TRY(r->launch(graphs, qs.data()));   // warm (uploads, graph instantiation)
+            DT_HIP(hipEventRecord(r->t0, r->stream));
+            DT_TRY(r->launch(graphs, qs.data()));
+            DT_HIP(hipEventRecord(r->t1, r->stream));
+            DT_HIP(hipEventSynchronize(r->t1));
+            float ms = 0;
+            DT_HIP(hipEventElapsedTime(&ms, r->t0, r->t1));
+            if (ms < best) {
+                best = ms;
+                best_c = c;
+            }
+        }
+        ctx->batch_light_chunk = best_c;
+    }
+    DT_TRY(batch_plan_and_launch(r, k, graphs, qs.data(), empty.get(), ctx->batch_light_chunk));
+    return batch_wait(r, k, empty.get(), out);
 }
 
 }  // namespace dt

@@ -21,199 +21,13 @@
 //
 // Counts are int64 and summed per lane, per wave, per block, then per launch, with no atomics on
 // the result (cells mode, a diagnostic, uses atomics).
-#include "internal.h"
+#include "count_dev.h"
 
 namespace dt {
 
+using namespace cdev;
+
 namespace {
-
-// ---------------------------------------------------------------------------------------------
-// cell and type tables
-// ---------------------------------------------------------------------------------------------
-// Figure 4: orientation number from the direction bit of each pair (0 = from the earlier vertex
-// of the ordering u < v < w, 1 = towards it).
-__host__ __device__ constexpr int rho_of(int d_uv, int d_uw, int d_vw) {
-    constexpr int tab[8] = {/*000*/ 1, /*001*/ 3, /*010*/ 4, /*011*/ 2,
-                            /*100*/ 5, /*101*/ 7, /*110*/ 8, /*111*/ 6};
-    return tab[(d_uv << 2) | (d_uw << 1) | d_vw];
-}
-
-// Table 2: psi[pi - 1][rho - 1] = type.
-__host__ __device__ constexpr int psi_of(int pi, int rho) {
-    constexpr int tab[6][8] = {
-        {7, 6, 5, 8, 3, 2, 4, 1},
-        {5, 3, 7, 4, 6, 1, 8, 2},
-        {3, 2, 1, 4, 7, 6, 8, 5},
-        {1, 7, 3, 8, 2, 5, 4, 6},
-        {6, 1, 2, 8, 5, 3, 4, 7},
-        {2, 5, 6, 4, 1, 7, 8, 3},
-    };
-    return tab[pi - 1][rho - 1];
-}
-
-// 0-based type index and cell index of (pi, direction bits)
-template <int PI, int DUV, int DUW, int DVW> struct Cell {
-    static constexpr int rho = rho_of(DUV, DUW, DVW);
-    static constexpr int type = psi_of(PI, rho) - 1;
-    static constexpr int cell = (PI - 1) * 8 + (rho - 1);
-};
-
-// accumulators: per-lane type counts, or (diagnostic) global atomics per cell
-template <bool CELLS> struct Acc;
-template <> struct Acc<false> {
-    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t *cells = nullptr;
-    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
-        t[CA::type] += first ? v : 0;
-        t[CB::type] += first ? 0 : v;
-    }
-    template <class C> __device__ __forceinline__ void add(int64_t v) { t[C::type] += v; }
-};
-template <> struct Acc<true> {
-    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t *cells = nullptr;
-    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
-        if (v) atomicAdd((unsigned long long *)(cells + (first ? CA::cell : CB::cell)),
-                         (unsigned long long)v);
-    }
-    template <class C> __device__ __forceinline__ void add(int64_t v) {
-        if (v) atomicAdd((unsigned long long *)(cells + C::cell), (unsigned long long)v);
-    }
-};
-
-// ---------------------------------------------------------------------------------------------
-// searches on key-sorted lists
-// ---------------------------------------------------------------------------------------------
-// first index in [lo, hi) whose key is >= K (hi if none)
-__device__ __forceinline__ uint32_t lower(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi,
-                                          uint64_t K) {
-    uint32_t len = hi - lo;
-    while (len > 0) {
-        uint32_t half = len >> 1;
-        if (key[lo + half] < K) {
-            lo += half + 1;
-            len -= half + 1;
-        } else {
-            len = half;
-        }
-    }
-    return lo;
-}
-
-// key bound of "t < x" for a relative time x
-__device__ __forceinline__ uint64_t before_time(int64_t x, const DQuery &q) {
-    return x <= 0 ? 0ull : (x > q.span ? ~0ull : ((uint64_t)x << q.shift));
-}
-
-struct Lists {
-    uint32_t lo[6], hi[6];   // uv+, uv-, uw+, uw-, vw+, vw- (clipped to the window)
-};
-
-__device__ __forceinline__ void load_lists(const uint32_t *__restrict__ eoff, uint32_t e_uv,
-                                           uint32_t e_uw, uint32_t e_vw, const uint64_t *__restrict__ key,
-                                           const DQuery &q, Lists &L) {
-    const uint32_t es[3] = {e_uv, e_uw, e_vw};
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1], c = eoff[2 * es[p] + 2];
-        L.lo[2 * p] = a;
-        L.hi[2 * p] = b;
-        L.lo[2 * p + 1] = b;
-        L.hi[2 * p + 1] = c;
-    }
-    if (q.windowed) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            uint32_t lo = L.lo[i], hi = L.hi[i];
-            L.lo[i] = lower(key, lo, hi, q.klo);
-            L.hi[i] = lower(key, L.lo[i], hi, q.khi);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// light path: one lane per triangle, every (uv edge, uw edge) pair
-// ---------------------------------------------------------------------------------------------
-template <bool CELLS, int A, int B, int C>
-__device__ __forceinline__ void light_third(const uint64_t *__restrict__ key, const Lists &L,
-                                            const DQuery &q, bool uv_first, uint64_t k_lo,
-                                            uint64_t k_hi, int64_t t_lo, int64_t t_hi, int64_t gap,
-                                            Acc<CELLS> &acc) {
-    const uint32_t zb = L.lo[4 + C], ze = L.hi[4 + C];
-    if (zb == ze) return;
-    const uint32_t below_lo = lower(key, zb, ze, k_lo);   // z with key < k_lo
-    const uint32_t below_hi = lower(key, below_lo, ze, k_hi);
-    // z first: e1 = z, e2 = earlier of x, y, e3 = later
-    if (gap <= q.d23) {
-        int64_t from = t_lo - q.d12 > t_hi - q.d13 ? t_lo - q.d12 : t_hi - q.d13;
-        uint32_t s = lower(key, zb, below_lo, before_time(from, q));
-        acc.template add2<Cell<5, A, B, C>, Cell<6, A, B, C>>(uv_first, (int64_t)(below_lo - s));
-    }
-    // z in the middle: t_hi - d23 <= t_z <= t_lo + d12, key between k_lo and k_hi
-    {
-        uint32_t a = lower(key, below_lo, below_hi, before_time(t_hi - q.d23, q));
-        uint32_t b = lower(key, below_lo, below_hi, before_time(t_lo + q.d12 + 1, q));
-        if (b > a) acc.template add2<Cell<3, A, B, C>, Cell<4, A, B, C>>(uv_first, (int64_t)(b - a));
-    }
-    // z last: t_z <= min(t_hi + d23, t_lo + d13), key after k_hi
-    if (gap <= q.d12) {
-        int64_t until = t_hi + q.d23 < t_lo + q.d13 ? t_hi + q.d23 : t_lo + q.d13;
-        uint32_t e = lower(key, below_hi, ze, before_time(until + 1, q));
-        acc.template add2<Cell<1, A, B, C>, Cell<2, A, B, C>>(uv_first, (int64_t)(e - below_hi));
-    }
-}
-
-template <bool CELLS, int A, int B>
-__device__ __forceinline__ void light_pairs(const uint64_t *__restrict__ key, const Lists &L,
-                                            const DQuery &q, Acc<CELLS> &acc) {
-    const uint32_t xb = L.lo[A], xe = L.hi[A], yb = L.lo[2 + B], ye = L.hi[2 + B];
-    for (uint32_t ix = xb; ix < xe; ++ix) {
-        const uint64_t kx = key[ix];
-        for (uint32_t iy = yb; iy < ye; ++iy) {
-            const uint64_t ky = key[iy];
-            const bool uv_first = kx < ky;
-            const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
-            const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
-            const int64_t gap = t_hi - t_lo;
-            if (gap > q.d13) continue;   // d12, d23 <= d13: no z completes this pair
-            light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-            light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-        }
-    }
-}
-
-// XCD-aware block order: blocks are dispatched round-robin over the 8 XCDs, so block b runs on
-// XCD b % 8; give each XCD a contiguous range of work so that triangles sharing u (adjacent in
-// the list) share that XCD's L2.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
-    if (nblk % 8) return b;
-    return (b % 8) * (nblk / 8) + b / 8;
-}
-
-template <class T> __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// reduce the block's 8 per-lane counters into out8 (block slot of the partials)
-template <unsigned BLOCK>
-__device__ __forceinline__ void block_store(const int64_t (&t)[8], int64_t *__restrict__ out8) {
-    __shared__ int64_t s[BLOCK / 64][8];
-    const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        int64_t v = wave_sum((long long)t[i]);
-        if (lane == 0) s[wave][i] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-        int64_t v = 0;
-#pragma unroll
-        for (unsigned w = 0; w < BLOCK / 64; ++w) v += s[w][threadIdx.x];
-        out8[threadIdx.x] = v;
-    }
-}
 
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
@@ -227,62 +41,22 @@ k_light(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__rest
     const uint64_t per = (n_tri + nblk - 1) / nblk;
     const uint64_t beg = (uint64_t)b * per;
     const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) {
-        Lists L;
-        load_lists(eoff, tri[3 * i], tri[3 * i + 1], tri[3 * i + 2], key, q, L);
-        light_pairs<CELLS, 0, 0>(key, L, q, acc);
-        light_pairs<CELLS, 0, 1>(key, L, q, acc);
-        light_pairs<CELLS, 1, 0>(key, L, q, acc);
-        light_pairs<CELLS, 1, 1>(key, L, q, acc);
-    }
+    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) light_tri<CELLS>(tri, i, eoff, key, q, acc);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
-// ---------------------------------------------------------------------------------------------
-// medium path: one wavefront per triangle, the (uv edge, uw edge) pairs spread over the lanes
-// ---------------------------------------------------------------------------------------------
-template <bool CELLS, int A, int B>
-__device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, const Lists &L,
-                                            const DQuery &q, uint32_t ix, uint32_t iy, Acc<CELLS> &acc) {
-    const uint64_t kx = key[ix], ky = key[iy];
-    const bool uv_first = kx < ky;
-    const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
-    const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
-    const int64_t gap = t_hi - t_lo;
-    if (gap > q.d13) return;
-    light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-    light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-}
-
-// triangles sorted by pair count, largest first; wave w takes w, w + W, w + 2W, ...
+// medium path: wave w takes work items w, w + W, w + 2W, ... (each at most kMediumChunk pairs)
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_medium(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
-         const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
-         int64_t *__restrict__ cells) {
+k_medium(uint64_t n_items, const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
+         const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, DQuery q,
+         int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
     Acc<CELLS> acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
-    for (uint64_t i = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; i < n_tri; i += W) {
-        Lists L;
-        load_lists(eoff, tri[3 * i], tri[3 * i + 1], tri[3 * i + 2], key, q, L);
-        const uint32_t su0 = L.hi[0] - L.lo[0], su = su0 + (L.hi[1] - L.lo[1]);
-        const uint32_t sw0 = L.hi[2] - L.lo[2], sw = sw0 + (L.hi[3] - L.lo[3]);
-        const uint32_t np = su * sw;   // at most the medium cap
-        for (uint32_t p = lane; p < np; p += 64) {
-            const uint32_t a = p / sw, b = p - a * sw;
-            const int A = a < su0 ? 0 : 1, B = b < sw0 ? 0 : 1;
-            const uint32_t ix = A ? L.lo[1] + (a - su0) : L.lo[0] + a;
-            const uint32_t iy = B ? L.lo[3] + (b - sw0) : L.lo[2] + b;
-            switch (A * 2 + B) {
-                case 0: medium_pair<CELLS, 0, 0>(key, L, q, ix, iy, acc); break;
-                case 1: medium_pair<CELLS, 0, 1>(key, L, q, ix, iy, acc); break;
-                case 2: medium_pair<CELLS, 1, 0>(key, L, q, ix, iy, acc); break;
-                default: medium_pair<CELLS, 1, 1>(key, L, q, ix, iy, acc); break;
-            }
-        }
-    }
+    for (uint64_t it = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; it < n_items; it += W)
+        medium_item<CELLS>(med, items, it, eoff, key, q, acc, lane);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -617,17 +391,18 @@ int normalise_query(const dt_graph *g, const dt_query *qq, DQuery *out, bool *em
 // Enqueue one count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the 48
 // cells into cells_dev (zeroed here) instead.
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev) {
+                  int64_t *cells_dev, Scratch &sc, unsigned parts) {
     dt_ctx *ctx = g->ctx;
     Schedule &S = g->sched;
-    const unsigned light_grid = S.n_light ? (unsigned)std::min<uint64_t>(
+    const bool do_light = parts & 1, do_medium = parts & 2, do_heavy = parts & 4;
+    const unsigned light_grid = (S.n_light && do_light) ? (unsigned)std::min<uint64_t>(
         (S.n_light + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
     const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
-    const unsigned hg = S.n_chunks ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    const unsigned mg = S.n_medium ? (unsigned)std::min<uint64_t>((S.n_medium + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
+    const unsigned hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
+    const unsigned mg = (S.n_mitems && do_medium) ? (unsigned)std::min<uint64_t>((S.n_mitems + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
     const uint64_t n_part = (uint64_t)lg + hg + mg;
-    DT_TRY(ensure(ctx, ctx->partials, (n_part + 1) * 8 * sizeof(int64_t)));
-    int64_t *part = ctx->partials.as<int64_t>();
+    DT_TRY(ensure(ctx, sc.partials, (n_part + 1) * 8 * sizeof(int64_t)));
+    int64_t *part = sc.partials.as<int64_t>();
     if (cells) {
         k_zero<<<1, 64, 0, s>>>(48, cells_dev);
         DT_HIP(hipGetLastError());
@@ -646,17 +421,19 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     if (mg) {
         prof_begin(ctx, kProfMedium, s);
         if (cells)
-            k_medium<true, 256><<<mg, 256, 0, s>>>(S.n_medium, S.medium.as<uint32_t>(), g->eoff.as<uint32_t>(),
+            k_medium<true, 256><<<mg, 256, 0, s>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+                g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
         else
-            k_medium<false, 256><<<mg, 256, 0, s>>>(S.n_medium, S.medium.as<uint32_t>(), g->eoff.as<uint32_t>(),
+            k_medium<false, 256><<<mg, 256, 0, s>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+                g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
         prof_end(ctx, kProfMedium, s);
         DT_HIP(hipGetLastError());
     }
-    if (S.n_heavy) {
-        DT_TRY(ensure(ctx, ctx->heavy_vals, S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256));
-        int64_t *P = ctx->heavy_vals.as<int64_t>();
+    if (S.n_heavy && do_heavy) {
+        DT_TRY(ensure(ctx, sc.heavy_vals, S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256));
+        int64_t *P = sc.heavy_vals.as<int64_t>();
         uint32_t *clip = reinterpret_cast<uint32_t *>(P + S.n_slots * kVals);
         k_heavy_clip<<<grid_for(S.n_heavy, 256), 256, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, clip);

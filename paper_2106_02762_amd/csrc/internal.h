@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -58,6 +59,14 @@ struct DevMem {
 
 }  // namespace dt
 
+namespace dt {
+// scratch of one count in flight: per-block partial sums and the heavy path's prefix arrays
+struct Scratch {
+    DevMem partials, heavy_vals;
+};
+struct BatchRunner;
+}  // namespace dt
+
 struct dt_ctx {
     int device = 0;
     uint64_t budget = 0;                 // 0 = no cap
@@ -65,7 +74,10 @@ struct dt_ctx {
     hipStream_t stream = nullptr;
     int num_cus = 0;
     // scratch reused by counts issued on the context's stream
-    dt::DevMem partials, out8, heavy_vals;
+    dt::Scratch scratch;
+    dt::DevMem out8;
+    dt::BatchRunner *batch = nullptr;        // dt_count_batch's runner (created on first use)
+    uint32_t batch_light_chunk = 0;          // autotuned on first use (0 = not yet)
     int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
     // optional per-kernel timing (dt_ctx_set_profiling)
@@ -100,13 +112,18 @@ struct DQuery {
     int windowed;            // 0: klo = 0, khi = ~0
 };
 
+// (uv edge, uw edge) pairs per medium-path work item
+constexpr uint32_t kMediumChunk = 4096;
+
 // ------------------------------------------------------------------------------------------------
 // build products of one graph (all device arrays unless noted)
 // ------------------------------------------------------------------------------------------------
 struct Schedule {
     uint64_t n_light = 0, n_medium = 0, n_heavy = 0;
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
-    DevMem medium;      // uint32[3 * n_medium], largest pair count first
+    DevMem medium;      // uint32[3 * n_medium]
+    DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, first pair) work items
+    uint64_t n_mitems = 0;
     DevMem heavy;       // uint32[3 * n_heavy]
     DevMem hslot;       // uint64[n_heavy + 1]: first scratch slot of each heavy triangle
     uint64_t n_slots = 0;
@@ -147,7 +164,7 @@ struct dt_graph {
     uint64_t alg_bytes = 0, alg_bytes_light = 0, alg_bytes_medium = 0, alg_bytes_peel = 0, alg_bytes_tri = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{64, 256, 65536, 0};
+    dt_tuning tuning{64, 256, 1u << 27, 0};
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 
@@ -162,8 +179,20 @@ int make_schedule(dt_graph *g, DevMem &tri);
 
 // counting
 int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *empty);
+// Enqueue one count on stream s using scratch sc.  parts: bit 0 light, bit 1 medium, bit 2 heavy
+// (all = 7).  Without cells the sum of the selected parts goes to out8_dev (int64[8]); with cells
+// the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev);
+                  int64_t *cells_dev, Scratch &sc, unsigned parts = 7);
+void destroy_batch_runner(BatchRunner *r);
+int make_batch_runner(dt_ctx *ctx, BatchRunner **out);
+// plan the item table of k queries and enqueue it on the runner's stream (asynchronous)
+int batch_plan_and_launch(BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs,
+                          const bool *empty, uint32_t light_chunk);
+int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]);
+bool batch_ready(BatchRunner *r);
+int batch_sync(BatchRunner *r);
+uint64_t graph_device_bytes(const dt_graph *g);
 int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
                 int64_t (*out)[8]);
 

@@ -2,8 +2,7 @@
 // independent of time periods"): each static triangle goes to the light path (one lane), the
 // medium path (one wavefront) or the heavy path (the prefix-count procedures split over
 // workgroups), decided by P = sigma_uv * sigma_uw, the number of (uv edge, uw edge) pairs the
-// pairwise paths walk.  Medium triangles are ordered by P, largest first, so that the static
-// interleaving of the medium kernel spreads the work evenly.  Also the graph totals reported in the
+// pairwise paths walk.  A medium triangle becomes ceil(P / kMediumChunk) work items of equal size.  Also the graph totals reported in the
 // statistics: the sum over triangles of the product of the three pair multiplicities (the count at
 // infinite deltas, an overflow bound) and the algorithmic bytes of one whole-graph count.
 #include "internal.h"
@@ -84,25 +83,24 @@ __global__ void k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, co
     dst[2] = tri[3 * i + 2];
 }
 
-// sort key of a medium triangle: its pair count, descending
-__global__ void k_medium_keys(uint64_t nm, const uint32_t *__restrict__ med, const uint32_t *__restrict__ eoff,
-                              uint64_t *__restrict__ key, uint32_t *__restrict__ idx) {
+// work items of the medium path: ceil(P / kMediumChunk) per triangle
+__global__ void k_medium_sizes(uint64_t nm, const uint32_t *__restrict__ med, const uint32_t *__restrict__ eoff,
+                               uint64_t *__restrict__ nch) {
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nm) return;
     const uint32_t e_uv = med[3 * i], e_uw = med[3 * i + 1];
     const uint64_t P = (uint64_t)(eoff[2 * e_uv + 2] - eoff[2 * e_uv]) * (eoff[2 * e_uw + 2] - eoff[2 * e_uw]);
-    key[i] = 0xffffffffull - (P < 0xffffffffull ? P : 0xffffffffull);
-    idx[i] = (uint32_t)i;
+    nch[i] = (P + kMediumChunk - 1) / kMediumChunk;
 }
 
-__global__ void k_gather3(uint64_t n, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ in,
-                          uint32_t *__restrict__ out) {
+__global__ void k_medium_fill(uint64_t nm, const uint64_t *__restrict__ nch, const uint64_t *__restrict__ base,
+                              uint32_t *__restrict__ items) {
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t j = idx[i];
-    out[3 * i] = in[3 * (uint64_t)j];
-    out[3 * i + 1] = in[3 * (uint64_t)j + 1];
-    out[3 * i + 2] = in[3 * (uint64_t)j + 2];
+    if (i >= nm) return;
+    for (uint64_t j = 0; j < nch[i]; ++j) {
+        items[2 * (base[i] + j)] = (uint32_t)i;
+        items[2 * (base[i] + j) + 1] = (uint32_t)(j * kMediumChunk);
+    }
 }
 
 // slots (four prefix arrays of length sigma + 1) and chunks of every heavy triangle
@@ -175,33 +173,38 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     S.n_heavy = nh;
     S.n_medium = nm;
     S.n_light = nt - nh - nm;
-    DevMem med_unsorted;
     DT_TRY(dev_alloc(ctx, S.light, S.n_light * 12));
-    DT_TRY(dev_alloc(ctx, med_unsorted, S.n_medium * 12));
     DT_TRY(dev_alloc(ctx, S.medium, S.n_medium * 12));
     DT_TRY(dev_alloc(ctx, S.heavy, S.n_heavy * 12));
     if (nt) {
         k_partition<<<grid_for(nt, kBlock), kBlock, 0, st>>>(nt, tri.as<uint32_t>(), f1.as<uint64_t>(),
             f2.as<uint64_t>(), p1.as<uint64_t>(), p2.as<uint64_t>(), S.light.as<uint32_t>(),
-            med_unsorted.as<uint32_t>(), S.heavy.as<uint32_t>());
+            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>());
         DT_HIP(hipGetLastError());
     }
     DT_HIP(hipStreamSynchronize(st));
     f1.reset(); f2.reset(); p1.reset(); p2.reset();
-    if (nm) {
-        DevMem mk, mi, mk2, mi2;
-        DT_TRY(dev_alloc(ctx, mk, nm * 8));
-        DT_TRY(dev_alloc(ctx, mi, nm * 4));
-        DT_TRY(dev_alloc(ctx, mk2, nm * 8));
-        DT_TRY(dev_alloc(ctx, mi2, nm * 4));
-        k_medium_keys<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, med_unsorted.as<uint32_t>(), g->eoff.as<uint32_t>(),
-                                                               mk.as<uint64_t>(), mi.as<uint32_t>());
-        DT_HIP(hipGetLastError());
-        DT_TRY(sort_pairs_u64_u32(ctx, mk.as<uint64_t>(), mk2.as<uint64_t>(), mi.as<uint32_t>(),
-                                  mi2.as<uint32_t>(), nm, 32, st));
-        k_gather3<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, mi2.as<uint32_t>(), med_unsorted.as<uint32_t>(),
-                                                           S.medium.as<uint32_t>());
-        DT_HIP(hipGetLastError());
+    {
+        DevMem nch, base;
+        DT_TRY(dev_alloc(ctx, nch, (nm + 1) * 8));
+        DT_TRY(dev_alloc(ctx, base, (nm + 1) * 8));
+        DT_HIP(hipMemsetAsync(nch.ptr, 0, (nm + 1) * 8, st));
+        if (nm) {
+            k_medium_sizes<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, S.medium.as<uint32_t>(),
+                                                                    g->eoff.as<uint32_t>(), nch.as<uint64_t>());
+            DT_HIP(hipGetLastError());
+        }
+        DT_TRY(exclusive_scan_u64(ctx, nch.as<uint64_t>(), base.as<uint64_t>(), nm + 1, st));
+        uint64_t ni = 0;
+        DT_HIP(hipMemcpyAsync(&ni, base.as<uint64_t>() + nm, 8, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipStreamSynchronize(st));
+        S.n_mitems = ni;
+        DT_TRY(dev_alloc(ctx, S.mitems, ni * 8));
+        if (nm) {
+            k_medium_fill<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, nch.as<uint64_t>(), base.as<uint64_t>(),
+                                                                   S.mitems.as<uint32_t>());
+            DT_HIP(hipGetLastError());
+        }
         DT_HIP(hipStreamSynchronize(st));
     }
     // heavy slots and chunks
