@@ -31,6 +31,115 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def run_batched(dt, ctx, k):
+    """The batched workload: k independent graphs, each with its own deltas, in one call."""
+    import synth
+    t0 = time.time()
+    gs = [synth.batch_graph(i) for i in range(k)]
+    deltas = [synth.batch_delta(i) for i in range(k)]
+    log(f"generated {k} batch graphs ({sum(g.m for g in gs)} edges) in {time.time() - t0:.1f}s")
+    hs = []
+    for g in gs:
+        h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
+        dt.dt_graph_build(h)
+        hs.append((h, g.n, int(g.t.min()), int(g.t.max())))
+    handles = [h for h, *_ in hs]
+    qs = [dt.make_query(*d) for d in deltas]
+    first = dt.dt_count_batch(ctx, handles, qs)   # the first batch autotunes the item size
+    reps = 5
+    a = time.perf_counter()
+    for _ in range(reps):
+        out = dt.dt_count_batch(ctx, handles, qs)
+    batch_s = (time.perf_counter() - a) / reps
+    a = time.perf_counter()
+    alone = [dt.dt_count(h, *d) for h, d in zip(handles, deltas)]
+    plain_s = time.perf_counter() - a
+    ok = bool((out == first).all()) and all((out[i] == alone[i]).all() for i in range(k))
+    m = sum(g.m for g in gs)
+    res = {"workload": f"{k} directed Chung-Lu graphs, n log-uniform [1e3, 2e5], m = 10 n, own deltas",
+           "graphs": k, "edges": m, "batch_ms": round(batch_s * 1e3, 3),
+           "plain_one_query_per_launch_ms": round(plain_s * 1e3, 3),
+           "speedup_vs_plain": round(plain_s / batch_s, 2),
+           "graphs_per_s": round(k / batch_s, 1), "edges_per_s": round(m / batch_s, 1),
+           "results_match_alone": ok}
+    log("batched", res)
+    return res, hs
+
+
+def run_served(dt, ctx, graphs, seconds, warmup, rate):
+    """Open-loop Poisson stream over resident graphs through the serving loop: p50/p99 latency
+    (completion - arrival) after the warm-up, then the burst capacity against one query per
+    synchronous launch."""
+    import queue
+    import threading
+
+    import synth
+    spans = [(tmin, tmax) for _, _, tmin, tmax in graphs]
+    stream = synth.served_stream(spans, duration_s=warmup + seconds, rate=rate)
+    srv = dt.dt_server_start(ctx, max_batch=512, max_inflight_queries=1 << 20)
+    ids = [dt.dt_server_add_graph(srv, h) for h, *_ in graphs]
+    q = queue.Queue()
+    lat, res = {}, {}
+
+    def waiter():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            i, ticket, t_arr = item
+            r = dt.dt_server_wait(srv, ticket)
+            lat[i] = time.perf_counter() - t_arr
+            res[i] = r
+
+    ws = [threading.Thread(target=waiter) for _ in range(16)]
+    for w in ws:
+        w.start()
+    t0 = time.perf_counter()
+    for i, x in enumerate(stream):
+        target = t0 + x["arrival"]
+        now = time.perf_counter()
+        if target > now:
+            time.sleep(target - now)
+        t_arr = time.perf_counter()
+        ticket = dt.dt_server_submit(srv, ids[x["graph"]], x["d13"], x["d12"], x["d23"], x["t_lo"], x["t_hi"])
+        q.put((i, ticket, t_arr))
+    for _ in ws:
+        q.put(None)
+    for w in ws:
+        w.join()
+    elapsed = time.perf_counter() - t0
+    keep = [i for i, x in enumerate(stream) if x["arrival"] >= warmup]
+    ls = np.array([lat[i] for i in keep]) * 1e3
+    # burst capacity: every query of the measured part submitted at once
+    burst = [stream[i] for i in keep]
+    a = time.perf_counter()
+    tickets = [dt.dt_server_submit(srv, ids[x["graph"]], x["d13"], x["d12"], x["d23"], x["t_lo"], x["t_hi"])
+               for x in burst]
+    outs = [dt.dt_server_wait(srv, t) for t in tickets]
+    burst_s = time.perf_counter() - a
+    dt.dt_server_stop(srv)
+    # plain comparator: the same queries one synchronous launch each (a prefix of them)
+    n_plain = min(len(burst), 3000)
+    a = time.perf_counter()
+    plain = [dt.dt_count(graphs[x["graph"]][0], x["d13"], x["d12"], x["d23"], x["t_lo"], x["t_hi"])
+             for x in burst[:n_plain]]
+    plain_s = time.perf_counter() - a
+    ok = all((outs[j] == plain[j]).all() for j in range(n_plain)) and \
+        all((res[keep[j]] == outs[j]).all() for j in range(len(keep)))
+    out = {"workload": f"{len(graphs)} resident graphs (the full-size graph and {len(graphs) - 1} "
+                       f"batch-style graphs), Poisson arrivals at {rate:g}/s, deltas as in the batch "
+                       "workload, windows log-uniform in [1 day, span]",
+           "queries": len(keep), "warmup_s": warmup, "offered_per_s": rate,
+           "achieved_per_s": round(len(stream) / elapsed, 1),
+           "p50_ms": round(float(np.percentile(ls, 50)), 3), "p99_ms": round(float(np.percentile(ls, 99)), 3),
+           "burst_capacity_per_s": round(len(burst) / burst_s, 1),
+           "plain_one_query_per_launch_per_s": round(n_plain / plain_s, 1),
+           "capacity_vs_plain": round((len(burst) / burst_s) / (n_plain / plain_s), 2),
+           "results_match_alone": bool(ok)}
+    log("served", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +150,11 @@ def main():
     ap.add_argument("--cpu-window-frac", type=float, default=0.25,
                     help="oracle sample: edges in the first fraction of the time span")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=512,
+                    help="graphs of the batched workload (0 skips the batched and served parts)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -144,6 +258,14 @@ def main():
                "gpu_matches_oracle": bool((got == want).all())}
         log("cpu baseline", cpu)
 
+    batched = served = None
+    if args.batch_graphs > 0:
+        batched, bgraphs = run_batched(dt, ctx, args.batch_graphs)
+        served = run_served(dt, ctx, [(h, g.n, int(g.t.min()), int(g.t.max()))] + bgraphs[:64],
+                            args.serve_seconds, args.serve_warmup, args.serve_rate)
+        for bh, *_ in bgraphs:
+            dt.dt_graph_free(bh)
+
     line = {
         "metric": "temporal edges/s counted (63M-edge graph, delta=3600s); p50/p99 query latency",
         "value": round(value, 1),
@@ -173,6 +295,8 @@ def main():
                            "alg_bytes": st["alg_bytes"],
                            "achieved_GBs": round(st["alg_bytes"] / (count_ms[str(d)] / 1e3) / 1e9, 2)},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     dt.dt_graph_free(h)
     dt.dt_ctx_destroy(ctx)
