@@ -13,12 +13,14 @@
 // The whole peel is one cooperative (co-resident) grid of a few blocks: levels and rounds are
 // separated by grid barriers instead of kernel launches and host round trips, since power-law
 // graphs need thousands of rounds, most with frontiers of a few vertices.  A barrier's cost grows
-// with the number of blocks that meet at it, so the grid is small and wide (64 blocks of 512
+// with the number of blocks that meet at it, so the grid is small and wide (32 blocks of 1024
 // threads), and the barrier is a counter whose last arriving block also snapshots the queue and
 // survivor counters before it releases the others: each round then needs one barrier, and every
-// block takes the same branch because all decisions use the snapshot.  A vertex joins the queue
-// through a compare-and-swap on its level, so no vertex is queued twice and the queue never
-// exceeds n entries.  A barrier that waits far longer than any peel could take sets an error
+// block takes the same branch because all decisions use the snapshot.  A vertex is queued at most
+// once: by the level scan when its degree is <= k (no decrement runs during a scan), or by the
+// single decrement that takes its degree from k + 1 to k (degrees only fall, and a queued vertex
+// already has degree <= k, so no later decrement can see k + 1 again); the queue index is also
+// bounds-checked, and the host checks that exactly n vertices were queued.  A barrier that waits far longer than any peel could take sets an error
 // flag and lets its block go, so that a fault in this logic ends the kernel instead of hanging it.
 #include "internal.h"
 
@@ -26,8 +28,8 @@ namespace dt {
 
 namespace {
 
-constexpr unsigned kBlock = 512;
-constexpr unsigned kGridBlocks = 64;
+constexpr unsigned kBlock = 1024;
+constexpr unsigned kGridBlocks = 32;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr long kSpinLimit = 1l << 26;
 
@@ -91,10 +93,9 @@ __device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, bool reset_scan, unsig
 
 __device__ __forceinline__ void enqueue(uint32_t v, uint32_t k, uint32_t n, uint32_t *level,
                                         uint32_t *queue, PeelCtl *ctl) {
-    if (atomicCAS(&level[v], kUnset, k) == kUnset) {
-        uint32_t p = atomicAdd(&ctl->qtail, 1u);
-        if (p < n) queue[p] = v;
-    }
+    level[v] = k;
+    uint32_t p = atomicAdd(&ctl->qtail, 1u);
+    if (p < n) queue[p] = v;
 }
 
 __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_t stride, uint32_t k,
@@ -105,7 +106,6 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
     const uint32_t e = row[v + 1];
     for (uint32_t j = row[v] + first; j < e; j += stride) {
         const uint32_t x = col[j];
-        if (ld_relaxed(&level[x]) != kUnset) continue;
         const int old = atomicSub(&deg[x], 1);
         if (old == (int)k + 1) enqueue(x, k, n, level, queue, ctl);
     }

@@ -6,6 +6,8 @@
 // shorter and binary-searching the longer (hub vertices late in the ordering have long N+(v)
 // runs reached from many u).  The candidates of all v are spread over the 64 lanes through a
 // prefix sum of those walk lengths; a hit yields the DAG edge ids of {u, w} and {v, w} directly.
+// When the walk over N+(u) is long (kStage entries or more) the longer run N+(v) is first copied
+// into LDS, so those searches (most of them on power-law graphs) never touch global memory.
 //
 // Waves take source vertices from the highest rank down, so the heaviest (the dense core, last in
 // the ordering) start first.  Two passes (count per source vertex, exclusive scan, fill) write the
@@ -19,7 +21,8 @@ namespace {
 
 constexpr unsigned kBlock = 256;
 constexpr unsigned kWaves = kBlock / 64;
-constexpr uint32_t kCap = 1024;   // LDS entries of N+(u) per wavefront
+constexpr uint32_t kCap = 512;    // LDS entries of N+(u) (and of one N+(v)) per wavefront
+constexpr uint32_t kStage = 32;   // walks at least this long search an LDS copy of N+(v)
 constexpr uint32_t kChunk = 8;    // source vertices taken per grab of the work counter
 
 __device__ __forceinline__ uint32_t find_u32(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -59,8 +62,10 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     __shared__ uint32_t s_nbr[kWaves][kCap];
     __shared__ uint32_t s_pre[kWaves][kCap + 1];
     __shared__ uint32_t s_dv[kWaves][kCap];
+    __shared__ uint32_t s_vn[kWaves][kCap];
     const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-    uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *dv_lds = s_dv[wave];
+    uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *dv_lds = s_dv[wave], *vn_lds = s_vn[wave];
+    unsigned long long wave_cand = 0;   // candidates of the flattened walks, added once per wave
     for (;;) {
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(next_u, kChunk);
@@ -89,7 +94,8 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                         nbr_lds[i] = v;
                         dv_lds[i] = outv;
                     }
-                    dv = in_lds ? (outv < after ? outv : after) : (i + 1 < du ? outv : 0);
+                    const bool staged = outv > after && after >= kStage && outv <= kCap;
+                    dv = in_lds ? (staged ? 0 : (outv < after ? outv : after)) : (i + 1 < du ? outv : 0);
                 }
                 uint32_t x = dv;   // inclusive wave scan
 #pragma unroll
@@ -101,7 +107,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 carry += __shfl(x, 63, 64);
             }
             const uint32_t work = carry;
-            if (!FILL && lane == 0) atomicAdd(cand, (unsigned long long)work);
+            wave_cand += work;
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
@@ -142,6 +148,36 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                     }
                     c += __popcll(mask);
                 }
+                // long walks into a long N+(v): copy N+(v) into LDS, then search it there
+                for (uint32_t i = 0; i + kStage < du; ++i) {
+                    const uint32_t after = du - i - 1, outv = dv_lds[i];
+                    if (!(outv > after && after >= kStage && outv <= kCap)) continue;
+                    const uint32_t v = nbr_lds[i], vb = dag_row[v];
+                    wave_cand += after;
+                    __builtin_amdgcn_wave_barrier();
+                    for (uint32_t j = lane; j < outv; j += 64) vn_lds[j] = dag_col[vb + j];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    for (uint32_t b = 0; b < after; b += 64) {
+                        const uint32_t j = b + lane;
+                        bool hit = false;
+                        uint32_t pos = 0;
+                        if (j < after) {
+                            const uint32_t w = nbr_lds[i + 1 + j];
+                            pos = find_u32(vn_lds, 0, outv, w);
+                            hit = pos < outv && vn_lds[pos] == w;
+                        }
+                        const uint64_t mask = __ballot(hit);
+                        if (FILL && hit) {
+                            const uint64_t t = o + c + __popcll(mask & ((1ull << lane) - 1));
+                            tri[3 * t] = r0 + i;
+                            tri[3 * t + 1] = r0 + i + 1 + j;
+                            tri[3 * t + 2] = vb + pos;
+                        }
+                        c += __popcll(mask);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
             } else {
                 // N+(u) larger than the LDS slice: the same candidates, v by v, on global memory
                 for (uint32_t i = 0; i + 1 < du; ++i) {
@@ -172,6 +208,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
         if (!FILL && lane == 0) cnt[u] = c;
         }
     }
+    if (!FILL && lane == 0) atomicAdd(cand, wave_cand);
 }
 
 }  // namespace
