@@ -220,6 +220,7 @@ def main():
 
     # roofline of the dominant kernel of the step (event-timed on the library's stream)
     mean = {k: float(np.mean([p[k] for p in prof])) for k in prof[0]}
+    heavy_bytes = st["alg_bytes"] - st["alg_bytes_light"] - st["alg_bytes_medium"] - st["alg_bytes_unit"]
     alg = {
         "peel": st["alg_bytes_peel"],
         "relayout": 25 * st["m_loaded"],
@@ -227,8 +228,9 @@ def main():
         "tri_fill": 4 * (st["m_static"] + st["tri_candidates"]) + 12 * st["n_static_triangles"],
         "light": st["alg_bytes_light"],
         "medium": st["alg_bytes_medium"],
-        "heavy_prefix": st["alg_bytes"] - st["alg_bytes_light"] - st["alg_bytes_medium"],
-        "heavy_count": st["alg_bytes"] - st["alg_bytes_light"] - st["alg_bytes_medium"],
+        "unit": st["alg_bytes_unit"],
+        "heavy_prefix": heavy_bytes,
+        "heavy_count": heavy_bytes,
         "reduce": 64,
     }
     dom = max(mean, key=lambda k: mean[k])
@@ -236,8 +238,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": None, "alg_bytes": int(alg[dom]), "avg_ms": round(mean[dom], 4)}
-    count_kernels = {k: round(mean[k], 4) for k in ("light", "medium", "heavy_prefix", "heavy_count",
-                                                     "reduce")}
+    count_kernels = {k: round(mean[k], 4) for k in ("unit", "light", "medium", "heavy_prefix",
+                                                     "heavy_count", "reduce")}
 
     cpu = None
     if not args.no_cpu:
@@ -286,6 +288,7 @@ def main():
                      "schedule": round(st["ms_schedule"], 3)},
         "graph": {"m_static": st["m_static"], "static_triangles": st["n_static_triangles"],
                   "degeneracy": st["degeneracy"], "max_multiplicity": st["max_multiplicity"],
+                  "unit": st["n_unit_triangles"],
                   "light": st["n_light_triangles"], "medium": st["n_medium_triangles"],
                   "heavy": st["n_heavy_triangles"], "heavy_slots": st["heavy_slots"],
                   "tri_candidates": st["tri_candidates"],

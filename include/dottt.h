@@ -77,10 +77,13 @@ typedef struct {
                                               three pair multiplicities, 128-bit                  */
     uint64_t n_light_triangles, n_heavy_triangles; /* split chosen by the scheduler               */
     uint64_t n_medium_triangles;
-    uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count: per triangle
-                                      12 + 36 + 8 (s_uv + s_uw) + 8 min(s_vw, 2 ceil(log2(s_vw+1)))  */
+    uint64_t n_unit_triangles;     /* one temporal edge on each pair, stored as 16-byte records   */
+    uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count: 16 per unit
+                                      triangle, else 12 + 36 + 8 (s_uv + s_uw)
+                                      + 8 min(s_vw, 2 ceil(log2(s_vw+1)))                          */
     uint64_t alg_bytes_light;      /* the part of alg_bytes on light triangles                    */
     uint64_t alg_bytes_medium;     /* the part of alg_bytes on medium triangles                   */
+    uint64_t alg_bytes_unit;       /* the part of alg_bytes on unit triangles                     */
     uint64_t alg_bytes_peel;       /* 16 n + 16 m_static: CSR and state read once, one update per pair */
     uint64_t alg_bytes_triangles;  /* 4 (m_static + candidates) + 12 per triangle written         */
     uint64_t tri_candidates;       /* (v, w) candidates tested: sum over v of d-(v) d+(v)          */
@@ -88,11 +91,15 @@ typedef struct {
     double   ms_load, ms_peel, ms_orient, ms_triangles, ms_schedule; /* phase wall times          */
 } dt_stats;
 
-/* Tuning of the count scheduler.  A static triangle whose two source-incident pairs carry
- * P = sigma_uv * sigma_uw temporal-edge pairs is counted by one lane enumerating those pairs (the
- * pairwise form of Lemma 1) when P <= light_pair_cap, by wavefronts taking the pairs in chunks of
- * 4096 spread over their lanes when P <= medium_pair_cap, and otherwise by the prefix-count procedures of
- * Algorithms 1-3 split into chunks of `heavy_chunk` source edges.  Zero fields keep the default. */
+/* Tuning of the count scheduler.  A static triangle with one temporal edge on each pair (a unit
+ * triangle) is stored with its ordering and orientation decided (Figures 3 and 4) and counted by
+ * testing its three times against the query (when the graph's time span is below 2^31).  Any other
+ * triangle whose two source-incident pairs carry P = sigma_uv * sigma_uw temporal-edge pairs is
+ * counted by one lane enumerating those pairs (the pairwise form of Lemma 1) when
+ * P <= light_pair_cap, by wavefronts taking the pairs in chunks of 4096 spread over their lanes
+ * when P <= medium_pair_cap, and otherwise by the prefix-count procedures of Algorithms 1-3 split
+ * into chunks of `heavy_chunk` source edges.  Zero fields keep the default; force_path 1-3 sends
+ * every triangle, unit ones included, down one path. */
 typedef struct {
     uint32_t light_pair_cap;       /* default 64                                                  */
     uint32_t heavy_chunk;          /* default 256 (the only compiled value)                       */
@@ -152,9 +159,12 @@ int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_qu
                    int64_t (*out)[8]);
 
 /* Diagnostics of the build products, for tests.  Host outputs.
- * dt_graph_order: core[v] (core number) and rank[v] (position of v in the ordering) for all n.
+ * dt_graph_order: core[v] (core number) and rank[v] (position of v in the ordering) for all n;
+ * vertices removed in the same peel round may take their positions in a different order in
+ * another build (any such order is a degeneracy ordering), and with them the names u, v, w of a
+ * triangle's vertices that dt_count_cells uses.
  * dt_graph_triangles: the static triangles as node-id triples (a < b < c), in no fixed order;
- * writes min(count, cap) triples and sets *count. */
+ * writes min(count, cap) triples and sets *count (it runs the enumeration pass again). */
 int dt_graph_order(const dt_graph *g, uint32_t *core, uint32_t *rank);
 int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t *count);
 
@@ -164,9 +174,9 @@ int dt_graph_free(dt_graph *g);
  * launched on, around the main kernels of the last build and the last count of the context:
  *   ms[0] core peel, ms[1] store re-layout, ms[2] triangle count pass, ms[3] triangle fill pass,
  *   ms[4] light count, ms[5] heavy prefix pass, ms[6] heavy count pass, ms[7] final reduction,
- *   ms[8] medium count.
+ *   ms[8] medium count, ms[9] unit-triangle count.
  * dt_ctx_last_profile waits for those events and reports their elapsed times (0 if not run). */
-#define DT_PROFILE_SLOTS 9
+#define DT_PROFILE_SLOTS 10
 int dt_ctx_set_profiling(dt_ctx *ctx, int enable);
 int dt_ctx_last_profile(dt_ctx *ctx, float ms[DT_PROFILE_SLOTS]);
 

@@ -203,7 +203,11 @@ int dt_graph_build(dt_graph *g) {
     DT_TRY(orient(g));
     double t2 = now_ms();
     DevMem tri;
-    DT_TRY(enumerate_triangles(g, tri));
+    uint64_t ntri = 0, cand = 0;
+    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    g->n_tri = ntri;
+    g->tri_candidates = cand;
+    g->alg_bytes_tri = 4 * (g->m_s + cand) + 12 * ntri;
     double t3 = now_ms();
     DT_TRY(make_schedule(g, tri));
     double t4 = now_ms();
@@ -229,17 +233,13 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     if (nt.medium_pair_cap > (1u << 30)) return fail(DT_EINVAL, "medium_pair_cap must be at most 2^30");
     g->tuning = nt;
     if (!g->built) return DT_OK;
-    // re-split the resident triangles under the new tuning
+    // re-split the triangles under the new tuning (unit triangles keep no edge ids, so the
+    // enumeration pass runs again; it yields the same triangles)
     DeviceGuard dg(g->ctx->device);
-    Schedule &S = g->sched;
     DevMem tri;
-    DT_TRY(dev_alloc(g->ctx, tri, g->n_tri * 12));
-    if (S.n_light) DT_HIP(hipMemcpy(tri.ptr, S.light.ptr, S.n_light * 12, hipMemcpyDeviceToDevice));
-    if (S.n_medium)
-        DT_HIP(hipMemcpy(tri.as<uint8_t>() + S.n_light * 12, S.medium.ptr, S.n_medium * 12, hipMemcpyDeviceToDevice));
-    if (S.n_heavy)
-        DT_HIP(hipMemcpy(tri.as<uint8_t>() + (S.n_light + S.n_medium) * 12, S.heavy.ptr, S.n_heavy * 12,
-                         hipMemcpyDeviceToDevice));
+    uint64_t ntri = 0, cand = 0;
+    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    if (ntri != g->n_tri) return fail(DT_EDEVICE, "triangle enumeration changed between passes");
     return make_schedule(g, tri);
 }
 
@@ -267,9 +267,11 @@ int dt_graph_stats(const dt_graph *g, dt_stats *out) {
         out->n_light_triangles = g->sched.n_light;
         out->n_heavy_triangles = g->sched.n_heavy;
         out->n_medium_triangles = g->sched.n_medium;
+        out->n_unit_triangles = g->sched.n_unit;
         out->alg_bytes = g->alg_bytes;
         out->alg_bytes_light = g->alg_bytes_light;
         out->alg_bytes_medium = g->alg_bytes_medium;
+        out->alg_bytes_unit = g->alg_bytes_unit;
         out->alg_bytes_peel = g->alg_bytes_peel;
         out->alg_bytes_triangles = g->alg_bytes_tri;
         out->tri_candidates = g->tri_candidates;
@@ -405,23 +407,16 @@ int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t 
     *count = g->n_tri;
     if (!out || cap == 0 || g->n_tri == 0) return DT_OK;
     DeviceGuard dg(g->ctx->device);
-    const Schedule &S = g->sched;
-    DevMem buf;
-    DT_TRY(dev_alloc(g->ctx, buf, g->n_tri * 12));
+    DevMem tri, buf;
+    uint64_t ntri = 0, cand = 0;
+    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    if (ntri != g->n_tri) return fail(DT_EDEVICE, "triangle enumeration changed between passes");
+    DT_TRY(dev_alloc(g->ctx, buf, ntri * 12));
     hipStream_t st = g->ctx->stream;
-    if (S.n_light)
-        k_tri_vertices<<<grid_for(S.n_light, kBlock), kBlock, 0, st>>>(S.n_light, S.light.as<uint32_t>(), g->n,
-            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(), buf.as<uint32_t>());
-    if (S.n_medium)
-        k_tri_vertices<<<grid_for(S.n_medium, kBlock), kBlock, 0, st>>>(S.n_medium, S.medium.as<uint32_t>(), g->n,
-            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(),
-            buf.as<uint32_t>() + 3 * S.n_light);
-    if (S.n_heavy)
-        k_tri_vertices<<<grid_for(S.n_heavy, kBlock), kBlock, 0, st>>>(S.n_heavy, S.heavy.as<uint32_t>(), g->n,
-            g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(),
-            buf.as<uint32_t>() + 3 * (S.n_light + S.n_medium));
+    k_tri_vertices<<<grid_for(ntri, kBlock), kBlock, 0, st>>>(ntri, tri.as<uint32_t>(), g->n,
+        g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(), buf.as<uint32_t>());
     DT_HIP(hipGetLastError());
-    uint64_t k = cap < g->n_tri ? cap : g->n_tri;
+    uint64_t k = cap < ntri ? cap : ntri;
     DT_HIP(hipMemcpyAsync(out, buf.ptr, k * 12, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
     return DT_OK;

@@ -1,7 +1,9 @@
 // Batched counting: many (graph, query) pairs in one persistent launch.
 //
 // The batch becomes one table of work items, each a bounded piece of one query's work: a run of
-// light triangles (one lane per triangle) or a run of medium-path items (one wavefront per item).
+// unit-triangle records, a run of light triangles (one lane per triangle) or a run of medium-path
+// items (one wavefront per item).  A windowed query's unit runs cover only the records whose
+// earliest time can fall in its window.
 // A persistent grid strides over the table, so graphs of very different sizes and queries with
 // different deltas and windows share the device evenly, and one launch serves the whole batch
 // whatever its composition.  Every item writes its own 8 partial sums (no atomics); a second
@@ -28,11 +30,14 @@ constexpr uint32_t kMediumGroup = 16;   // medium items per table entry
 struct BQuery {
     const uint32_t *light, *medium, *mitems, *eoff;
     const uint64_t *key;
+    const uint4 *unit;
     DQuery q;
+    UQuery u;
 };
 
 struct BItem {
-    uint32_t q, kind, b, e;   // kind 0: light triangles [b, e); 1: medium items [b, e); 2: heavy sums
+    // kind 0: light triangles [b, e); 1: medium items [b, e); 2: heavy sums; 3: unit records [b, e)
+    uint32_t q, kind, b, e;
 };
 
 __global__ void __launch_bounds__(kBB)
@@ -45,7 +50,12 @@ k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
         if (I.kind == 2) continue;
         const BQuery Q = qs[I.q];
         Acc<false> acc;
-        if (I.kind == 0) {
+        if (I.kind == 3) {
+            uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            unit_run<false, kBB>(Q.unit, I.b, I.e, Q.u, c, nullptr);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc.t[j] = c[j];
+        } else if (I.kind == 0) {
             for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri<false>(Q.light, i, Q.eoff, Q.key, Q.q, acc);
         } else {
             for (uint64_t j = I.b + wave; j < I.e; j += kBB / 64)
@@ -100,6 +110,7 @@ struct BatchRunner {
     hipGraphExec_t gexec = nullptr;
     uint64_t g_items = 0, g_q = 0;
     std::vector<std::pair<uint32_t, uint32_t>> heavy;   // (query, item slot)
+    std::vector<std::pair<uint64_t, uint64_t>> uranges; // unit records of each query
     uint64_t n_items = 0, nq = 0;
 
     int init(dt_ctx *c) {
@@ -129,12 +140,15 @@ struct BatchRunner {
     int plan(uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty, uint32_t light_chunk) {
         nq = k;
         heavy.clear();
+        const uint64_t unit_chunk = 4 * (uint64_t)light_chunk;
+        uranges.resize(k);
         uint64_t total = 0;
         for (uint64_t i = 0; i < k; ++i) {
             if (empty[i]) continue;
             const Schedule &S = graphs[i]->sched;
+            unit_range(graphs[i], qs[i], &uranges[i].first, &uranges[i].second);
             total += (S.n_light + light_chunk - 1) / light_chunk + (S.n_mitems + kMediumGroup - 1) / kMediumGroup +
-                     (S.n_heavy ? 1 : 0);
+                     (S.n_heavy ? 1 : 0) + (uranges[i].second - uranges[i].first + unit_chunk - 1) / unit_chunk;
         }
         if (total >= 0xffffffffull) return fail(DT_EOVERFLOW, "batch table too large");
         DT_TRY(host_grow(h_items, cap_h_items, total + 1));
@@ -147,8 +161,12 @@ struct BatchRunner {
             dt_graph *g = graphs[i];
             const Schedule &S = g->sched;
             h_q[i] = BQuery{S.light.as<uint32_t>(), S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
-                            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), qs[i]};
+                            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), S.unit.as<uint4>(), qs[i],
+                            unit_query(qs[i])};
             if (empty[i]) continue;
+            for (uint64_t b = uranges[i].first; b < uranges[i].second; b += unit_chunk)
+                h_items[n++] = BItem{(uint32_t)i, 3, (uint32_t)b,
+                                     (uint32_t)std::min<uint64_t>(b + unit_chunk, uranges[i].second)};
             for (uint64_t b = 0; b < S.n_light; b += light_chunk)
                 h_items[n++] = BItem{(uint32_t)i, 0, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + light_chunk, S.n_light)};
             for (uint64_t b = 0; b < S.n_mitems; b += kMediumGroup)

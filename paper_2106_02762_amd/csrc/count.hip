@@ -7,7 +7,10 @@
 // type psi(pi, rho) (Table 2).  Only the lists on the two pairs at u are ever walked; the {v,w}
 // lists are only searched (Section 5, "source vertex").
 //
-// Two paths, chosen per triangle by the scheduler:
+// Paths, chosen per triangle by the scheduler:
+//  - unit: a triangle with one temporal edge on each pair has its ordering, orientation and type
+//    fixed at build time; a query tests the record's three times against its deltas and window
+//    (Definition 1) and adds one to that type.  A pure stream of 16-byte records.
 //  - light: one lane walks every pair (x, y) of edges from the uv and uw lists (the pairwise form
 //    of Lemma 1).  With x, y fixed and ordered, the third edge z on {v,w} is first, middle or last,
 //    and each case is one key range of the vw list found by binary search; that is cells
@@ -58,6 +61,25 @@ k_medium(uint64_t n_items, const uint32_t *__restrict__ med, const uint32_t *__r
     for (uint64_t it = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; it < n_items; it += W)
         medium_item<CELLS>(med, items, it, eoff, key, q, acc, lane);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+}
+
+// unit path: block b takes a contiguous run of the records [beg, end)
+template <bool CELLS, unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_unit(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, UQuery u, int64_t *__restrict__ partial,
+       int64_t *__restrict__ cells) {
+    const uint64_t n = end - beg;
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b = beg + (uint64_t)blockIdx.x * per;
+    const uint64_t e = b + per < end ? b + per : end;
+    uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (b < e) unit_run<CELLS, BLOCK>(rec, b, e, u, c, cells);
+    if (!CELLS) {
+        int64_t t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = c[j];
+        block_store<BLOCK>(t, partial + 8 * (uint64_t)blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -345,6 +367,8 @@ __global__ void k_zero(uint64_t n, int64_t *__restrict__ p) {
 }
 
 constexpr unsigned kLightBlock = 256;
+constexpr unsigned kUnitBlock = 256;
+constexpr uint64_t kUnitPerBlock = 16384;   // records per workgroup at least (64 per thread)
 
 }  // namespace
 
@@ -400,7 +424,11 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
     const unsigned hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
     const unsigned mg = (S.n_mitems && do_medium) ? (unsigned)std::min<uint64_t>((S.n_mitems + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
-    const uint64_t n_part = (uint64_t)lg + hg + mg;
+    uint64_t ub = 0, ue = 0;
+    if (S.n_unit && (parts & 8)) unit_range(g, q, &ub, &ue);
+    const unsigned ug = ue > ub ? (unsigned)std::min<uint64_t>((ue - ub + kUnitPerBlock - 1) / kUnitPerBlock,
+                                                               (uint64_t)ctx->num_cus * 8) : 0;
+    const uint64_t n_part = (uint64_t)lg + hg + mg + ug;
     DT_TRY(ensure(ctx, sc.partials, (n_part + 1) * 8 * sizeof(int64_t)));
     int64_t *part = sc.partials.as<int64_t>();
     if (cells) {
@@ -429,6 +457,17 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
         prof_end(ctx, kProfMedium, s);
+        DT_HIP(hipGetLastError());
+    }
+    if (ug) {
+        const UQuery u = unit_query(q);
+        int64_t *up = part + 8 * ((uint64_t)lg + hg + mg);
+        prof_begin(ctx, kProfUnit, s);
+        if (cells)
+            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(ub, ue, S.unit.as<uint4>(), u, up, cells_dev);
+        else
+            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(ub, ue, S.unit.as<uint4>(), u, up, nullptr);
+        prof_end(ctx, kProfUnit, s);
         DT_HIP(hipGetLastError());
     }
     if (S.n_heavy && do_heavy) {

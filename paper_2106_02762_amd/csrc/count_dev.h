@@ -221,6 +221,56 @@ __device__ __forceinline__ void medium_item(const uint32_t *__restrict__ med, co
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// unit path: one record per triangle with one temporal edge on each pair
+// ---------------------------------------------------------------------------------------------
+// A query against unit records: the normalised deltas and the window [wlo, whi) as relative times
+// (all below 2^31 + 1 on this path; whi = 2^32 - 1 when unwindowed).
+struct UQuery {
+    uint32_t d12, d23, d13, wlo, whi;
+};
+
+inline UQuery unit_query(const DQuery &q) {
+    UQuery u;
+    u.d12 = (uint32_t)q.d12;
+    u.d23 = (uint32_t)q.d23;
+    u.d13 = (uint32_t)q.d13;
+    u.wlo = q.windowed ? (uint32_t)(q.klo >> q.shift) : 0u;
+    u.whi = q.windowed ? (uint32_t)(q.khi >> q.shift) : 0xffffffffu;
+    return u;
+}
+
+// record r = (t1, t2 - t1, t3 - t2, cell << 8 | type): Definition 1's three delta constraints and
+// the window, then one count for its type (or its cell)
+template <bool CELLS>
+__device__ __forceinline__ void unit_one(const uint4 r, const UQuery &u, uint32_t (&c)[8],
+                                         int64_t *__restrict__ cells) {
+    const uint32_t g13 = r.y + r.z;
+    const bool ok = r.y <= u.d12 && r.z <= u.d23 && g13 <= u.d13 && r.x >= u.wlo && r.x + g13 < u.whi;
+    if (CELLS) {
+        if (ok) atomicAdd((unsigned long long *)(cells + (r.w >> 8)), 1ull);
+    } else {
+        const uint32_t ty = r.w & 7u;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) c[j] += (ok && ty == j) ? 1u : 0u;
+    }
+}
+
+// records [beg, end) by the BLOCK threads of one workgroup, four loads in flight per thread
+template <bool CELLS, unsigned BLOCK>
+__device__ __forceinline__ void unit_run(const uint4 *__restrict__ rec, uint64_t beg, uint64_t end,
+                                         const UQuery &u, uint32_t (&c)[8], int64_t *__restrict__ cells) {
+    uint64_t i = beg + threadIdx.x;
+    for (; i + 3 * BLOCK < end; i += 4 * BLOCK) {
+        const uint4 r0 = rec[i], r1 = rec[i + BLOCK], r2 = rec[i + 2 * BLOCK], r3 = rec[i + 3 * BLOCK];
+        unit_one<CELLS>(r0, u, c, cells);
+        unit_one<CELLS>(r1, u, c, cells);
+        unit_one<CELLS>(r2, u, c, cells);
+        unit_one<CELLS>(r3, u, c, cells);
+    }
+    for (; i < end; i += BLOCK) unit_one<CELLS>(rec[i], u, c, cells);
+}
+
 // XCD-aware block order: blocks are dispatched round-robin over the 8 XCDs, so block b runs on
 // XCD b % 8; give each XCD a contiguous range of work so that triangles sharing u (adjacent in
 // the list) share that XCD's L2.

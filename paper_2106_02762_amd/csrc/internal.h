@@ -92,7 +92,7 @@ int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes);   // DT_ENOMEM on budget or
 
 // profiling marks around one kernel launch (no-ops unless profiling is on)
 enum ProfSlot { kProfPeel = 0, kProfRelayout, kProfTriCount, kProfTriFill, kProfLight,
-                kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium };
+                kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium, kProfUnit };
 inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
     if (c->prof) { (void)hipEventRecord(c->prof_ev[2 * slot], s); c->prof_used[slot] = true; }
 }
@@ -114,12 +114,23 @@ struct DQuery {
 
 // (uv edge, uw edge) pairs per medium-path work item
 constexpr uint32_t kMediumChunk = 4096;
+// Unit triangles: static triangles with exactly one temporal edge on each of their three pairs
+// (the common case in sparse interaction data).  Their ordering pi (Figure 3) and orientation rho
+// (Figure 4) do not depend on the query, so each is stored as one 16-byte record
+//   x = t1, y = t2 - t1, z = t3 - t2, w = (cell << 8) | (type - 1)
+// with times relative to t_min and cell = 8 (pi - 1) + (rho - 1); a query only tests its deltas
+// and window against (x, y, z).  Used when the time span is below 2^31.  Records are ordered by t1
+// so that a window selects a contiguous range; the host keeps t1 of every kUnitStride-th record.
+constexpr uint32_t kUnitStride = 4096;
+constexpr int64_t kUnitMaxSpan = (int64_t(1) << 31) - 1;
 
 // ------------------------------------------------------------------------------------------------
 // build products of one graph (all device arrays unless noted)
 // ------------------------------------------------------------------------------------------------
 struct Schedule {
-    uint64_t n_light = 0, n_medium = 0, n_heavy = 0;
+    uint64_t n_light = 0, n_medium = 0, n_heavy = 0, n_unit = 0;
+    DevMem unit;                        // uint4[n_unit] unit-triangle records
+    std::vector<uint32_t> unit_index;   // host: t1 of records 0, kUnitStride, 2 kUnitStride, ...
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
     DevMem medium;      // uint32[3 * n_medium]
     DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, first pair) work items
@@ -162,6 +173,7 @@ struct dt_graph {
     uint64_t n_tri = 0;
     unsigned __int128 sum_sigma3 = 0;
     uint64_t alg_bytes = 0, alg_bytes_light = 0, alg_bytes_medium = 0, alg_bytes_peel = 0, alg_bytes_tri = 0;
+    uint64_t alg_bytes_unit = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
     dt_tuning tuning{64, 256, 1u << 27, 0};
@@ -174,16 +186,19 @@ namespace dt {
 int load_graph(dt_graph *g, const uint32_t *src_dev, const uint32_t *dst_dev, const int64_t *t_dev);
 int peel(dt_graph *g);
 int orient(dt_graph *g);
-int enumerate_triangles(dt_graph *g, DevMem &tri);
+// every static triangle as (e_uv, e_uw, e_vw) DAG edge ids; *ntri and *cand (candidates tested)
+int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand);
 int make_schedule(dt_graph *g, DevMem &tri);
+// unit records [*b, *e) that can hold triangles inside the query's window (all when unwindowed)
+void unit_range(const dt_graph *g, const DQuery &q, uint64_t *b, uint64_t *e);
 
 // counting
 int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *empty);
-// Enqueue one count on stream s using scratch sc.  parts: bit 0 light, bit 1 medium, bit 2 heavy
-// (all = 7).  Without cells the sum of the selected parts goes to out8_dev (int64[8]); with cells
+// Enqueue one count on stream s using scratch sc.  parts: bit 0 light, bit 1 medium, bit 2 heavy,
+// bit 3 unit (all = 15).  Without cells the sum of the selected parts goes to out8_dev (int64[8]); with cells
 // the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev, Scratch &sc, unsigned parts = 7);
+                  int64_t *cells_dev, Scratch &sc, unsigned parts = 15);
 void destroy_batch_runner(BatchRunner *r);
 int make_batch_runner(dt_ctx *ctx, BatchRunner **out);
 // plan the item table of k queries and enqueue it on the runner's stream (asynchronous)
@@ -197,9 +212,11 @@ int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query
                 int64_t (*out)[8]);
 
 // library primitives (rocPRIM), out of place, enqueued on stream s; temporary storage is taken
-// from the context's budget and released before returning
+// from the context's budget and released before returning.  Sorts always start at bit 0: on this
+// rocPRIM a nonzero begin_bit gave unsorted output for mid-size inputs (its merge-sort path).
 int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
                        uint32_t *vout, size_t n, int end_bit, hipStream_t s);
+int sort_keys_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, size_t n, int end_bit, hipStream_t s);
 int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
                        uint64_t *vout, size_t n, int end_bit, hipStream_t s);
 int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);

@@ -213,7 +213,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
 
 }  // namespace
 
-int enumerate_triangles(dt_graph *g, DevMem &tri) {
+int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint64_t *cand_out) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
@@ -238,9 +238,8 @@ int enumerate_triangles(dt_graph *g, DevMem &tri) {
     DT_HIP(hipMemcpyAsync(&ntri, off.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, st));
     if (n) DT_HIP(hipMemcpyAsync(&cand, ctr.as<uint8_t>() + 8, 8, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    g->n_tri = ntri;
-    g->tri_candidates = cand;
-    g->alg_bytes_tri = 4 * (g->m_s + cand) + 12 * ntri;
+    *ntri_out = ntri;
+    *cand_out = cand;
     DT_TRY(dev_alloc(ctx, tri, ntri * 12));
     if (n && ntri) {
         DT_HIP(hipMemsetAsync(ctr.ptr, 0, 4, st));

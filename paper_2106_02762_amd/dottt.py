@@ -36,7 +36,7 @@ ENTRY_POINTS = (
     "dt_ctx_set_profiling", "dt_ctx_last_profile",
 )
 PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
-                 "heavy_count", "reduce", "medium")
+                 "heavy_count", "reduce", "medium", "unit")
 
 
 class DtError(RuntimeError):
@@ -59,9 +59,9 @@ class dt_stats(ctypes.Structure):
         ("max_out_degree", ctypes.c_uint32), ("peel_rounds", ctypes.c_uint32),
         ("sum_sigma3_lo", ctypes.c_uint64), ("sum_sigma3_hi", ctypes.c_uint64),
         ("n_light_triangles", ctypes.c_uint64), ("n_heavy_triangles", ctypes.c_uint64),
-        ("n_medium_triangles", ctypes.c_uint64),
+        ("n_medium_triangles", ctypes.c_uint64), ("n_unit_triangles", ctypes.c_uint64),
         ("alg_bytes", ctypes.c_uint64), ("alg_bytes_light", ctypes.c_uint64),
-        ("alg_bytes_medium", ctypes.c_uint64),
+        ("alg_bytes_medium", ctypes.c_uint64), ("alg_bytes_unit", ctypes.c_uint64),
         ("alg_bytes_peel", ctypes.c_uint64), ("alg_bytes_triangles", ctypes.c_uint64),
         ("tri_candidates", ctypes.c_uint64), ("heavy_slots", ctypes.c_uint64),
         ("ms_load", ctypes.c_double), ("ms_peel", ctypes.c_double),
@@ -204,7 +204,7 @@ def dt_graph_build(g):
 
 
 def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0):
-    """force_path: 0 split by the caps, 1 all light, 2 all heavy, 3 all medium."""
+    """force_path: 0 unit records and the caps, 1 all light, 2 all heavy, 3 all medium."""
     tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path))
     _check(library().dt_graph_set_tuning(g, ctypes.byref(tu)), "dt_graph_set_tuning")
 
