@@ -107,6 +107,9 @@ typedef struct {
     uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;
                                       2: every triangle heavy; 3: every triangle medium
                                       (diagnostics and tests)                                     */
+    uint32_t peel_tail;            /* the core peel hands the last peel_tail vertices to one
+                                      workgroup (default and at most 16384; 1 keeps every level
+                                      on the whole grid); read by the next dt_graph_build        */
 } dt_tuning;
 
 const char *dt_strerror(int code);

@@ -229,6 +229,8 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     if (tu->medium_pair_cap) nt.medium_pair_cap = tu->medium_pair_cap;
     if (tu->force_path > 3) return fail(DT_EINVAL, "force_path must be 0, 1, 2 or 3");
     nt.force_path = tu->force_path;
+    if (tu->peel_tail > 16384) return fail(DT_EINVAL, "peel_tail must be at most 16384");
+    if (tu->peel_tail) nt.peel_tail = tu->peel_tail;
     if (nt.heavy_chunk != 256) return fail(DT_EINVAL, "heavy_chunk must be 256 in this version");
     if (nt.medium_pair_cap > (1u << 30)) return fail(DT_EINVAL, "medium_pair_cap must be at most 2^30");
     g->tuning = nt;

@@ -176,7 +176,7 @@ struct dt_graph {
     uint64_t alg_bytes_unit = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{64, 256, 1u << 27, 0};
+    dt_tuning tuning{64, 256, 1u << 27, 0, 0};
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 

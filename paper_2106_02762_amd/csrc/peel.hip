@@ -19,9 +19,11 @@
 // block takes the same branch because all decisions use the snapshot.  A vertex is queued at most
 // once: by the level scan when its degree is <= k (no decrement runs during a scan), or by the
 // single decrement that takes its degree from k + 1 to k (degrees only fall, and a queued vertex
-// already has degree <= k, so no later decrement can see k + 1 again); the queue index is also
-// bounds-checked, and the host checks that exactly n vertices were queued.  A barrier that waits far longer than any peel could take sets an error
-// flag and lets its block go, so that a fault in this logic ends the kernel instead of hanging it.
+// already has degree <= k, so no later decrement can see k + 1 again); a vertex queued by a
+// decrement also gets a large negative degree, so that the next scans, which still list it, skip
+// it.  The queue index is also bounds-checked, and the host checks that exactly n vertices were
+// queued.  A barrier that waits far longer than any peel could take sets an error flag and lets its
+// block go, so that a fault in this logic ends the kernel instead of hanging it.
 #include "internal.h"
 
 namespace dt {
@@ -30,8 +32,16 @@ namespace {
 
 constexpr unsigned kBlock = 1024;
 constexpr unsigned kGridBlocks = 32;
+constexpr uint32_t kTail = 16384;   // most vertices the one-workgroup finish takes (16-bit ids)
+// LDS of a peel block: the one-workgroup finish keeps kTail degrees (int) and a kTail-entry queue
+// (16-bit) there; on the grid the same words stage the vertices a block queues in one round
+constexpr uint32_t kLdsWords = kTail + kTail / 2;
+constexpr uint32_t kStage = kLdsWords;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr long kSpinLimit = 1l << 26;
+// degree of a vertex queued during removal rounds: negative, and it stays negative under the
+// at most n further decrements, so a level scan never takes it again
+constexpr int kRemoved = -(1 << 30);
 
 struct PeelCtl {
     unsigned int qtail;      // vertices queued so far (positions in the ordering)
@@ -42,6 +52,7 @@ struct PeelCtl {
     unsigned int error;      // a barrier gave up waiting
     unsigned int rounds;     // removal rounds
     unsigned int kappa;      // largest level that removed a vertex
+    unsigned int ladj;       // local adjacency entries reserved at the hand-over
     unsigned int snap[2][4]; // per generation parity: qtail, n_alive2, min_deg at the release
 };
 
@@ -91,82 +102,279 @@ __device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, bool reset_scan, unsig
     snap[2] = ld_relaxed(&ctl->snap[par][2]);
 }
 
+// A vertex whose degree a removal took from k + 1 to k joins the block's staging list; the block
+// appends the list to the queue with one atomic at the end of the round (any order of the
+// vertices queued in one round is a valid ordering: each has at most k neighbours that are not
+// removed before the round ends).  A full staging list sends the rest straight to the queue.
 __device__ __forceinline__ void enqueue(uint32_t v, uint32_t k, uint32_t n, uint32_t *level,
-                                        uint32_t *queue, PeelCtl *ctl) {
+                                        uint32_t *queue, int *deg, PeelCtl *ctl, uint32_t *s_stage,
+                                        unsigned *s_cnt) {
     level[v] = k;
-    uint32_t p = atomicAdd(&ctl->qtail, 1u);
-    if (p < n) queue[p] = v;
+    __hip_atomic_store(&deg[v], kRemoved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t p = atomicAdd(s_cnt, 1u);
+    if (p < kStage) {
+        s_stage[p] = v;
+    } else {
+        const uint32_t q = atomicAdd(&ctl->qtail, 1u);
+        if (q < n) queue[q] = v;
+    }
+}
+
+__device__ __forceinline__ unsigned wave_min(unsigned x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
 }
 
 __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_t stride, uint32_t k,
                                              uint32_t n, const uint32_t *__restrict__ row,
                                              const uint32_t *__restrict__ col, int *__restrict__ deg,
                                              uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
-                                             PeelCtl *ctl) {
+                                             PeelCtl *ctl, uint32_t *s_stage, unsigned *s_cnt) {
     const uint32_t e = row[v + 1];
     for (uint32_t j = row[v] + first; j < e; j += stride) {
         const uint32_t x = col[j];
         const int old = atomicSub(&deg[x], 1);
-        if (old == (int)k + 1) enqueue(x, k, n, level, queue, ctl);
+        if (old == (int)k + 1) enqueue(x, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+    }
+}
+
+// The last vertices: one workgroup finishes the peel on the subgraph they induce, with local
+// (16-bit) vertex ids, degrees and queue in LDS and workgroup barriers between rounds.  rlist maps
+// local ids to vertices; the local adjacency of lid is lcol[lbeg[lid], lbeg[lid] + ldeg0[lid]).
+// Queue positions continue from qbase.
+__device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t rounds,
+                          const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lbeg,
+                          const uint32_t *__restrict__ ldeg0, const uint16_t *__restrict__ lcol,
+                          uint32_t *__restrict__ level, uint32_t *__restrict__ queue, PeelCtl *ctl,
+                          uint32_t *s_mem) {
+    int *s_deg = reinterpret_cast<int *>(s_mem);                    // kTail
+    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_mem + kTail);    // kTail
+    __shared__ unsigned s_qt, s_keep, s_min;
+    const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid / 64;
+    constexpr unsigned kWaves = kBlock / 64;
+    const uint64_t below = (1ull << lane) - 1;
+    for (uint32_t l = tid; l < R; l += kBlock) s_deg[l] = (int)ldeg0[l];
+    if (tid == 0) s_qt = 0;
+    uint32_t h = 0, t = 0;
+    // a vertex whose local degree a removal took from k + 1 to k
+    auto take = [&](uint32_t x, uint32_t kk) {
+        s_deg[x] = kRemoved;
+        const uint32_t p = atomicAdd(&s_qt, 1u);
+        if (p < R) {
+            s_q[p] = (uint16_t)x;
+            const uint32_t v = rlist[x];
+            level[v] = kk;
+            queue[qbase + p] = v;
+        }
+    };
+    while (true) {
+        __syncthreads();
+        if (tid == 0) {
+            s_keep = 0;
+            s_min = 0xffffffffu;
+        }
+        __syncthreads();
+        const uint32_t level_start = t;
+        // level scan over all local vertices (removed ones hold negative degrees)
+        for (uint32_t b0 = wave * 64; b0 < R; b0 += kWaves * 64) {
+            const uint32_t l = b0 + lane;
+            const int d = l < R ? s_deg[l] : -1;
+            const bool tk = d >= 0 && d <= (int)k, kp = d > (int)k;
+            const uint64_t mt = __ballot(tk), mk = __ballot(kp);
+            uint32_t qb = 0;
+            if (lane == 0 && mt) qb = atomicAdd(&s_qt, (unsigned)__popcll(mt));
+            qb = __shfl(qb, 0, 64);
+            if (tk) {
+                const uint32_t p = qb + (uint32_t)__popcll(mt & below);
+                s_deg[l] = kRemoved;
+                if (p < R) {
+                    s_q[p] = (uint16_t)l;
+                    const uint32_t v = rlist[l];
+                    level[v] = k;
+                    queue[qbase + p] = v;
+                }
+            }
+            const unsigned md = wave_min(kp ? (unsigned)d : 0xffffffffu);
+            if (lane == 0 && mk) {
+                atomicAdd(&s_keep, (unsigned)__popcll(mk));
+                atomicMin(&s_min, md);
+            }
+        }
+        __syncthreads();
+        t = s_qt;
+        const uint32_t keep = s_keep, md = s_min;
+        if (keep == 0) h = t;   // every remaining vertex is queued: nothing left to update
+        // rounds: remove s_q[h, t)
+        while (h < t) {
+            const uint32_t f = t - h;
+            uint32_t i0, first, stride, step;
+            if (f >= kWaves) {
+                i0 = h + wave; first = lane; stride = 64; step = kWaves;
+            } else {
+                const uint32_t per = kWaves / f;
+                i0 = h + wave / per; first = (wave % per) * 64 + lane; stride = per * 64; step = f;
+                if (wave / per >= f) i0 = t;
+            }
+            for (uint32_t i = i0; i < t; i += step) {
+                const uint32_t x = s_q[i];
+                const uint32_t e = lbeg[x] + ldeg0[x];
+                uint32_t j = lbeg[x] + first;
+                for (; j + 3 * stride < e; j += 4 * stride) {
+                    const uint32_t y0 = lcol[j], y1 = lcol[j + stride], y2 = lcol[j + 2 * stride],
+                                   y3 = lcol[j + 3 * stride];
+                    if (atomicSub(&s_deg[y0], 1) == (int)k + 1) take(y0, k);
+                    if (atomicSub(&s_deg[y1], 1) == (int)k + 1) take(y1, k);
+                    if (atomicSub(&s_deg[y2], 1) == (int)k + 1) take(y2, k);
+                    if (atomicSub(&s_deg[y3], 1) == (int)k + 1) take(y3, k);
+                }
+                for (; j < e; j += stride)
+                    if (atomicSub(&s_deg[lcol[j]], 1) == (int)k + 1) take(lcol[j], k);
+            }
+            ++rounds;
+            __syncthreads();
+            h = t;
+            t = s_qt;
+            __syncthreads();
+        }
+        if (t >= R) break;
+        uint32_t next = k + 1;
+        if (t == level_start && md != 0xffffffffu && md > next) next = md;
+        k = next;
+        if (k > R + qbase + 1) {   // cannot happen, as in the grid loop
+            if (tid == 0) atomicOr(&ctl->error, 2u);
+            break;
+        }
+    }
+    if (tid == 0) {
+        __hip_atomic_store(&ctl->qtail, qbase + (t < R ? t : R), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctl->kappa = k;
+        ctl->rounds = rounds;
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict__ col,
        int *__restrict__ deg, uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
-       uint32_t *__restrict__ alive_a, uint32_t *__restrict__ alive_b, PeelCtl *__restrict__ ctl) {
+       uint32_t *__restrict__ alive_a, uint32_t *__restrict__ alive_b, uint32_t *__restrict__ loc,
+       uint32_t *__restrict__ rlist, uint32_t *__restrict__ lbeg, uint32_t *__restrict__ ldeg0,
+       uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, PeelCtl *__restrict__ ctl) {
     const unsigned nblk = gridDim.x;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t gsize = nblk * kBlock;
     const uint32_t gwave = gtid / 64, nwaves = gsize / 64, lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
     unsigned snap[3];
+    __shared__ __attribute__((aligned(16))) uint32_t s_mem[kLdsWords];
+    __shared__ unsigned s_cnt, s_base;
 
     // the host cleared the control block; initialise per-vertex state
     for (uint32_t v = gtid; v < n; v += gsize) {
         deg[v] = (int)(row[v + 1] - row[v]);
         level[v] = kUnset;
         alive_a[v] = v;
+        loc[v] = kUnset;
     }
     grid_barrier(ctl, nblk, true, snap);
 
-    uint32_t k = 0, head = 0, n_alive = n, prev_tail = 0, rounds = 0;
+    uint32_t k = 0, head = 0, tail = 0, n_alive = n, prev_tail = 0, rounds = 0;
     uint32_t *cur = alive_a, *nxt = alive_b;
-    while (true) {
-        // level scan: queue every remaining vertex of degree <= k, keep the others
-        for (uint32_t i = gtid; i < n_alive; i += gsize) {
-            const uint32_t v = cur[i];
-            if (ld_relaxed(&level[v]) != kUnset) continue;
-            const int d = ld_relaxed(&deg[v]);
-            if (d <= (int)k) {
-                enqueue(v, k, n, level, queue, ctl);
-            } else {
-                nxt[atomicAdd(&ctl->n_alive2, 1u)] = v;
-                atomicMin(&ctl->min_deg, (unsigned)d);
+    bool done = false;
+    // here every queued vertex has been removed: n - tail vertices remain
+    while (n - tail > tail_cap) {
+        // level scan: queue every remaining vertex of degree <= k, keep the others.  Each
+        // wavefront takes a contiguous segment, counts its picks, reserves room in both lists with
+        // one atomic each, then writes its picks in order (no degree changes during a scan), so
+        // both lists keep the roughly ascending vertex order of the previous one and the degree
+        // reads of the next scan stay coalesced.
+        {
+            const uint32_t seg = ((n_alive + nwaves - 1) / nwaves + 63) & ~63u;
+            const uint32_t sb = gwave * seg < n_alive ? gwave * seg : n_alive;
+            const uint32_t se = sb + seg < n_alive ? sb + seg : n_alive;
+            uint32_t ct = 0, ck = 0;
+            unsigned mdl = 0xffffffffu;
+            for (uint32_t b0 = sb; b0 < se; b0 += 64) {
+                const uint32_t i = b0 + lane;
+                const int d = i < se ? ld_relaxed(&deg[cur[i]]) : -1;
+                const bool keep = d > (int)k;
+                ct += (uint32_t)__popcll(__ballot(d >= 0 && d <= (int)k));   // d < 0: queued
+                ck += (uint32_t)__popcll(__ballot(keep));
+                mdl = keep && (unsigned)d < mdl ? (unsigned)d : mdl;
+            }
+            mdl = wave_min(mdl);
+            uint32_t qb = 0, kb = 0;
+            if (lane == 0) {
+                if (ct) qb = atomicAdd(&ctl->qtail, ct);
+                if (ck) kb = atomicAdd(&ctl->n_alive2, ck);
+                if (mdl != 0xffffffffu) atomicMin(&ctl->min_deg, mdl);
+            }
+            qb = __shfl(qb, 0, 64);
+            kb = __shfl(kb, 0, 64);
+            if (ct | ck) {
+                for (uint32_t b0 = sb; b0 < se; b0 += 64) {
+                    const uint32_t i = b0 + lane;
+                    uint32_t v = 0;
+                    int d = -1;
+                    if (i < se) {
+                        v = cur[i];
+                        d = ld_relaxed(&deg[v]);
+                    }
+                    const bool take = d >= 0 && d <= (int)k, keep = d > (int)k;
+                    const uint64_t mt = __ballot(take), mk = __ballot(keep);
+                    if (take) {
+                        level[v] = k;
+                        const uint32_t p = qb + (uint32_t)__popcll(mt & below);
+                        if (p < n) queue[p] = v;
+                    }
+                    if (keep) nxt[kb + (uint32_t)__popcll(mk & below)] = v;
+                    qb += (uint32_t)__popcll(mt);
+                    kb += (uint32_t)__popcll(mk);
+                }
             }
         }
         grid_barrier(ctl, nblk, true, snap);
-        uint32_t tail = snap[0];
+        tail = snap[0];
         const uint32_t na2 = snap[1], md = snap[2];
+        // no survivors: every remaining vertex is queued at this level, and removing them can
+        // queue nothing more
+        if (na2 == 0) head = tail;
         // rounds: remove queue[head, tail).  A frontier of at least one vertex per wavefront is
         // split by vertex; a smaller one gives each vertex an equal share of the wavefronts.
         while (head < tail) {
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
             const uint32_t f = tail - head;
             if (f >= nwaves) {
                 for (uint32_t i = head + gwave; i < tail; i += nwaves)
-                    remove_edges(queue[i], lane, 64, k, n, row, col, deg, level, queue, ctl);
+                    remove_edges(queue[i], lane, 64, k, n, row, col, deg, level, queue, ctl, s_mem, &s_cnt);
             } else {
                 const uint32_t per = nwaves / f;
                 const uint32_t i = gwave / per, sub = gwave % per;
                 if (i < f)
                     remove_edges(queue[head + i], sub * 64 + lane, per * 64, k, n, row, col, deg,
-                                 level, queue, ctl);
+                                 level, queue, ctl, s_mem, &s_cnt);
+            }
+            // append the block's staged vertices to the queue
+            __syncthreads();
+            const uint32_t c = s_cnt < kStage ? s_cnt : kStage;
+            if (threadIdx.x == 0) s_base = c ? atomicAdd(&ctl->qtail, c) : 0u;
+            __syncthreads();
+            for (uint32_t x = threadIdx.x; x < c; x += kBlock) {
+                const uint32_t p = s_base + x;
+                if (p < n) queue[p] = s_mem[x];
             }
             ++rounds;
             grid_barrier(ctl, nblk, false, snap);
             head = tail;
             tail = snap[0];
         }
-        if (tail >= n || ld_relaxed(&ctl->error)) break;
+        if (tail >= n || ld_relaxed(&ctl->error)) {
+            done = true;
+            break;
+        }
         // every survivor now has degree > k; when this level removed nothing, no degree changed
         // since the scan, so the smallest survivor degree is the next level that removes anything
         uint32_t next = k + 1;
@@ -175,6 +383,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         k = next;
         if (k > n + 1) {   // cannot happen: some vertex is removed at the smallest survivor degree
             if (gtid == 0) atomicOr(&ctl->error, 2u);
+            done = true;
             break;
         }
         n_alive = na2;
@@ -182,10 +391,78 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         cur = nxt;
         nxt = t;
     }
-    if (gtid == 0) {
-        ctl->kappa = k;
-        ctl->rounds = rounds;
+    if (done) {
+        if (gtid == 0) {
+            ctl->kappa = k;
+            ctl->rounds = rounds;
+        }
+        return;
     }
+    // Hand over to one workgroup.  Every remaining vertex is in cur with its degree (the number
+    // of its remaining neighbours, since every queued vertex has been removed): give it a local
+    // id and reserve that many entries of the local adjacency, then write its remaining
+    // neighbours' local ids there.
+    for (uint32_t b0 = gwave * 64; b0 < n_alive; b0 += nwaves * 64) {
+        const uint32_t i = b0 + lane;
+        uint32_t v = 0;
+        int d = -1;
+        if (i < n_alive) {
+            v = cur[i];
+            d = ld_relaxed(&deg[v]);
+        }
+        const bool live = d >= 0;
+        const uint64_t ml = __ballot(live);
+        // exclusive prefix of the live degrees within the wavefront
+        uint32_t inc = live ? (uint32_t)d : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= (unsigned)o) inc += y;
+        }
+        const uint32_t tot = __shfl(inc, 63, 64);
+        uint32_t lb = 0, ab = 0;
+        if (lane == 0 && ml) {
+            lb = atomicAdd(&ctl->n_alive2, (unsigned)__popcll(ml));
+            ab = atomicAdd(&ctl->ladj, tot);
+        }
+        lb = __shfl(lb, 0, 64);
+        ab = __shfl(ab, 0, 64);
+        if (live) {
+            const uint32_t lid = lb + (uint32_t)__popcll(ml & below);
+            const uint64_t off = (uint64_t)ab + inc - (uint32_t)d;
+            if (lid < kTail && off + (uint32_t)d <= lcol_cap) {
+                rlist[lid] = v;
+                loc[v] = lid;
+                lbeg[lid] = (uint32_t)off;
+                ldeg0[lid] = (uint32_t)d;
+            } else {
+                atomicOr(&ctl->error, 4u);
+            }
+        }
+    }
+    grid_barrier(ctl, nblk, true, snap);
+    const uint32_t R = snap[1];
+    if (R != n - tail || R > kTail || ld_relaxed(&ctl->error)) {
+        if (gtid == 0) atomicOr(&ctl->error, 4u);
+        return;
+    }
+    for (uint32_t l = gwave; l < R; l += nwaves) {
+        const uint32_t v = rlist[l], b = lbeg[l], d = ldeg0[l];
+        const uint32_t e = row[v + 1];
+        uint32_t c = 0;
+        for (uint32_t j0 = row[v]; j0 < e; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const uint32_t lx = j < e ? loc[col[j]] : kUnset;
+            const uint64_t m = __ballot(lx != kUnset);
+            const uint32_t p = c + (uint32_t)__popcll(m & below);
+            if (lx != kUnset && p < d) lcol[b + p] = (uint16_t)lx;
+            c += (uint32_t)__popcll(m);
+        }
+        if (lane == 0 && c != d) atomicOr(&ctl->error, 4u);
+    }
+    grid_barrier(ctl, nblk, false, snap);
+    if (blockIdx.x != 0 || ld_relaxed(&ctl->error)) return;
+    peel_tail(R, tail, k, rounds, rlist, lbeg, ldeg0, lcol, level, queue, ctl, s_mem);
 }
 
 __global__ void k_finish(uint32_t n, const uint32_t *__restrict__ queue, uint32_t *__restrict__ rank) {
@@ -199,7 +476,7 @@ int peel(dt_graph *g) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
-    DevMem deg, alive, alive2, ctlm;
+    DevMem deg, alive, alive2, ctlm, loc, rlist, lbeg, ldeg0, lcol;
     DT_TRY(dev_alloc(ctx, deg, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive2, (uint64_t)n * 4));
@@ -207,6 +484,15 @@ int peel(dt_graph *g) {
     DT_TRY(dev_alloc(ctx, g->order, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, g->rank, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, ctlm, sizeof(PeelCtl)));
+    // the one-workgroup finish: at most tail_cap vertices, their adjacency within 2 m_static
+    // entries and below tail_cap (tail_cap - 1) as well
+    const uint32_t tail_cap = std::min<uint32_t>(g->tuning.peel_tail ? g->tuning.peel_tail : kTail, kTail);
+    const uint64_t lcol_cap = std::min<uint64_t>(2ull * g->m_s, (uint64_t)tail_cap * (tail_cap - 1));
+    DT_TRY(dev_alloc(ctx, loc, (uint64_t)n * 4));
+    DT_TRY(dev_alloc(ctx, rlist, (uint64_t)tail_cap * 4));
+    DT_TRY(dev_alloc(ctx, lbeg, (uint64_t)tail_cap * 4));
+    DT_TRY(dev_alloc(ctx, ldeg0, (uint64_t)tail_cap * 4));
+    DT_TRY(dev_alloc(ctx, lcol, (lcol_cap + 1) * 2));
     if (n == 0) {
         g->kappa = 0;
         g->peel_rounds = 0;
@@ -226,14 +512,20 @@ int peel(dt_graph *g) {
     uint32_t *aa = alive.as<uint32_t>(), *ab = alive2.as<uint32_t>();
     PeelCtl *ctl = ctlm.as<PeelCtl>();
     uint32_t nn = n;
-    void *args[] = {&nn, &row, &col, &degp, &level, &queue, &aa, &ab, &ctl};
+    uint32_t *locp = loc.as<uint32_t>(), *rl = rlist.as<uint32_t>(), *lb = lbeg.as<uint32_t>(),
+             *ld = ldeg0.as<uint32_t>();
+    uint16_t *lc = lcol.as<uint16_t>();
+    uint64_t lcap = lcol_cap;
+    uint32_t tcap = tail_cap;
+    void *args[] = {&nn, &row, &col, &degp, &level, &queue, &aa, &ab, &locp, &rl, &lb, &ld, &lc, &lcap, &tcap, &ctl};
     prof_begin(ctx, kProfPeel, st);
     DT_HIP(hipLaunchCooperativeKernel((const void *)k_peel, dim3(grid), dim3(kBlock), args, 0, st));
     prof_end(ctx, kProfPeel, st);
     PeelCtl h{};
     DT_HIP(hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    if (h.error) return fail(DT_EDEVICE, "core peel barrier timed out");
+    if (h.error & 1u) return fail(DT_EDEVICE, "core peel barrier timed out");
+    if (h.error) return fail(DT_EDEVICE, "core peel failed its consistency checks (code %u)", h.error);
     if (h.qtail != n) return fail(DT_EDEVICE, "core peel queued %u of %u vertices", h.qtail, n);
     g->kappa = h.kappa;
     g->peel_rounds = h.rounds;

@@ -72,7 +72,8 @@ class dt_stats(ctypes.Structure):
 
 class dt_tuning(ctypes.Structure):
     _fields_ = [("light_pair_cap", ctypes.c_uint32), ("heavy_chunk", ctypes.c_uint32),
-                ("medium_pair_cap", ctypes.c_uint32), ("force_path", ctypes.c_uint32)]
+                ("medium_pair_cap", ctypes.c_uint32), ("force_path", ctypes.c_uint32),
+                ("peel_tail", ctypes.c_uint32)]
 
 
 class dt_server_cfg(ctypes.Structure):
@@ -203,9 +204,12 @@ def dt_graph_build(g):
     _check(library().dt_graph_build(g), "dt_graph_build")
 
 
-def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0):
-    """force_path: 0 unit records and the caps, 1 all light, 2 all heavy, 3 all medium."""
-    tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path))
+def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0,
+                        peel_tail=0):
+    """force_path: 0 unit records and the caps, 1 all light, 2 all heavy, 3 all medium.
+    peel_tail: vertices the core peel leaves to one workgroup (next build; 0 keeps the setting)."""
+    tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path),
+                   int(peel_tail))
     _check(library().dt_graph_set_tuning(g, ctypes.byref(tu)), "dt_graph_set_tuning")
 
 

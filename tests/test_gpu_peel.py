@@ -1,0 +1,89 @@
+"""GPU parity of the core peel (the degeneracy ordering of Section 3) in its three regimes: the
+whole peel on the cooperative grid (peel_tail = 1), the whole peel in one workgroup (graphs of at
+most 16384 vertices), and the grid handing its last vertices to one workgroup.  Core numbers must
+equal the oracle's exactly (they are unique, unlike the ordering), the ordering must be a
+permutation, and every vertex must have at most core(v) neighbours after it in the ordering (the
+out-degree bound Theorem 1 uses)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import INF, say
+
+pytestmark = pytest.mark.gpu
+
+import paper_2106_02762_amd as dt  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dt.dt_ctx_create(0)
+    yield c
+    dt.dt_ctx_destroy(c)
+
+
+def _static_pairs(g):
+    a = np.minimum(g.src, g.dst).astype(np.int64)
+    b = np.maximum(g.src, g.dst).astype(np.int64)
+    keep = a != b
+    key = np.unique(a[keep] * g.n + b[keep])
+    return key // g.n, key % g.n
+
+
+def _check(ctx, g, peel_tail, ocore, pairs, query):
+    say("peel", g.name, "peel_tail", peel_tail)
+    h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
+    try:
+        dt.dt_graph_set_tuning(h, peel_tail=peel_tail)
+        dt.dt_graph_build(h)
+        st = dt.dt_graph_stats(h)
+        core, rank = dt.dt_graph_order(h, g.n)
+        assert (core == ocore).all(), (g.name, peel_tail, int((core != ocore).sum()))
+        assert st["degeneracy"] == int(ocore.max())
+        assert np.array_equal(np.sort(rank), np.arange(g.n, dtype=rank.dtype))
+        u, v = pairs
+        first = np.where(rank[u] < rank[v], u, v)   # each pair points away from this endpoint
+        outdeg = np.bincount(first, minlength=g.n)
+        assert (outdeg <= core).all(), (g.name, peel_tail)
+        assert st["max_out_degree"] == int(outdeg.max())
+        return dt.dt_count(h, *query)
+    finally:
+        dt.dt_graph_free(h)
+
+
+@pytest.mark.parametrize("name", ["scaled", "batch5", "plain_tiny", "tiny"])
+def test_peel_regimes_match_oracle(ctx, name):
+    if name == "scaled":
+        g = synth.plain_full(n=60_000, ms=800_000)       # grid, then one workgroup
+        tails = [0, 1, 100, 16384]
+        q = (3600, 3600, 3600, dt.INT64_MIN, INF)
+    elif name == "batch5":
+        g = synth.batch_graph(5)                          # n = 48,229
+        tails = [0, 1, 5000]
+        q = (3600, 1800, 3600, dt.INT64_MIN, INF)
+    elif name == "plain_tiny":
+        g = synth.plain_tiny()                            # n = 1,000: one workgroup throughout
+        tails = [0, 1, 10]
+        q = (10**5, 5 * 10**4, 8 * 10**4, dt.INT64_MIN, INF)
+    else:
+        g = synth.tiny_multigraph(3, n=9, m=60, t_range=5)
+        tails = [0, 1, 2]
+        q = (3, 2, 2, dt.INT64_MIN, INF)
+    _, ocore = oracle.stats(g.n, g.src, g.dst, g.t, core=True)
+    pairs = _static_pairs(g)
+    want = oracle.count(g.n, g.src, g.dst, g.t, *q)
+    for pt in tails:
+        got = _check(ctx, g, pt, ocore, pairs, q)
+        assert (got == want).all(), (name, pt, got, want)
+
+
+def test_peel_tail_is_validated(ctx):
+    g = synth.seed_graph()
+    h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
+    try:
+        with pytest.raises(dt.DtError) as e:
+            dt.dt_graph_set_tuning(h, peel_tail=16385)
+        assert e.value.code == dt.DT_EINVAL
+    finally:
+        dt.dt_graph_free(h)
