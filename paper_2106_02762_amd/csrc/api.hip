@@ -141,7 +141,7 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
         return fail(DT_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
     }
     if (c->num_cus <= 0) c->num_cus = 256;
-    int rc = dev_alloc(c, c->out8, 64 * sizeof(int64_t));
+    int rc = dev_alloc(c, c->out8, 64 * sizeof(int64_t), false);
     if (rc != DT_OK) {
         (void)hipStreamDestroy(c->stream);
         (void)hipHostFree(c->pinned_out);
@@ -162,6 +162,7 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     ctx->scratch.partials.reset();
     ctx->scratch.heavy_vals.reset();
     ctx->out8.reset();
+    pool_trim(ctx, 0);
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
     for (auto &e : ctx->prof_ev)
         if (e) (void)hipEventDestroy(e);

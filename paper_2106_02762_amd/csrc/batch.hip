@@ -187,18 +187,18 @@ struct BatchRunner {
         bool regrow = false;
         if (!d_items.ptr || cap_items < n_items + 1) {
             cap_items = n_items + n_items / 2 + 64;
-            DT_TRY(dev_alloc(ctx, d_items, cap_items * sizeof(BItem)));
-            DT_TRY(dev_alloc(ctx, d_part, cap_items * 8 * sizeof(int64_t)));
+            DT_TRY(dev_alloc(ctx, d_items, cap_items * sizeof(BItem), false));
+            DT_TRY(dev_alloc(ctx, d_part, cap_items * 8 * sizeof(int64_t), false));
             regrow = true;
         }
         if (!d_q.ptr || cap_q < nq + 1) {
             cap_q = nq + nq / 2 + 64;
-            DT_TRY(dev_alloc(ctx, d_q, cap_q * sizeof(BQuery)));
-            DT_TRY(dev_alloc(ctx, d_qfirst, (cap_q + 1) * 4));
-            DT_TRY(dev_alloc(ctx, d_out, cap_q * 8 * sizeof(int64_t)));
+            DT_TRY(dev_alloc(ctx, d_q, cap_q * sizeof(BQuery), false));
+            DT_TRY(dev_alloc(ctx, d_qfirst, (cap_q + 1) * 4, false));
+            DT_TRY(dev_alloc(ctx, d_out, cap_q * 8 * sizeof(int64_t), false));
             regrow = true;
         }
-        if (!d_counts.ptr) DT_TRY(dev_alloc(ctx, d_counts, 256));
+        if (!d_counts.ptr) DT_TRY(dev_alloc(ctx, d_counts, 256, false));
         if (regrow || cap_h_out < 8 * cap_q) {
             DT_TRY(host_grow(h_out, cap_h_out, 8 * cap_q));
             if (gexec) (void)hipGraphExecDestroy(gexec);

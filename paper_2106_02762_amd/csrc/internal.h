@@ -43,10 +43,15 @@ void clear_error();
 // context and device memory with a budget
 // ------------------------------------------------------------------------------------------------
 // A device allocation owned by a context; released by reset() or the destructor.
+// Device memory owned by one object.  A pooled block goes back to its context's cache when
+// released and may be handed to the next allocation at once: pooled memory must only be used in
+// stream order on the context's own stream (build products and build temporaries).  Memory used
+// on other streams (batch runners, scratch shared with foreign streams) is not pooled.
 struct DevMem {
     dt_ctx *ctx = nullptr;
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool pooled = false;
     DevMem() = default;
     DevMem(const DevMem &) = delete;
     DevMem &operator=(const DevMem &) = delete;
@@ -84,11 +89,17 @@ struct dt_ctx {
     bool prof = false;
     hipEvent_t prof_ev[2 * DT_PROFILE_SLOTS] = {};
     bool prof_used[DT_PROFILE_SLOTS] = {};
+    // cache of released pooled blocks (size -> address); counted in `used`
+    std::mutex pool_mu;
+    std::multimap<size_t, void *> pool;
+    uint64_t pool_bytes = 0;
 };
 
 namespace dt {
 
-int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes);   // DT_ENOMEM on budget or HIP failure
+// DT_ENOMEM on budget or HIP failure; see DevMem for when `pooled` is allowed
+int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes, bool pooled = true);
+void pool_trim(dt_ctx *ctx, uint64_t keep_bytes);   // free cached blocks down to keep_bytes
 
 // profiling marks around one kernel launch (no-ops unless profiling is on)
 enum ProfSlot { kProfPeel = 0, kProfRelayout, kProfTriCount, kProfTriFill, kProfLight,
@@ -99,7 +110,7 @@ inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
 inline void prof_end(dt_ctx *c, int slot, hipStream_t s) {
     if (c->prof) (void)hipEventRecord(c->prof_ev[2 * slot + 1], s);
 }
-int ensure(dt_ctx *ctx, DevMem &m, size_t bytes);      // grow-only
+int ensure(dt_ctx *ctx, DevMem &m, size_t bytes);   // grow-only, not pooled
 
 // ------------------------------------------------------------------------------------------------
 // query as the kernels see it: deltas rewritten and clamped, window in key space

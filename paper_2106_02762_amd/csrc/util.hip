@@ -27,14 +27,50 @@ void clear_error() { g_last_error.clear(); }
 
 const char *last_error() { return g_last_error.c_str(); }
 
+namespace {
+
+// most bytes the cache may hold: half the budget, or 32 GiB without one
+uint64_t pool_cap(const dt_ctx *ctx) { return ctx->budget ? ctx->budget / 2 : (32ull << 30); }
+
+void pool_put(dt_ctx *ctx, void *p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    ctx->pool.emplace(bytes, p);
+    ctx->pool_bytes += bytes;
+    while (ctx->pool_bytes > pool_cap(ctx) && !ctx->pool.empty()) {   // largest first
+        auto it = std::prev(ctx->pool.end());
+        (void)hipFree(it->second);
+        ctx->used -= it->first;
+        ctx->pool_bytes -= it->first;
+        ctx->pool.erase(it);
+    }
+}
+
+}  // namespace
+
+void pool_trim(dt_ctx *ctx, uint64_t keep_bytes) {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    while (ctx->pool_bytes > keep_bytes && !ctx->pool.empty()) {
+        auto it = std::prev(ctx->pool.end());
+        (void)hipFree(it->second);
+        ctx->used -= it->first;
+        ctx->pool_bytes -= it->first;
+        ctx->pool.erase(it);
+    }
+}
+
 void DevMem::reset() {
     if (ptr) {
-        (void)hipFree(ptr);
-        if (ctx) ctx->used -= bytes;
+        if (pooled && ctx) {
+            pool_put(ctx, ptr, bytes);
+        } else {
+            (void)hipFree(ptr);
+            if (ctx) ctx->used -= bytes;
+        }
     }
     ctx = nullptr;
     ptr = nullptr;
     bytes = 0;
+    pooled = false;
 }
 
 DevMem &DevMem::operator=(DevMem &&o) noexcept {
@@ -43,22 +79,47 @@ DevMem &DevMem::operator=(DevMem &&o) noexcept {
         ctx = o.ctx;
         ptr = o.ptr;
         bytes = o.bytes;
+        pooled = o.pooled;
         o.ctx = nullptr;
         o.ptr = nullptr;
         o.bytes = 0;
+        o.pooled = false;
     }
     return *this;
 }
 
-int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes) {
+int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes, bool pooled) {
     m.reset();
     if (bytes == 0) bytes = 256;   // a valid pointer even for empty arrays
     bytes = (bytes + 255) & ~size_t(255);
+    if (pooled) {
+        // best fit among cached blocks, wasting at most an eighth plus 2 MiB
+        std::lock_guard<std::mutex> lk(ctx->pool_mu);
+        auto it = ctx->pool.lower_bound(bytes);
+        if (it != ctx->pool.end() && it->first <= bytes + bytes / 8 + (2u << 20)) {
+            m.ctx = ctx;
+            m.ptr = it->second;
+            m.bytes = it->first;
+            m.pooled = true;
+            ctx->pool_bytes -= it->first;
+            ctx->pool.erase(it);
+            return DT_OK;
+        }
+    }
+    if (ctx->budget && ctx->used.load() + bytes > ctx->budget) {
+        const uint64_t over = ctx->used.load() + bytes - ctx->budget;
+        pool_trim(ctx, ctx->pool_bytes > over ? ctx->pool_bytes - over : 0);
+    }
     if (ctx->budget && ctx->used.load() + bytes > ctx->budget)
         return fail(DT_ENOMEM, "device allocation of %zu bytes exceeds the budget (%llu used of %llu)",
                     bytes, (unsigned long long)ctx->used.load(), (unsigned long long)ctx->budget);
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {   // cached blocks may be what is missing
+        (void)hipGetLastError();
+        pool_trim(ctx, 0);
+        e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(DT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -66,13 +127,14 @@ int dev_alloc(dt_ctx *ctx, DevMem &m, size_t bytes) {
     m.ctx = ctx;
     m.ptr = p;
     m.bytes = bytes;
+    m.pooled = pooled;
     ctx->used += bytes;
     return DT_OK;
 }
 
 int ensure(dt_ctx *ctx, DevMem &m, size_t bytes) {
     if (m.ptr && m.bytes >= bytes) return DT_OK;
-    return dev_alloc(ctx, m, bytes + bytes / 4);
+    return dev_alloc(ctx, m, bytes + bytes / 4, false);
 }
 
 double now_ms() {
