@@ -130,9 +130,9 @@ constexpr uint32_t kMediumChunk = 4096;
 // (Figure 4) do not depend on the query, so each is stored as one 16-byte record
 //   x = t1, y = t2 - t1, z = t3 - t2, w = (cell << 8) | (type - 1)
 // with times relative to t_min and cell = 8 (pi - 1) + (rho - 1); a query only tests its deltas
-// and window against (x, y, z).  Used when the time span is below 2^31.  Records are ordered by t1
-// so that a window selects a contiguous range; the host keeps t1 of every kUnitStride-th record.
-constexpr uint32_t kUnitStride = 4096;
+// and window against (x, y, z).  Used when the time span is below 2^31.  Records are grouped by
+// t1 bucket (t1 >> unit_shift, at most 2^16 buckets) so that a window selects a contiguous range;
+// the host keeps the bucket starts.
 constexpr int64_t kUnitMaxSpan = (int64_t(1) << 31) - 1;
 
 // ------------------------------------------------------------------------------------------------
@@ -141,7 +141,8 @@ constexpr int64_t kUnitMaxSpan = (int64_t(1) << 31) - 1;
 struct Schedule {
     uint64_t n_light = 0, n_medium = 0, n_heavy = 0, n_unit = 0;
     DevMem unit;                        // uint4[n_unit] unit-triangle records
-    std::vector<uint32_t> unit_index;   // host: t1 of records 0, kUnitStride, 2 kUnitStride, ...
+    int unit_shift = 0;                 // t1 bucket of a record: t1 >> unit_shift
+    std::vector<uint32_t> unit_index;   // host: first record of each t1 bucket, then n_unit
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
     DevMem medium;      // uint32[3 * n_medium]
     DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, first pair) work items
@@ -227,7 +228,6 @@ int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query
 // rocPRIM a nonzero begin_bit gave unsorted output for mid-size inputs (its merge-sort path).
 int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint32_t *vin,
                        uint32_t *vout, size_t n, int end_bit, hipStream_t s);
-int sort_keys_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, size_t n, int end_bit, hipStream_t s);
 int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
                        uint64_t *vout, size_t n, int end_bit, hipStream_t s);
 int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);

@@ -33,9 +33,11 @@ namespace {
 constexpr unsigned kBlock = 1024;
 constexpr unsigned kGridBlocks = 32;
 constexpr uint32_t kTail = 16384;   // most vertices the one-workgroup finish takes (16-bit ids)
-// LDS of a peel block: the one-workgroup finish keeps kTail degrees (int) and a kTail-entry queue
-// (16-bit) there; on the grid the same words stage the vertices a block queues in one round
-constexpr uint32_t kLdsWords = kTail + kTail / 2;
+// LDS of a peel block.  The one-workgroup finish keeps there the local CSR rows (kTail + 1
+// words), the degrees (16-bit, two per word), the queue of local ids (16-bit) and a removed-vertex
+// bitmap; on the grid the same words stage the vertices a block queues in one round.
+constexpr uint32_t kRowWords = kTail + 1, kDegWords = kTail / 2, kQWords = kTail / 2, kRemWords = kTail / 32;
+constexpr uint32_t kLdsWords = kRowWords + kDegWords + kQWords + kRemWords;
 constexpr uint32_t kStage = kLdsWords;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr long kSpinLimit = 1l << 26;
@@ -52,7 +54,8 @@ struct PeelCtl {
     unsigned int error;      // a barrier gave up waiting
     unsigned int rounds;     // removal rounds
     unsigned int kappa;      // largest level that removed a vertex
-    unsigned int ladj;       // local adjacency entries reserved at the hand-over
+    unsigned long long lres; // hand-over: local ids (low word) and adjacency entries (high word) given out
+    unsigned int nlvl;       // levels recorded by the one-workgroup finish
     unsigned int snap[2][4]; // per generation parity: qtail, n_alive2, min_deg at the release
 };
 
@@ -135,7 +138,18 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
                                              uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
                                              PeelCtl *ctl, uint32_t *s_stage, unsigned *s_cnt) {
     const uint32_t e = row[v + 1];
-    for (uint32_t j = row[v] + first; j < e; j += stride) {
+    uint32_t j = row[v] + first;
+    // four independent decrements in flight per lane
+    for (; j + 3 * stride < e; j += 4 * stride) {
+        const uint32_t x0 = col[j], x1 = col[j + stride], x2 = col[j + 2 * stride], x3 = col[j + 3 * stride];
+        const int o0 = atomicSub(&deg[x0], 1), o1 = atomicSub(&deg[x1], 1), o2 = atomicSub(&deg[x2], 1),
+                  o3 = atomicSub(&deg[x3], 1);
+        if (o0 == (int)k + 1) enqueue(x0, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+        if (o1 == (int)k + 1) enqueue(x1, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+        if (o2 == (int)k + 1) enqueue(x2, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+        if (o3 == (int)k + 1) enqueue(x3, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+    }
+    for (; j < e; j += stride) {
         const uint32_t x = col[j];
         const int old = atomicSub(&deg[x], 1);
         if (old == (int)k + 1) enqueue(x, k, n, level, queue, deg, ctl, s_stage, s_cnt);
@@ -143,32 +157,45 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
 }
 
 // The last vertices: one workgroup finishes the peel on the subgraph they induce, with local
-// (16-bit) vertex ids, degrees and queue in LDS and workgroup barriers between rounds.  rlist maps
-// local ids to vertices; the local adjacency of lid is lcol[lbeg[lid], lbeg[lid] + ldeg0[lid]).
-// Queue positions continue from qbase.
+// (16-bit) vertex ids.  The local CSR rows, the degrees, the removal queue and a removed bitmap
+// live in LDS, so a round touches global memory only to read adjacency (lcol); workgroup barriers
+// separate rounds.  rlist maps local ids to vertices.  Degrees count the neighbours not yet
+// removed, so a decrement never takes one below zero and two 16-bit degrees share a word safely.
+// The queue positions (continuing from qbase) and the core numbers are written at the end, from
+// the queue and the level boundaries recorded in lvl (pairs: first queue position, level).
 __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t rounds,
-                          const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lbeg,
-                          const uint32_t *__restrict__ ldeg0, const uint16_t *__restrict__ lcol,
+                          const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lrow,
+                          const uint16_t *__restrict__ lcol, uint32_t *__restrict__ lvl,
                           uint32_t *__restrict__ level, uint32_t *__restrict__ queue, PeelCtl *ctl,
                           uint32_t *s_mem) {
-    int *s_deg = reinterpret_cast<int *>(s_mem);                    // kTail
-    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_mem + kTail);    // kTail
-    __shared__ unsigned s_qt, s_keep, s_min;
+    uint32_t *s_row = s_mem;                                              // kRowWords
+    uint32_t *s_deg = s_mem + kRowWords;                                  // kDegWords
+    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_mem + kRowWords + kDegWords);   // kTail
+    uint32_t *s_rem = s_mem + kRowWords + kDegWords + kQWords;            // kRemWords
+    __shared__ unsigned s_qt, s_keep, s_min, s_nlvl;
     const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid / 64;
     constexpr unsigned kWaves = kBlock / 64;
     const uint64_t below = (1ull << lane) - 1;
-    for (uint32_t l = tid; l < R; l += kBlock) s_deg[l] = (int)ldeg0[l];
-    if (tid == 0) s_qt = 0;
+    for (uint32_t l = tid; l <= R; l += kBlock) s_row[l] = lrow[l];
+    for (uint32_t w = tid; w < kDegWords; w += kBlock) s_deg[w] = 0;
+    for (uint32_t w = tid; w < kRemWords; w += kBlock) s_rem[w] = 0;
+    __syncthreads();
+    for (uint32_t l = tid; l < R; l += kBlock)
+        atomicAdd(&s_deg[l >> 1], (s_row[l + 1] - s_row[l]) << ((l & 1) * 16));
+    if (tid == 0) {
+        s_qt = 0;
+        s_nlvl = 0;
+    }
     uint32_t h = 0, t = 0;
-    // a vertex whose local degree a removal took from k + 1 to k
-    auto take = [&](uint32_t x, uint32_t kk) {
-        s_deg[x] = kRemoved;
-        const uint32_t p = atomicAdd(&s_qt, 1u);
-        if (p < R) {
-            s_q[p] = (uint16_t)x;
-            const uint32_t v = rlist[x];
-            level[v] = kk;
-            queue[qbase + p] = v;
+    auto deg_of = [&](uint32_t l) { return (s_deg[l >> 1] >> ((l & 1) * 16)) & 0xffffu; };
+    // remove one edge end at y; a degree taken from k + 1 to k queues y
+    auto dec = [&](uint32_t y, uint32_t kk) {
+        const uint32_t sh = (y & 1) * 16;
+        const uint32_t old = (atomicSub(&s_deg[y >> 1], 1u << sh) >> sh) & 0xffffu;
+        if (old == kk + 1) {
+            atomicOr(&s_rem[y >> 5], 1u << (y & 31));
+            const uint32_t p = atomicAdd(&s_qt, 1u);
+            if (p < R) s_q[p] = (uint16_t)y;
         }
     };
     while (true) {
@@ -179,26 +206,22 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
         }
         __syncthreads();
         const uint32_t level_start = t;
-        // level scan over all local vertices (removed ones hold negative degrees)
+        // level scan over all local vertices not yet removed
         for (uint32_t b0 = wave * 64; b0 < R; b0 += kWaves * 64) {
             const uint32_t l = b0 + lane;
-            const int d = l < R ? s_deg[l] : -1;
-            const bool tk = d >= 0 && d <= (int)k, kp = d > (int)k;
+            const bool live = l < R && !((s_rem[l >> 5] >> (l & 31)) & 1u);
+            const uint32_t d = live ? deg_of(l) : 0u;
+            const bool tk = live && d <= k, kp = live && d > k;
             const uint64_t mt = __ballot(tk), mk = __ballot(kp);
             uint32_t qb = 0;
             if (lane == 0 && mt) qb = atomicAdd(&s_qt, (unsigned)__popcll(mt));
             qb = __shfl(qb, 0, 64);
             if (tk) {
                 const uint32_t p = qb + (uint32_t)__popcll(mt & below);
-                s_deg[l] = kRemoved;
-                if (p < R) {
-                    s_q[p] = (uint16_t)l;
-                    const uint32_t v = rlist[l];
-                    level[v] = k;
-                    queue[qbase + p] = v;
-                }
+                atomicOr(&s_rem[l >> 5], 1u << (l & 31));
+                if (p < R) s_q[p] = (uint16_t)l;
             }
-            const unsigned md = wave_min(kp ? (unsigned)d : 0xffffffffu);
+            const unsigned md = wave_min(kp ? d : 0xffffffffu);
             if (lane == 0 && mk) {
                 atomicAdd(&s_keep, (unsigned)__popcll(mk));
                 atomicMin(&s_min, md);
@@ -221,24 +244,28 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
             }
             for (uint32_t i = i0; i < t; i += step) {
                 const uint32_t x = s_q[i];
-                const uint32_t e = lbeg[x] + ldeg0[x];
-                uint32_t j = lbeg[x] + first;
+                const uint32_t e = s_row[x + 1];
+                uint32_t j = s_row[x] + first;
                 for (; j + 3 * stride < e; j += 4 * stride) {
                     const uint32_t y0 = lcol[j], y1 = lcol[j + stride], y2 = lcol[j + 2 * stride],
                                    y3 = lcol[j + 3 * stride];
-                    if (atomicSub(&s_deg[y0], 1) == (int)k + 1) take(y0, k);
-                    if (atomicSub(&s_deg[y1], 1) == (int)k + 1) take(y1, k);
-                    if (atomicSub(&s_deg[y2], 1) == (int)k + 1) take(y2, k);
-                    if (atomicSub(&s_deg[y3], 1) == (int)k + 1) take(y3, k);
+                    dec(y0, k);
+                    dec(y1, k);
+                    dec(y2, k);
+                    dec(y3, k);
                 }
-                for (; j < e; j += stride)
-                    if (atomicSub(&s_deg[lcol[j]], 1) == (int)k + 1) take(lcol[j], k);
+                for (; j < e; j += stride) dec(lcol[j], k);
             }
             ++rounds;
             __syncthreads();
             h = t;
             t = s_qt;
             __syncthreads();
+        }
+        if (t > level_start && tid == 0) {   // this level removed s_q[level_start, t)
+            const uint32_t li = s_nlvl++;
+            lvl[2 * li] = level_start;
+            lvl[2 * li + 1] = k;
         }
         if (t >= R) break;
         uint32_t next = k + 1;
@@ -249,10 +276,30 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
             break;
         }
     }
+    __syncthreads();
+    // queue positions and core numbers of the removed vertices, in removal order
+    const uint32_t nl = s_nlvl, nq = t < R ? t : R;
+    __threadfence_block();
+    for (uint32_t p = tid; p < nq; p += kBlock) {
+        const uint32_t v = rlist[s_q[p]];
+        queue[qbase + p] = v;
+        uint32_t lo = 0, len = nl;   // last boundary at or before p
+        while (len > 0) {
+            const uint32_t half = len >> 1;
+            if (lvl[2 * (lo + half)] <= p) {
+                lo += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
+        }
+        level[v] = lo > 0 ? lvl[2 * (lo - 1) + 1] : k;
+    }
     if (tid == 0) {
-        __hip_atomic_store(&ctl->qtail, qbase + (t < R ? t : R), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->qtail, qbase + nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ctl->kappa = k;
         ctl->rounds = rounds;
+        ctl->nlvl = nl;
     }
 }
 
@@ -260,7 +307,7 @@ __global__ void __launch_bounds__(kBlock)
 k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict__ col,
        int *__restrict__ deg, uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
        uint32_t *__restrict__ alive_a, uint32_t *__restrict__ alive_b, uint32_t *__restrict__ loc,
-       uint32_t *__restrict__ rlist, uint32_t *__restrict__ lbeg, uint32_t *__restrict__ ldeg0,
+       uint32_t *__restrict__ rlist, uint32_t *__restrict__ lrow, uint32_t *__restrict__ lvl,
        uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, PeelCtl *__restrict__ ctl) {
     const unsigned nblk = gridDim.x;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
@@ -400,8 +447,9 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     }
     // Hand over to one workgroup.  Every remaining vertex is in cur with its degree (the number
     // of its remaining neighbours, since every queued vertex has been removed): give it a local
-    // id and reserve that many entries of the local adjacency, then write its remaining
-    // neighbours' local ids there.
+    // id and that many consecutive entries of the local adjacency (one 64-bit atomic per
+    // wavefront reserves both, so rows follow local ids and lrow is a CSR row array), then write
+    // its remaining neighbours' local ids there.
     for (uint32_t b0 = gwave * 64; b0 < n_alive; b0 += nwaves * 64) {
         const uint32_t i = b0 + lane;
         uint32_t v = 0;
@@ -412,7 +460,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         }
         const bool live = d >= 0;
         const uint64_t ml = __ballot(live);
-        // exclusive prefix of the live degrees within the wavefront
+        // inclusive prefix of the live degrees within the wavefront
         uint32_t inc = live ? (uint32_t)d : 0u;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -420,34 +468,33 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             if (lane >= (unsigned)o) inc += y;
         }
         const uint32_t tot = __shfl(inc, 63, 64);
-        uint32_t lb = 0, ab = 0;
-        if (lane == 0 && ml) {
-            lb = atomicAdd(&ctl->n_alive2, (unsigned)__popcll(ml));
-            ab = atomicAdd(&ctl->ladj, tot);
-        }
-        lb = __shfl(lb, 0, 64);
-        ab = __shfl(ab, 0, 64);
+        unsigned long long base = 0;
+        if (lane == 0 && ml)
+            base = atomicAdd(&ctl->lres, ((unsigned long long)tot << 32) | (unsigned long long)__popcll(ml));
+        base = __shfl(base, 0, 64);
         if (live) {
-            const uint32_t lid = lb + (uint32_t)__popcll(ml & below);
-            const uint64_t off = (uint64_t)ab + inc - (uint32_t)d;
+            const uint32_t lid = (uint32_t)base + (uint32_t)__popcll(ml & below);
+            const uint64_t off = (base >> 32) + inc - (uint32_t)d;
             if (lid < kTail && off + (uint32_t)d <= lcol_cap) {
                 rlist[lid] = v;
                 loc[v] = lid;
-                lbeg[lid] = (uint32_t)off;
-                ldeg0[lid] = (uint32_t)d;
+                lrow[lid] = (uint32_t)off;
             } else {
                 atomicOr(&ctl->error, 4u);
             }
         }
     }
-    grid_barrier(ctl, nblk, true, snap);
-    const uint32_t R = snap[1];
-    if (R != n - tail || R > kTail || ld_relaxed(&ctl->error)) {
+    grid_barrier(ctl, nblk, false, snap);
+    const unsigned long long lres = __hip_atomic_load(&ctl->lres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t R = (uint32_t)lres, total = (uint32_t)(lres >> 32);
+    if (R != n - tail || R > kTail || total > lcol_cap || ld_relaxed(&ctl->error)) {
         if (gtid == 0) atomicOr(&ctl->error, 4u);
         return;
     }
+    if (gtid == 0) lrow[R] = total;
     for (uint32_t l = gwave; l < R; l += nwaves) {
-        const uint32_t v = rlist[l], b = lbeg[l], d = ldeg0[l];
+        const uint32_t v = rlist[l], b = lrow[l];
+        const uint32_t d = (uint32_t)ld_relaxed(&deg[v]);
         const uint32_t e = row[v + 1];
         uint32_t c = 0;
         for (uint32_t j0 = row[v]; j0 < e; j0 += 64) {
@@ -462,7 +509,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     }
     grid_barrier(ctl, nblk, false, snap);
     if (blockIdx.x != 0 || ld_relaxed(&ctl->error)) return;
-    peel_tail(R, tail, k, rounds, rlist, lbeg, ldeg0, lcol, level, queue, ctl, s_mem);
+    peel_tail(R, tail, k, rounds, rlist, lrow, lcol, lvl, level, queue, ctl, s_mem);
 }
 
 __global__ void k_finish(uint32_t n, const uint32_t *__restrict__ queue, uint32_t *__restrict__ rank) {
@@ -476,7 +523,7 @@ int peel(dt_graph *g) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
-    DevMem deg, alive, alive2, ctlm, loc, rlist, lbeg, ldeg0, lcol;
+    DevMem deg, alive, alive2, ctlm, loc, rlist, lrow, lvl, lcol;
     DT_TRY(dev_alloc(ctx, deg, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive2, (uint64_t)n * 4));
@@ -490,8 +537,8 @@ int peel(dt_graph *g) {
     const uint64_t lcol_cap = std::min<uint64_t>(2ull * g->m_s, (uint64_t)tail_cap * (tail_cap - 1));
     DT_TRY(dev_alloc(ctx, loc, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, rlist, (uint64_t)tail_cap * 4));
-    DT_TRY(dev_alloc(ctx, lbeg, (uint64_t)tail_cap * 4));
-    DT_TRY(dev_alloc(ctx, ldeg0, (uint64_t)tail_cap * 4));
+    DT_TRY(dev_alloc(ctx, lrow, ((uint64_t)tail_cap + 1) * 4));
+    DT_TRY(dev_alloc(ctx, lvl, (uint64_t)tail_cap * 8));
     DT_TRY(dev_alloc(ctx, lcol, (lcol_cap + 1) * 2));
     if (n == 0) {
         g->kappa = 0;
@@ -512,8 +559,8 @@ int peel(dt_graph *g) {
     uint32_t *aa = alive.as<uint32_t>(), *ab = alive2.as<uint32_t>();
     PeelCtl *ctl = ctlm.as<PeelCtl>();
     uint32_t nn = n;
-    uint32_t *locp = loc.as<uint32_t>(), *rl = rlist.as<uint32_t>(), *lb = lbeg.as<uint32_t>(),
-             *ld = ldeg0.as<uint32_t>();
+    uint32_t *locp = loc.as<uint32_t>(), *rl = rlist.as<uint32_t>(), *lb = lrow.as<uint32_t>(),
+             *ld = lvl.as<uint32_t>();
     uint16_t *lc = lcol.as<uint16_t>();
     uint64_t lcap = lcol_cap;
     uint32_t tcap = tail_cap;

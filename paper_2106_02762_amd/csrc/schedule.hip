@@ -32,38 +32,50 @@ __device__ __forceinline__ int tri_class(uint64_t P, uint64_t cap_l, uint64_t ca
 }
 
 constexpr int kPartWords = 6;   // per block: sum_sigma3 lo, hi, bytes, light, medium, unit bytes
+constexpr unsigned kClsGrid = 4096;   // blocks of the classify and partition passes (grid-stride)
 
-// per triangle: class flags; per block: the sum of sigma products (128-bit) and the byte totals
-__global__ void k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
-                           uint64_t cap_l, uint64_t cap_m, uint32_t force, uint32_t unit_ok,
-                           uint64_t *__restrict__ f1, uint64_t *__restrict__ f2, uint64_t *__restrict__ f3,
-                           uint64_t *__restrict__ part) {
+// Per triangle its class (one byte); per block the triangles of each class and the sum of sigma
+// products (128-bit) and byte totals.  The partition pass walks the triangles in the same
+// block / iteration order, so per-block class counts give every triangle its place.
+__global__ void __launch_bounds__(kBlock)
+k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+           uint64_t cap_l, uint64_t cap_m, uint32_t force, uint32_t unit_ok, uint8_t *__restrict__ cls,
+           uint32_t *__restrict__ bcnt, uint64_t *__restrict__ part) {
     __shared__ unsigned long long s_w[kPartWords][kBlock];
+    __shared__ unsigned s_cnt[4];
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
     unsigned __int128 acc = 0;
     unsigned long long bytes = 0, bytes_light = 0, bytes_medium = 0, bytes_unit = 0;
+    unsigned c[4] = {0, 0, 0, 0};
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n_tri; i += (uint64_t)gridDim.x * kBlock) {
         const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
         const uint64_t s_uv = eoff[2 * e_uv + 2] - eoff[2 * e_uv];
         const uint64_t s_uw = eoff[2 * e_uw + 2] - eoff[2 * e_uw];
         const uint32_t s_vw = eoff[2 * e_vw + 2] - eoff[2 * e_vw];
         const bool unit = unit_ok && s_uv == 1 && s_uw == 1 && s_vw == 1;
-        const int cls = tri_class(s_uv * s_uw, cap_l, cap_m, force, unit);
-        f1[i] = cls == 1 ? 1ull : 0ull;
-        f2[i] = cls == 2 ? 1ull : 0ull;
-        f3[i] = cls == 3 ? 1ull : 0ull;
+        const int k = tri_class(s_uv * s_uw, cap_l, cap_m, force, unit);
+        cls[i] = (uint8_t)k;
+        c[0] += k == 0;
+        c[1] += k == 1;
+        c[2] += k == 2;
+        c[3] += k == 3;
         acc += (unsigned __int128)(s_uv * s_uw) * s_vw;
         uint64_t b;
-        if (cls == 3) {
+        if (k == 3) {
             b = sizeof(uint4);
         } else {
             const uint32_t probe = 2 * ceil_log2_1(s_vw);
             b = 12 + 36 + 8 * (s_uv + s_uw) + 8 * (uint64_t)(s_vw < probe ? s_vw : probe);
         }
         bytes += b;
-        bytes_light += cls == 0 ? b : 0;
-        bytes_medium += cls == 1 ? b : 0;
-        bytes_unit += cls == 3 ? b : 0;
+        bytes_light += k == 0 ? b : 0;
+        bytes_medium += k == 1 ? b : 0;
+        bytes_unit += k == 3 ? b : 0;
     }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+        if (c[x]) atomicAdd(&s_cnt[x], c[x]);
     s_w[0][threadIdx.x] = (unsigned long long)acc;
     s_w[1][threadIdx.x] = (unsigned long long)(acc >> 64);
     s_w[2][threadIdx.x] = bytes;
@@ -71,6 +83,7 @@ __global__ void k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, con
     s_w[4][threadIdx.x] = bytes_medium;
     s_w[5][threadIdx.x] = bytes_unit;
     __syncthreads();
+    if (threadIdx.x < 4) bcnt[4 * blockIdx.x + threadIdx.x] = s_cnt[threadIdx.x];
     if (threadIdx.x == 0) {
         unsigned __int128 t = 0;
         unsigned long long w[kPartWords] = {0, 0, 0, 0, 0, 0};
@@ -114,45 +127,66 @@ __device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint3
     return make_uint4(t1, t2 - t1, t3 - t2, (uint32_t)(((pi - 1) * 8 + (rho - 1)) << 8) | (uint32_t)(type - 1));
 }
 
-__global__ void k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint64_t *__restrict__ f1,
-                            const uint64_t *__restrict__ f2, const uint64_t *__restrict__ f3,
-                            const uint64_t *__restrict__ p1, const uint64_t *__restrict__ p2,
-                            const uint64_t *__restrict__ p3, const uint32_t *__restrict__ eoff,
-                            const uint64_t *__restrict__ key, int shift, int pos_bits,
-                            uint32_t *__restrict__ light,
-                            uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy,
-                            uint4 *__restrict__ urec, uint64_t *__restrict__ ukey) {
-    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_tri) return;
-    const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
-    if (f3[i]) {
-        // sort key: t1 above the record's position (positions ascend, so the order is stable)
-        const uint64_t j = p3[i];
-        const uint4 r = unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
-        urec[j] = r;
-        ukey[j] = ((uint64_t)r.x << pos_bits) | j;
-        return;
+// Every triangle to its class's list at base[class][block] + its rank in the block's walk; unit
+// triangles become records (in triangle order) and are counted per t1 bucket.
+__global__ void __launch_bounds__(kBlock)
+k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__restrict__ cls,
+            const uint64_t *__restrict__ base, const uint32_t *__restrict__ eoff,
+            const uint64_t *__restrict__ key, int shift, int bshift, uint32_t *__restrict__ light,
+            uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy, uint4 *__restrict__ urec,
+            uint32_t *__restrict__ ucount) {
+    __shared__ unsigned long long s_wave[kBlock / 64];
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    uint64_t run[4] = {base[4 * blockIdx.x], base[4 * blockIdx.x + 1], base[4 * blockIdx.x + 2],
+                       base[4 * blockIdx.x + 3]};
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kBlock; b0 < n_tri; b0 += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = b0 + threadIdx.x;
+        const int k = i < n_tri ? cls[i] : 4;
+        // four 16-bit class counters in one word (a block holds at most 256 triangles)
+        const unsigned long long f = k < 4 ? 1ull << (16 * k) : 0ull;
+        unsigned long long x = f;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o, 64);
+            if (lane >= (unsigned)o) x += y;
+        }
+        if (lane == 63) s_wave[wave] = x;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+#pragma unroll
+        for (unsigned w = 0; w < kBlock / 64; ++w) {
+            before += w < wave ? s_wave[w] : 0ull;
+            total += s_wave[w];
+        }
+        __syncthreads();
+        if (k < 4) {
+            const uint64_t pos = run[k] + (((before + x - f) >> (16 * k)) & 0xffffull);
+            const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
+            if (k == 3) {
+                const uint4 r = unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
+                urec[pos] = r;
+                atomicAdd(&ucount[r.x >> bshift], 1u);
+            } else {
+                uint32_t *dst = (k == 0 ? light : (k == 1 ? medium : heavy)) + 3 * pos;
+                dst[0] = e_uv;
+                dst[1] = e_uw;
+                dst[2] = e_vw;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) run[c] += (total >> (16 * c)) & 0xffffull;
     }
-    uint32_t *dst = f2[i] ? heavy + 3 * p2[i]
-                          : (f1[i] ? medium + 3 * p1[i] : light + 3 * (i - p1[i] - p2[i] - p3[i]));
-    dst[0] = e_uv;
-    dst[1] = e_uw;
-    dst[2] = e_vw;
 }
 
-// records in t1 order
-__global__ void k_unit_gather(uint64_t nu, const uint64_t *__restrict__ skey, uint64_t pos_mask,
-                              const uint4 *__restrict__ src, uint4 *__restrict__ dst) {
+// records grouped by t1 bucket (order inside a bucket unspecified)
+__global__ void k_unit_scatter(uint64_t nu, const uint4 *__restrict__ src, int bshift,
+                               const uint32_t *__restrict__ ustart, uint32_t *__restrict__ ucur,
+                               uint4 *__restrict__ dst) {
     uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nu) return;
-    dst[j] = src[skey[j] & pos_mask];
-}
-
-// t1 of every kUnitStride-th record
-__global__ void k_unit_index(uint64_t nidx, const uint4 *__restrict__ rec, uint32_t *__restrict__ idx) {
-    uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nidx) return;
-    idx[j] = rec[j * kUnitStride].x;
+    const uint4 r = src[j];
+    const uint32_t b = r.x >> bshift;
+    dst[ustart[b] + atomicAdd(&ucur[b], 1u)] = r;
 }
 
 // work items of the medium path: ceil(P / kMediumChunk) per triangle
@@ -209,34 +243,21 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     const uint64_t cap_l = g->tuning.light_pair_cap, cap_m = g->tuning.medium_pair_cap;
     const uint32_t force = g->tuning.force_path;
     const uint32_t chunk = g->tuning.heavy_chunk;
-    // unit records hold 32-bit relative times and 32-bit positions in their sort key
-    const uint32_t unit_ok = g->span <= kUnitMaxSpan && nt < (1ull << 32) ? 1u : 0u;
-    DevMem f1, f2, f3, p1, p2, p3, part;
-    DT_TRY(dev_alloc(ctx, f1, (nt + 1) * 8));
-    DT_TRY(dev_alloc(ctx, f2, (nt + 1) * 8));
-    DT_TRY(dev_alloc(ctx, f3, (nt + 1) * 8));
-    DT_TRY(dev_alloc(ctx, p1, (nt + 1) * 8));
-    DT_TRY(dev_alloc(ctx, p2, (nt + 1) * 8));
-    DT_TRY(dev_alloc(ctx, p3, (nt + 1) * 8));
-    unsigned grid = grid_for(nt, kBlock);
-    if (grid > 4096) grid = 4096;
+    // unit records hold 32-bit relative times
+    const uint32_t unit_ok = g->span <= kUnitMaxSpan ? 1u : 0u;
+    const unsigned grid = kClsGrid;
+    DevMem cls, bcnt, part, base;
+    DT_TRY(dev_alloc(ctx, cls, nt + 1));
+    DT_TRY(dev_alloc(ctx, bcnt, (uint64_t)grid * 4 * 4));
     DT_TRY(dev_alloc(ctx, part, (uint64_t)grid * kPartWords * 8));
-    DT_HIP(hipMemsetAsync(f1.ptr, 0, (nt + 1) * 8, st));
-    DT_HIP(hipMemsetAsync(f2.ptr, 0, (nt + 1) * 8, st));
-    DT_HIP(hipMemsetAsync(f3.ptr, 0, (nt + 1) * 8, st));
+    DT_TRY(dev_alloc(ctx, base, (uint64_t)grid * 4 * 8));
     k_classify<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), g->eoff.as<uint32_t>(), cap_l, cap_m, force,
-                                        unit_ok, f1.as<uint64_t>(), f2.as<uint64_t>(), f3.as<uint64_t>(),
-                                        part.as<uint64_t>());
+                                        unit_ok, cls.as<uint8_t>(), bcnt.as<uint32_t>(), part.as<uint64_t>());
     DT_HIP(hipGetLastError());
     std::vector<uint64_t> hp((size_t)grid * kPartWords);
+    std::vector<uint32_t> hc((size_t)grid * 4);
     DT_HIP(hipMemcpyAsync(hp.data(), part.ptr, hp.size() * 8, hipMemcpyDeviceToHost, st));
-    DT_TRY(exclusive_scan_u64(ctx, f1.as<uint64_t>(), p1.as<uint64_t>(), nt + 1, st));
-    DT_TRY(exclusive_scan_u64(ctx, f2.as<uint64_t>(), p2.as<uint64_t>(), nt + 1, st));
-    DT_TRY(exclusive_scan_u64(ctx, f3.as<uint64_t>(), p3.as<uint64_t>(), nt + 1, st));
-    uint64_t nm = 0, nh = 0, nu = 0;
-    DT_HIP(hipMemcpyAsync(&nm, p1.as<uint64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipMemcpyAsync(&nh, p2.as<uint64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipMemcpyAsync(&nu, p3.as<uint64_t>() + nt, 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipMemcpyAsync(hc.data(), bcnt.ptr, hc.size() * 4, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
     unsigned __int128 s3 = 0;
     uint64_t w[kPartWords] = {0, 0, 0, 0, 0, 0};
@@ -244,55 +265,61 @@ int make_schedule(dt_graph *g, DevMem &tri) {
         s3 += ((unsigned __int128)hp[kPartWords * b + 1] << 64) | hp[kPartWords * b];
         for (int x = 2; x < kPartWords; ++x) w[x] += hp[kPartWords * b + x];
     }
+    // each block's first position in each class list
+    std::vector<uint64_t> hb((size_t)grid * 4);
+    uint64_t ncls[4] = {0, 0, 0, 0};
+    for (unsigned b = 0; b < grid; ++b)
+        for (int c = 0; c < 4; ++c) {
+            hb[4 * b + c] = ncls[c];
+            ncls[c] += hc[4 * b + c];
+        }
+    DT_HIP(hipMemcpyAsync(base.ptr, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st));
     g->sum_sigma3 = s3;
     g->alg_bytes = w[2];
     g->alg_bytes_light = w[3];
     g->alg_bytes_medium = w[4];
     g->alg_bytes_unit = w[5];
-    S.n_heavy = nh;
+    const uint64_t nm = ncls[1], nh = ncls[2], nu = ncls[3];
+    if (ncls[0] + nm + nh + nu != nt) return fail(DT_EDEVICE, "triangle classes do not add up");
+    S.n_light = ncls[0];
     S.n_medium = nm;
+    S.n_heavy = nh;
     S.n_unit = nu;
-    S.n_light = nt - nh - nm - nu;
     DT_TRY(dev_alloc(ctx, S.light, S.n_light * 12));
     DT_TRY(dev_alloc(ctx, S.medium, S.n_medium * 12));
     DT_TRY(dev_alloc(ctx, S.heavy, S.n_heavy * 12));
-    // positions take pos_bits, t1 < 2^31 the bits above: at most 63 in all
-    int pos_bits = 0;
-    while (pos_bits < 32 && (1ull << pos_bits) < nu) ++pos_bits;
+    // t1 buckets of the unit records: at most 2^16, t1 >> unit_shift
     int t_bits = 0;
     while (t_bits < 31 && (1ll << t_bits) <= g->span) ++t_bits;
-    DevMem urec, ukey, skey;
+    S.unit_shift = t_bits > 16 ? t_bits - 16 : 0;
+    const uint64_t nbk = unit_ok ? ((uint64_t)g->span >> S.unit_shift) + 1 : 1;
+    DevMem urec, ucount, ucur;
     DT_TRY(dev_alloc(ctx, urec, nu * sizeof(uint4)));
-    DT_TRY(dev_alloc(ctx, ukey, nu * 8));
+    DT_TRY(dev_alloc(ctx, ucount, (nbk + 1) * 4));
+    DT_TRY(dev_alloc(ctx, ucur, (nbk + 1) * 4));
+    DT_HIP(hipMemsetAsync(ucount.ptr, 0, (nbk + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(ucur.ptr, 0, (nbk + 1) * 4, st));
     if (nt) {
-        k_partition<<<grid_for(nt, kBlock), kBlock, 0, st>>>(nt, tri.as<uint32_t>(), f1.as<uint64_t>(),
-            f2.as<uint64_t>(), f3.as<uint64_t>(), p1.as<uint64_t>(), p2.as<uint64_t>(), p3.as<uint64_t>(),
-            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, pos_bits, S.light.as<uint32_t>(),
-            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), urec.as<uint4>(), ukey.as<uint64_t>());
+        k_partition<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), cls.as<uint8_t>(), base.as<uint64_t>(),
+            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, S.unit_shift, S.light.as<uint32_t>(),
+            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), urec.as<uint4>(), ucount.as<uint32_t>());
         DT_HIP(hipGetLastError());
+    }
+    cls.reset();
+    // unit records grouped by t1 bucket; the host keeps the bucket starts
+    if (nu) {
+        DevMem ustart;
+        DT_TRY(dev_alloc(ctx, ustart, (nbk + 1) * 4));
+        DT_TRY(exclusive_scan_u32(ctx, ucount.as<uint32_t>(), ustart.as<uint32_t>(), nbk + 1, st));
+        DT_TRY(dev_alloc(ctx, S.unit, nu * sizeof(uint4)));
+        k_unit_scatter<<<grid_for(nu, kBlock), kBlock, 0, st>>>(nu, urec.as<uint4>(), S.unit_shift,
+            ustart.as<uint32_t>(), ucur.as<uint32_t>(), S.unit.as<uint4>());
+        DT_HIP(hipGetLastError());
+        S.unit_index.resize(nbk + 1);
+        DT_HIP(hipMemcpyAsync(S.unit_index.data(), ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, st));
     }
     DT_HIP(hipStreamSynchronize(st));
-    f1.reset(); f2.reset(); f3.reset(); p1.reset(); p2.reset(); p3.reset();
-    // unit records in t1 order, and the host index of every kUnitStride-th t1
-    if (nu) {
-        DT_TRY(dev_alloc(ctx, skey, nu * 8));
-        DT_TRY(sort_keys_u64(ctx, ukey.as<uint64_t>(), skey.as<uint64_t>(), nu, std::max(1, pos_bits + t_bits), st));
-        ukey.reset();
-        DT_TRY(dev_alloc(ctx, S.unit, nu * sizeof(uint4)));
-        k_unit_gather<<<grid_for(nu, kBlock), kBlock, 0, st>>>(nu, skey.as<uint64_t>(), (1ull << pos_bits) - 1,
-                                                               urec.as<uint4>(), S.unit.as<uint4>());
-        DT_HIP(hipGetLastError());
-        const uint64_t nidx = (nu + kUnitStride - 1) / kUnitStride;
-        DevMem didx;
-        DT_TRY(dev_alloc(ctx, didx, nidx * 4));
-        k_unit_index<<<grid_for(nidx, kBlock), kBlock, 0, st>>>(nidx, S.unit.as<uint4>(), didx.as<uint32_t>());
-        DT_HIP(hipGetLastError());
-        S.unit_index.resize(nidx);
-        DT_HIP(hipMemcpyAsync(S.unit_index.data(), didx.ptr, nidx * 4, hipMemcpyDeviceToHost, st));
-        DT_HIP(hipStreamSynchronize(st));
-    }
     urec.reset();
-    skey.reset();
     {
         DevMem nch, base;
         DT_TRY(dev_alloc(ctx, nch, (nm + 1) * 8));
@@ -354,18 +381,19 @@ void unit_range(const dt_graph *g, const DQuery &q, uint64_t *b, uint64_t *e) {
     *b = 0;
     *e = S.n_unit;
     if (!q.windowed || S.n_unit == 0) return;
-    // a triangle inside the window has wlo <= t1 < whi (relative times)
+    // a triangle inside the window has wlo <= t1 < whi (relative times): buckets
+    // wlo >> shift .. (whi - 1) >> shift
+    const std::vector<uint32_t> &ix = S.unit_index;   // bucket starts, nbk + 1 entries
+    const uint64_t nbk = ix.size() - 1;
     const uint64_t wlo = q.klo >> q.shift, whi = q.khi >> q.shift;
-    const std::vector<uint32_t> &ix = S.unit_index;
-    // index entries below wlo: the records before the last of them all have t1 < wlo
-    const size_t below = std::lower_bound(ix.begin(), ix.end(), wlo,
-                                          [](uint32_t a, uint64_t v) { return (uint64_t)a < v; }) - ix.begin();
-    *b = below > 0 ? (uint64_t)(below - 1) * kUnitStride : 0;
-    // the first entry at or after whi starts a run of records with t1 >= whi
-    const size_t upto = std::lower_bound(ix.begin(), ix.end(), whi,
-                                         [](uint32_t a, uint64_t v) { return (uint64_t)a < v; }) - ix.begin();
-    if (upto < ix.size()) *e = std::min<uint64_t>((uint64_t)upto * kUnitStride, S.n_unit);
-    if (*e < *b) *e = *b;
+    if (whi <= wlo) {
+        *e = *b;
+        return;
+    }
+    const uint64_t bl = std::min<uint64_t>(wlo >> S.unit_shift, nbk);
+    const uint64_t bh = std::min<uint64_t>(((whi - 1) >> S.unit_shift) + 1, nbk);
+    *b = ix[bl];
+    *e = bh > bl ? ix[bh] : ix[bl];
 }
 
 }  // namespace dt

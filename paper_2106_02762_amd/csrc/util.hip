@@ -156,17 +156,6 @@ int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
     return DT_OK;
 }
 
-int sort_keys_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, size_t n, int end_bit, hipStream_t s) {
-    if (n == 0) return DT_OK;
-    size_t bytes = 0;
-    DT_HIP(rocprim::radix_sort_keys(nullptr, bytes, kin, kout, n, 0u, (unsigned)end_bit, s));
-    DevMem tmp;
-    DT_TRY(dev_alloc(ctx, tmp, bytes));
-    DT_HIP(rocprim::radix_sort_keys(tmp.ptr, bytes, kin, kout, n, 0u, (unsigned)end_bit, s));
-    DT_HIP(hipStreamSynchronize(s));
-    return DT_OK;
-}
-
 int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
                        uint64_t *vout, size_t n, int end_bit, hipStream_t s) {
     if (n == 0) return DT_OK;
