@@ -230,6 +230,9 @@ int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
                        uint32_t *vout, size_t n, int end_bit, hipStream_t s);
 int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
                        uint64_t *vout, size_t n, int end_bit, hipStream_t s);
+// (16-bit key, 16-byte record) pairs
+int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const uint4 *vin, uint4 *vout,
+                      size_t n, int end_bit, hipStream_t s);
 int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
 int exclusive_scan_u64(dt_ctx *ctx, const uint64_t *in, uint64_t *out, size_t n, hipStream_t s);
 

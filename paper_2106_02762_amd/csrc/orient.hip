@@ -2,7 +2,10 @@
 // u to v iff u comes first), and the re-layout of the temporal edge store in DAG-edge order.
 //
 // Vertices are renamed by their rank, so a DAG edge is (rank u, rank v) with rank u < rank v and
-// the out-neighbours of u are a sorted run.  DAG edges are numbered in (tail, head) order, and the
+// the out-neighbours of u are a sorted run.  The runs are built without a global sort: out-degrees
+// are counted from the pair list, scanned into rows, every pair is placed in its tail's run, and
+// each run (at most the degeneracy long) is sorted by one wavefront.  DAG edges are numbered in
+// (tail, head) order, and the
 // temporal edges of DAG edge d are stored at [eoff[2d], eoff[2d+2]): first those directed
 // tail -> head, then head -> tail, each in key order (a scatter by rank, no re-sort).  All edges at one source vertex u are then
 // one contiguous stretch of the store, which is exactly what the counting of all triangles with
@@ -15,43 +18,176 @@ namespace {
 
 constexpr unsigned kBlock = 256;
 
-__global__ void k_dag_keys(uint64_t ms, const uint32_t *__restrict__ sx, const uint32_t *__restrict__ sy,
-                           const uint32_t *__restrict__ rank, uint64_t *__restrict__ dk,
-                           uint32_t *__restrict__ dv) {
-    uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= ms) return;
-    uint32_t rx = rank[sx[s]], ry = rank[sy[s]];
-    uint32_t a = rx < ry ? rx : ry, b = rx < ry ? ry : rx;
-    dk[s] = ((uint64_t)a << 32) | b;
-    dv[s] = (uint32_t)s;
+// Lanes with equal keys in consecutive lanes form runs; the first lane of a run adds the run's
+// length to ctr[key] with one atomic, and each lane gets the old value plus its offset in the run.
+__device__ __forceinline__ uint32_t run_add(uint32_t *ctr, uint32_t key, bool active, unsigned lane) {
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool prev_active = __shfl_up(active ? 1 : 0, 1, 64) != 0;
+    const bool head = active && (lane == 0 || !prev_active || prev != key);
+    const uint64_t heads = __ballot(head), acts = __ballot(active);
+    const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
+    const uint64_t mine = heads & upto;
+    const unsigned start = mine ? 63 - __clzll(mine) : 0;
+    // the run ends at the next head or inactive lane
+    const uint64_t stops = (heads | ~acts) & ~upto;
+    const unsigned end = stops ? (unsigned)__ffsll((unsigned long long)stops) - 1 : 64;
+    uint32_t old = 0;
+    if (head) old = atomicAdd(&ctr[key], end - start);
+    old = __shfl(old, start, 64);
+    return old + (lane - start);
 }
 
-// DAG edge d (in (tail, head) order) is pair s = dv[d]: its head rank, the pair's DAG id and
-// direction swap, the sizes of its two direction groups, and the CSR rows: the edges being sorted
-// by tail, dag_row[u] for every u in (tail of d - 1, tail of d] is d (d = ms closes the array)
-__global__ void k_dag_fill(uint64_t ms, uint32_t n, const uint64_t *__restrict__ dk,
-                           const uint32_t *__restrict__ dv, const uint32_t *__restrict__ sx,
-                           const uint32_t *__restrict__ rank, const uint32_t *__restrict__ pstart,
-                           const uint32_t *__restrict__ c1, uint32_t *__restrict__ dag_col,
-                           uint32_t *__restrict__ dag_of, uint8_t *__restrict__ sflip,
-                           uint32_t *__restrict__ dag_row, uint32_t *__restrict__ gsize) {
-    uint64_t d = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (d > ms) return;
-    const uint32_t tail = d < ms ? (uint32_t)(dk[d] >> 32) : n;
-    const int64_t prev = d > 0 ? (int64_t)(dk[d - 1] >> 32) : -1;
-    for (int64_t u = prev + 1; u <= (int64_t)tail; ++u) dag_row[u] = (uint32_t)d;
-    if (d == ms) return;
-    const uint64_t k = dk[d];
-    const uint32_t s = dv[d];
-    dag_col[d] = (uint32_t)k;
-    dag_of[s] = (uint32_t)d;
-    // pdir = 0 means sx -> sy; the DAG tail is sx unless sx has the larger rank
-    const uint32_t flip = rank[sx[s]] != tail ? 1u : 0u;
-    sflip[s] = (uint8_t)flip;
-    const uint32_t ps = pstart[s], pe = pstart[s + 1];
-    const uint32_t n1 = c1[pe] - c1[ps], n0 = (pe - ps) - n1;
-    gsize[2 * d] = flip ? n1 : n0;       // tail -> head
-    gsize[2 * d + 1] = flip ? n0 : n1;   // head -> tail
+// out-degree of every rank (each static pair points from its lower-ranked end), and per pair its
+// (tail, head) ranks and whether the DAG direction swaps the pair's (sx -> sy) direction
+__global__ void k_dag_count(uint64_t ms, const uint32_t *__restrict__ sx, const uint32_t *__restrict__ sy,
+                            const uint32_t *__restrict__ rank, uint32_t *__restrict__ outdeg,
+                            uint2 *__restrict__ th, uint8_t *__restrict__ sflip) {
+    const uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool act = s < ms;
+    uint32_t tail = 0;
+    if (act) {
+        const uint32_t ra = rank[sx[s]], rb = rank[sy[s]];
+        tail = ra < rb ? ra : rb;
+        th[s] = make_uint2(tail, ra < rb ? rb : ra);
+        sflip[s] = ra < rb ? 0 : 1;
+    }
+    (void)run_add(outdeg, tail, act, threadIdx.x & 63);
+}
+
+// every pair into its tail's run (unordered) as (head rank, pair id, edges tail -> head,
+// edges head -> tail)
+__global__ void k_dag_place(uint64_t ms, const uint2 *__restrict__ th, const uint8_t *__restrict__ sflip,
+                            const uint32_t *__restrict__ pstart, const uint32_t *__restrict__ c1,
+                            const uint32_t *__restrict__ dag_row, uint32_t *__restrict__ cursor,
+                            uint4 *__restrict__ runs) {
+    const uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool act = s < ms;
+    uint2 e = make_uint2(0, 0);
+    if (act) e = th[s];
+    const uint32_t off = run_add(cursor, e.x, act, threadIdx.x & 63);
+    if (act) {
+        const uint32_t ps = pstart[s], pe = pstart[s + 1];
+        const uint32_t n1 = c1[pe] - c1[ps], n0 = (pe - ps) - n1;   // pdir 1: sy -> sx
+        const bool flip = sflip[s] != 0;
+        runs[dag_row[e.x] + off] = make_uint4(e.y, (uint32_t)s, flip ? n1 : n0, flip ? n0 : n1);
+    }
+}
+
+// DAG edge d: its head, its pair's DAG id, and the sizes of its two direction groups
+__device__ __forceinline__ void dag_edge(uint64_t d, uint4 r, uint32_t *__restrict__ dag_col,
+                                         uint32_t *__restrict__ dag_of, uint32_t *__restrict__ gsize) {
+    dag_col[d] = r.x;
+    dag_of[r.y] = (uint32_t)d;
+    gsize[2 * d] = r.z;
+    gsize[2 * d + 1] = r.w;
+}
+
+// Sort every run by head rank (heads are distinct).  Wavefronts take chunks of kTailChunk tails
+// from a work counter; runs that fit together in 64 lanes are loaded in one piece and sorted at
+// once by a bitonic network on (run, head).  Longer runs go to a list for k_dag_sort_long.
+constexpr uint32_t kTailChunk = 64;
+
+__global__ void __launch_bounds__(kBlock)
+k_dag_sort(uint32_t n, const uint32_t *__restrict__ dag_row, const uint4 *__restrict__ runs,
+           uint32_t *__restrict__ dag_col, uint32_t *__restrict__ dag_of, uint32_t *__restrict__ gsize,
+           unsigned *__restrict__ next_chunk, unsigned *__restrict__ n_long, uint32_t *__restrict__ longs) {
+    const unsigned lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(next_chunk, kTailChunk);
+        t0 = __shfl(t0, 0, 64);
+        if (t0 >= n) break;
+        const uint32_t t1 = t0 + kTailChunk < n ? t0 + kTailChunk : n;
+        uint32_t r = t0;
+        while (r < t1) {
+            const uint32_t b = dag_row[r];
+            // lane l: end of run r + l (relative to b) if that tail is in the chunk
+            const uint32_t endl = r + lane < t1 ? dag_row[r + lane + 1] - b : 0xffffffffu;
+            const uint64_t fits = __ballot(endl <= 64);
+            const uint32_t cnt = fits == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~fits) - 1;
+            if (cnt == 0) {   // run r alone exceeds 64
+                if (lane == 0) longs[atomicAdd(n_long, 1u)] = r;
+                r += 1;
+                continue;
+            }
+            const uint32_t len = __shfl(endl, cnt - 1, 64);
+            // run of lane x: the number of runs ending at or before x
+            uint32_t seg = 0;
+            for (uint32_t q = 0; q < cnt; ++q) seg += __shfl(endl, q, 64) <= lane ? 1u : 0u;
+            uint4 rec = make_uint4(0xffffffffu, 0, 0, 0);
+            uint64_t key = ~0ull;
+            if (lane < len) {
+                rec = runs[b + lane];
+                key = ((uint64_t)seg << 32) | rec.x;
+            }
+#pragma unroll
+            for (unsigned k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+                for (unsigned j = k >> 1; j > 0; j >>= 1) {
+                    const uint64_t ok = __shfl_xor(key, j, 64);
+                    const uint32_t o0 = __shfl_xor(rec.x, j, 64), o1 = __shfl_xor(rec.y, j, 64),
+                                   o2 = __shfl_xor(rec.z, j, 64), o3 = __shfl_xor(rec.w, j, 64);
+                    const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
+                    const bool other = take_min ? ok < key : key < ok;
+                    if (other) {
+                        key = ok;
+                        rec = make_uint4(o0, o1, o2, o3);
+                    }
+                }
+            }
+            if (lane < len) dag_edge(b + lane, rec, dag_col, dag_of, gsize);
+            r += cnt;
+        }
+    }
+}
+
+// Runs longer than 64: one workgroup per run, a bitonic sort of (head, index) keys in LDS (runs
+// past kLongCap entries, beyond any degeneracy met in practice, are ranked in global memory).
+constexpr uint32_t kLongCap = 2048;
+
+__global__ void __launch_bounds__(kBlock)
+k_dag_sort_long(const unsigned *__restrict__ n_long_p, const uint32_t *__restrict__ longs,
+                const uint32_t *__restrict__ dag_row, const uint4 *__restrict__ runs,
+                uint32_t *__restrict__ dag_col, uint32_t *__restrict__ dag_of, uint32_t *__restrict__ gsize) {
+    __shared__ uint64_t sk[kLongCap];
+    const unsigned n_long = *n_long_p;
+    for (unsigned li = blockIdx.x; li < n_long; li += gridDim.x) {
+        const uint32_t r = longs[li];
+        const uint32_t b = dag_row[r], L = dag_row[r + 1] - b;
+        if (L <= kLongCap) {
+            uint32_t P = 64;
+            while (P < L) P <<= 1;
+            for (uint32_t i = threadIdx.x; i < P; i += kBlock)
+                sk[i] = i < L ? ((uint64_t)runs[b + i].x << 32) | i : ~0ull;
+            __syncthreads();
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+                        const uint32_t p = i ^ j;
+                        if (p > i) {
+                            const uint64_t x = sk[i], y = sk[p];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                sk[i] = y;
+                                sk[p] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < L; i += kBlock)
+                dag_edge(b + i, runs[b + (uint32_t)sk[i]], dag_col, dag_of, gsize);
+            __syncthreads();
+        } else {
+            for (uint32_t i = threadIdx.x; i < L; i += kBlock) {
+                const uint32_t h = runs[b + i].x;
+                uint32_t pos = 0;
+                for (uint32_t j = 0; j < L; ++j) pos += runs[b + j].x < h ? 1u : 0u;
+                dag_edge(b + pos, runs[b + i], dag_col, dag_of, gsize);
+            }
+        }
+    }
 }
 
 // largest out-degree: max of row[i + 1] - row[i] over i < n
@@ -88,12 +224,6 @@ __global__ void k_relayout(uint64_t m, const uint32_t *__restrict__ psid, const 
     key[eoff[g] + r] = pkey[k];
 }
 
-int bits_for(uint64_t x) {
-    int b = 1;
-    while (b < 64 && (1ull << b) < x) b++;
-    return b;
-}
-
 }  // namespace
 
 int orient(dt_graph *g) {
@@ -101,12 +231,13 @@ int orient(dt_graph *g) {
     hipStream_t st = ctx->stream;
     const uint64_t ms = g->m_s, m = g->m;
     const uint32_t n = g->n;
-    DevMem dk, dv, dk2, dv2, dag_of, sflip, gsize, scal;
+    DevMem outdeg, cursor, th, runs, longs, dag_of, sflip, gsize, scal;
     const uint64_t ngroups = 2 * ms;
-    DT_TRY(dev_alloc(ctx, dk, ms * 8));
-    DT_TRY(dev_alloc(ctx, dv, ms * 4));
-    DT_TRY(dev_alloc(ctx, dk2, ms * 8));
-    DT_TRY(dev_alloc(ctx, dv2, ms * 4));
+    DT_TRY(dev_alloc(ctx, outdeg, ((uint64_t)n + 1) * 4));
+    DT_TRY(dev_alloc(ctx, cursor, ((uint64_t)n + 1) * 4));
+    DT_TRY(dev_alloc(ctx, th, ms * 8));
+    DT_TRY(dev_alloc(ctx, runs, ms * 16));
+    DT_TRY(dev_alloc(ctx, longs, ((uint64_t)n + 1) * 4));
     DT_TRY(dev_alloc(ctx, dag_of, ms * 4));
     DT_TRY(dev_alloc(ctx, sflip, ms));
     DT_TRY(dev_alloc(ctx, gsize, (ngroups + 1) * 4));
@@ -115,21 +246,30 @@ int orient(dt_graph *g) {
     DT_TRY(dev_alloc(ctx, g->eoff, (ngroups + 1) * 4));
     DT_TRY(dev_alloc(ctx, g->key, m * 8));
     DT_TRY(dev_alloc(ctx, scal, 256));
+    DT_HIP(hipMemsetAsync(outdeg.ptr, 0, ((uint64_t)n + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(cursor.ptr, 0, ((uint64_t)n + 1) * 4, st));
     DT_HIP(hipMemsetAsync(gsize.ptr, 0, (ngroups + 1) * 4, st));
     DT_HIP(hipMemsetAsync(scal.ptr, 0, 256, st));
     if (ms) {
-        k_dag_keys<<<grid_for(ms, kBlock), kBlock, 0, st>>>(ms, g->sx.as<uint32_t>(), g->sy.as<uint32_t>(),
-                                                            g->rank.as<uint32_t>(), dk.as<uint64_t>(),
-                                                            dv.as<uint32_t>());
+        k_dag_count<<<grid_for(ms, kBlock), kBlock, 0, st>>>(ms, g->sx.as<uint32_t>(), g->sy.as<uint32_t>(),
+            g->rank.as<uint32_t>(), outdeg.as<uint32_t>(), th.as<uint2>(), sflip.as<uint8_t>());
         DT_HIP(hipGetLastError());
-        DT_TRY(sort_pairs_u64_u32(ctx, dk.as<uint64_t>(), dk2.as<uint64_t>(), dv.as<uint32_t>(),
-                                  dv2.as<uint32_t>(), ms, 32 + bits_for((uint64_t)n + 1), st));
     }
-    k_dag_fill<<<grid_for(ms + 1, kBlock), kBlock, 0, st>>>(
-        ms, n, dk2.as<uint64_t>(), dv2.as<uint32_t>(), g->sx.as<uint32_t>(), g->rank.as<uint32_t>(),
-        g->pstart.as<uint32_t>(), g->c1.as<uint32_t>(), g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(),
-        sflip.as<uint8_t>(), g->dag_row.as<uint32_t>(), gsize.as<uint32_t>());
-    DT_HIP(hipGetLastError());
+    DT_TRY(exclusive_scan_u32(ctx, outdeg.as<uint32_t>(), g->dag_row.as<uint32_t>(), (uint64_t)n + 1, st));
+    if (ms) {
+        k_dag_place<<<grid_for(ms, kBlock), kBlock, 0, st>>>(ms, th.as<uint2>(), sflip.as<uint8_t>(),
+            g->pstart.as<uint32_t>(), g->c1.as<uint32_t>(), g->dag_row.as<uint32_t>(), cursor.as<uint32_t>(),
+            runs.as<uint4>());
+        DT_HIP(hipGetLastError());
+        k_dag_sort<<<(unsigned)ctx->num_cus * 8, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), runs.as<uint4>(),
+            g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(), gsize.as<uint32_t>(), scal.as<unsigned>() + 8,
+            scal.as<unsigned>() + 16, longs.as<uint32_t>());
+        DT_HIP(hipGetLastError());
+        k_dag_sort_long<<<(unsigned)ctx->num_cus * 4, kBlock, 0, st>>>(scal.as<unsigned>() + 16, longs.as<uint32_t>(),
+            g->dag_row.as<uint32_t>(), runs.as<uint4>(), g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(),
+            gsize.as<uint32_t>());
+        DT_HIP(hipGetLastError());
+    }
     if (n) {
         unsigned grid = grid_for(n, kBlock);
         if (grid > 2048) grid = 2048;

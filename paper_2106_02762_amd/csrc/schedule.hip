@@ -128,13 +128,13 @@ __device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint3
 }
 
 // Every triangle to its class's list at base[class][block] + its rank in the block's walk; unit
-// triangles become records (in triangle order) and are counted per t1 bucket.
+// triangles become records (in triangle order) with their t1 bucket as a sort key.
 __global__ void __launch_bounds__(kBlock)
 k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__restrict__ cls,
             const uint64_t *__restrict__ base, const uint32_t *__restrict__ eoff,
             const uint64_t *__restrict__ key, int shift, int bshift, uint32_t *__restrict__ light,
             uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy, uint4 *__restrict__ urec,
-            uint32_t *__restrict__ ucount) {
+            uint16_t *__restrict__ ubkt) {
     __shared__ unsigned long long s_wave[kBlock / 64];
     const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
     uint64_t run[4] = {base[4 * blockIdx.x], base[4 * blockIdx.x + 1], base[4 * blockIdx.x + 2],
@@ -165,7 +165,7 @@ k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__r
             if (k == 3) {
                 const uint4 r = unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
                 urec[pos] = r;
-                atomicAdd(&ucount[r.x >> bshift], 1u);
+                ubkt[pos] = (uint16_t)(r.x >> bshift);
             } else {
                 uint32_t *dst = (k == 0 ? light : (k == 1 ? medium : heavy)) + 3 * pos;
                 dst[0] = e_uv;
@@ -178,15 +178,15 @@ k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__r
     }
 }
 
-// records grouped by t1 bucket (order inside a bucket unspecified)
-__global__ void k_unit_scatter(uint64_t nu, const uint4 *__restrict__ src, int bshift,
-                               const uint32_t *__restrict__ ustart, uint32_t *__restrict__ ucur,
-                               uint4 *__restrict__ dst) {
+// bucket starts from the sorted bucket keys: start[x] for every x in (key[j - 1], key[j]] is j;
+// j = nu closes the array at nbk
+__global__ void k_unit_starts(uint64_t nu, uint32_t nbk, const uint16_t *__restrict__ bkt,
+                              uint32_t *__restrict__ start) {
     uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nu) return;
-    const uint4 r = src[j];
-    const uint32_t b = r.x >> bshift;
-    dst[ustart[b] + atomicAdd(&ucur[b], 1u)] = r;
+    if (j > nu) return;
+    const int64_t cur = j < nu ? (int64_t)bkt[j] : (int64_t)nbk;
+    const int64_t prev = j > 0 ? (int64_t)bkt[j - 1] : -1;
+    for (int64_t x = prev + 1; x <= cur; ++x) start[x] = (uint32_t)j;
 }
 
 // work items of the medium path: ceil(P / kMediumChunk) per triangle
@@ -293,27 +293,26 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     while (t_bits < 31 && (1ll << t_bits) <= g->span) ++t_bits;
     S.unit_shift = t_bits > 16 ? t_bits - 16 : 0;
     const uint64_t nbk = unit_ok ? ((uint64_t)g->span >> S.unit_shift) + 1 : 1;
-    DevMem urec, ucount, ucur;
+    DevMem urec, ubkt, ubkt2, ustart;
     DT_TRY(dev_alloc(ctx, urec, nu * sizeof(uint4)));
-    DT_TRY(dev_alloc(ctx, ucount, (nbk + 1) * 4));
-    DT_TRY(dev_alloc(ctx, ucur, (nbk + 1) * 4));
-    DT_HIP(hipMemsetAsync(ucount.ptr, 0, (nbk + 1) * 4, st));
-    DT_HIP(hipMemsetAsync(ucur.ptr, 0, (nbk + 1) * 4, st));
+    DT_TRY(dev_alloc(ctx, ubkt, nu * 2));
     if (nt) {
         k_partition<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), cls.as<uint8_t>(), base.as<uint64_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, S.unit_shift, S.light.as<uint32_t>(),
-            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), urec.as<uint4>(), ucount.as<uint32_t>());
+            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), urec.as<uint4>(), ubkt.as<uint16_t>());
         DT_HIP(hipGetLastError());
     }
     cls.reset();
-    // unit records grouped by t1 bucket; the host keeps the bucket starts
+    // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket); the
+    // host keeps the bucket starts
     if (nu) {
-        DevMem ustart;
-        DT_TRY(dev_alloc(ctx, ustart, (nbk + 1) * 4));
-        DT_TRY(exclusive_scan_u32(ctx, ucount.as<uint32_t>(), ustart.as<uint32_t>(), nbk + 1, st));
+        DT_TRY(dev_alloc(ctx, ubkt2, nu * 2));
         DT_TRY(dev_alloc(ctx, S.unit, nu * sizeof(uint4)));
-        k_unit_scatter<<<grid_for(nu, kBlock), kBlock, 0, st>>>(nu, urec.as<uint4>(), S.unit_shift,
-            ustart.as<uint32_t>(), ucur.as<uint32_t>(), S.unit.as<uint4>());
+        DT_TRY(sort_pairs_u16_u4(ctx, ubkt.as<uint16_t>(), ubkt2.as<uint16_t>(), urec.as<uint4>(), S.unit.as<uint4>(),
+                                 nu, 16, st));
+        DT_TRY(dev_alloc(ctx, ustart, (nbk + 1) * 4));
+        k_unit_starts<<<grid_for(nu + 1, kBlock), kBlock, 0, st>>>(nu, (uint32_t)nbk, ubkt2.as<uint16_t>(),
+                                                                   ustart.as<uint32_t>());
         DT_HIP(hipGetLastError());
         S.unit_index.resize(nbk + 1);
         DT_HIP(hipMemcpyAsync(S.unit_index.data(), ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, st));

@@ -170,6 +170,17 @@ int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
     return DT_OK;
 }
 
+int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const uint4 *vin, uint4 *vout,
+                      size_t n, int end_bit, hipStream_t s) {
+    if (n == 0) return DT_OK;
+    size_t bytes = 0;
+    DT_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, n, 0u, (unsigned)end_bit, s));
+    DevMem tmp;
+    DT_TRY(dev_alloc(ctx, tmp, bytes));
+    DT_HIP(rocprim::radix_sort_pairs(tmp.ptr, bytes, kin, kout, vin, vout, n, 0u, (unsigned)end_bit, s));
+    return DT_OK;
+}
+
 int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s) {
     if (n == 0) return DT_OK;
     size_t bytes = 0;
