@@ -14,9 +14,10 @@
 // separated by grid barriers instead of kernel launches and host round trips, since power-law
 // graphs need thousands of rounds, most with frontiers of a few vertices.  A barrier's cost grows
 // with the number of blocks that meet at it, so the grid is small and wide (32 blocks of 1024
-// threads), and the barrier is a counter whose last arriving block also snapshots the queue and
-// survivor counters before it releases the others: each round then needs one barrier, and every
-// block takes the same branch because all decisions use the snapshot.  A vertex is queued at most
+// threads), and the barrier is a monotonic arrival counter that every block polls.  Counters that
+// decide the next step (queue positions taken in a phase, survivors of a level scan) rotate over
+// three slots, so a fast block starting the next phase never changes what a slow block reads, and
+// every block takes the same branch.  A vertex is queued at most
 // once: by the level scan when its degree is <= k (no decrement runs during a scan), or by the
 // single decrement that takes its degree from k + 1 to k (degrees only fall, and a queued vertex
 // already has degree <= k, so no later decrement can see k + 1 again); a vertex queued by a
@@ -46,17 +47,15 @@ constexpr long kSpinLimit = 1l << 26;
 constexpr int kRemoved = -(1 << 30);
 
 struct PeelCtl {
-    unsigned int qtail;      // vertices queued so far (positions in the ordering)
-    unsigned int n_alive2;   // survivors of the current level scan
-    unsigned int min_deg;    // smallest degree among those survivors
-    unsigned int arrived;    // barrier arrivals
-    unsigned int gen;        // barrier generation
-    unsigned int error;      // a barrier gave up waiting
+    unsigned int qtail;      // vertices queued in all (written at the end)
+    unsigned int qc[3];      // per grid phase mod 3: queue positions taken in that phase
+    unsigned int arrived;    // barrier arrivals (only ever increases)
+    unsigned int error;      // a barrier gave up waiting, or a consistency check failed
     unsigned int rounds;     // removal rounds
     unsigned int kappa;      // largest level that removed a vertex
-    unsigned long long lres; // hand-over: local ids (low word) and adjacency entries (high word) given out
     unsigned int nlvl;       // levels recorded by the one-workgroup finish
-    unsigned int snap[2][4]; // per generation parity: qtail, n_alive2, min_deg at the release
+    unsigned long long lres; // hand-over: local ids (low word) and adjacency entries (high word) given out
+    unsigned int scan[3][2]; // per level mod 3: survivors of the level scan, their smallest degree
 };
 
 __device__ __forceinline__ unsigned ld_relaxed(const unsigned *p) {
@@ -66,43 +65,31 @@ __device__ __forceinline__ int ld_relaxed(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier; returns the snapshot taken by the last block to arrive.  With reset_scan the
-// survivor counters are cleared after the snapshot, ready for the next level scan.
-__device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, bool reset_scan, unsigned snap[3]) {
-    __shared__ unsigned s_gen;
+// Grid barrier number `gen` (every block calls barriers 0, 1, 2, ... in the same order).  Arrivals
+// only ever increase, so barrier gen is complete once nblk * (gen + 1) blocks have arrived: each
+// block's first thread publishes its block's writes, arrives, and polls the count; no block has to
+// release the others.  A barrier that waits far longer than any peel could take sets an error
+// flag and lets its block go.
+__device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, unsigned gen) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned my = __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = nblk * (gen + 1);
         __threadfence();
-        const unsigned arrived = atomicAdd(&ctl->arrived, 1u) + 1;
-        if (arrived == nblk) {
-            const unsigned par = my & 1u;
-            ctl->snap[par][0] = ld_relaxed(&ctl->qtail);
-            ctl->snap[par][1] = ld_relaxed(&ctl->n_alive2);
-            ctl->snap[par][2] = ld_relaxed(&ctl->min_deg);
-            if (reset_scan) {
-                __hip_atomic_store(&ctl->n_alive2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&ctl->min_deg, 0xffffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            __hip_atomic_store(&ctl->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        const unsigned a = atomicAdd(&ctl->arrived, 1u) + 1;
+        if (a < target) {
             long spins = 0;
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
+            while (__hip_atomic_load(&ctl->arrived, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > kSpinLimit) {
                     atomicOr(&ctl->error, 1u);
                     break;
                 }
             }
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        s_gen = my;
     }
     __syncthreads();
-    const unsigned par = s_gen & 1u;
-    snap[0] = ld_relaxed(&ctl->snap[par][0]);
-    snap[1] = ld_relaxed(&ctl->snap[par][1]);
-    snap[2] = ld_relaxed(&ctl->snap[par][2]);
 }
 
 // A vertex whose degree a removal took from k + 1 to k joins the block's staging list; the block
@@ -110,15 +97,15 @@ __device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, bool reset_scan, unsig
 // vertices queued in one round is a valid ordering: each has at most k neighbours that are not
 // removed before the round ends).  A full staging list sends the rest straight to the queue.
 __device__ __forceinline__ void enqueue(uint32_t v, uint32_t k, uint32_t n, uint32_t *level,
-                                        uint32_t *queue, int *deg, PeelCtl *ctl, uint32_t *s_stage,
-                                        unsigned *s_cnt) {
+                                        uint32_t *queue, int *deg, unsigned *qc, uint32_t qbase,
+                                        uint32_t *s_stage, unsigned *s_cnt) {
     level[v] = k;
     __hip_atomic_store(&deg[v], kRemoved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t p = atomicAdd(s_cnt, 1u);
     if (p < kStage) {
         s_stage[p] = v;
     } else {
-        const uint32_t q = atomicAdd(&ctl->qtail, 1u);
+        const uint32_t q = qbase + atomicAdd(qc, 1u);
         if (q < n) queue[q] = v;
     }
 }
@@ -136,7 +123,8 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
                                              uint32_t n, const uint32_t *__restrict__ row,
                                              const uint32_t *__restrict__ col, int *__restrict__ deg,
                                              uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
-                                             PeelCtl *ctl, uint32_t *s_stage, unsigned *s_cnt) {
+                                             unsigned *qc, uint32_t qbase, uint32_t *s_stage,
+                                             unsigned *s_cnt) {
     const uint32_t e = row[v + 1];
     uint32_t j = row[v] + first;
     // four independent decrements in flight per lane
@@ -144,15 +132,15 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
         const uint32_t x0 = col[j], x1 = col[j + stride], x2 = col[j + 2 * stride], x3 = col[j + 3 * stride];
         const int o0 = atomicSub(&deg[x0], 1), o1 = atomicSub(&deg[x1], 1), o2 = atomicSub(&deg[x2], 1),
                   o3 = atomicSub(&deg[x3], 1);
-        if (o0 == (int)k + 1) enqueue(x0, k, n, level, queue, deg, ctl, s_stage, s_cnt);
-        if (o1 == (int)k + 1) enqueue(x1, k, n, level, queue, deg, ctl, s_stage, s_cnt);
-        if (o2 == (int)k + 1) enqueue(x2, k, n, level, queue, deg, ctl, s_stage, s_cnt);
-        if (o3 == (int)k + 1) enqueue(x3, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+        if (o0 == (int)k + 1) enqueue(x0, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
+        if (o1 == (int)k + 1) enqueue(x1, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
+        if (o2 == (int)k + 1) enqueue(x2, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
+        if (o3 == (int)k + 1) enqueue(x3, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
     }
     for (; j < e; j += stride) {
         const uint32_t x = col[j];
         const int old = atomicSub(&deg[x], 1);
-        if (old == (int)k + 1) enqueue(x, k, n, level, queue, deg, ctl, s_stage, s_cnt);
+        if (old == (int)k + 1) enqueue(x, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
     }
 }
 
@@ -314,7 +302,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     const uint32_t gsize = nblk * kBlock;
     const uint32_t gwave = gtid / 64, nwaves = gsize / 64, lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1;
-    unsigned snap[3];
+    unsigned bgen = 0;   // barriers passed
     __shared__ __attribute__((aligned(16))) uint32_t s_mem[kLdsWords];
     __shared__ unsigned s_cnt, s_base;
 
@@ -325,9 +313,14 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         alive_a[v] = v;
         loc[v] = kUnset;
     }
-    grid_barrier(ctl, nblk, true, snap);
+    if (gtid == 0)
+        for (int x = 0; x < 3; ++x) ctl->scan[x][1] = 0xffffffffu;
+    grid_barrier(ctl, nblk, bgen++);
 
-    uint32_t k = 0, head = 0, tail = 0, n_alive = n, prev_tail = 0, rounds = 0;
+    // tail: vertices queued before the current grid phase (a scan or a round); phase ph takes its
+    // queue positions tail + [0, qc[ph % 3]) and every block adds the final count after the phase's
+    // barrier, so all blocks agree on tail although a fast block may already be in the next phase
+    uint32_t k = 0, head = 0, tail = 0, n_alive = n, prev_tail = 0, rounds = 0, lv = 0, ph = 0;
     uint32_t *cur = alive_a, *nxt = alive_b;
     bool done = false;
     // here every queued vertex has been removed: n - tail vertices remain
@@ -354,9 +347,9 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             mdl = wave_min(mdl);
             uint32_t qb = 0, kb = 0;
             if (lane == 0) {
-                if (ct) qb = atomicAdd(&ctl->qtail, ct);
-                if (ck) kb = atomicAdd(&ctl->n_alive2, ck);
-                if (mdl != 0xffffffffu) atomicMin(&ctl->min_deg, mdl);
+                if (ct) qb = tail + atomicAdd(&ctl->qc[ph % 3], ct);
+                if (ck) kb = atomicAdd(&ctl->scan[lv % 3][0], ck);
+                if (mdl != 0xffffffffu) atomicMin(&ctl->scan[lv % 3][1], mdl);
             }
             qb = __shfl(qb, 0, 64);
             kb = __shfl(kb, 0, 64);
@@ -382,9 +375,18 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
                 }
             }
         }
-        grid_barrier(ctl, nblk, true, snap);
-        tail = snap[0];
-        const uint32_t na2 = snap[1], md = snap[2];
+        grid_barrier(ctl, nblk, bgen++);
+        tail += ld_relaxed(&ctl->qc[ph % 3]);
+        const uint32_t na2 = ld_relaxed(&ctl->scan[lv % 3][0]), md = ld_relaxed(&ctl->scan[lv % 3][1]);
+        // the counters of the previous level were read by every block before this barrier: clear
+        // them for the level after next (the next level's barrier publishes the clearing)
+        if (gtid == 0) {
+            __hip_atomic_store(&ctl->scan[(lv + 2) % 3][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->scan[(lv + 2) % 3][1], 0xffffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->qc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++lv;
+        ++ph;
         // no survivors: every remaining vertex is queued at this level, and removing them can
         // queue nothing more
         if (na2 == 0) head = tail;
@@ -396,27 +398,30 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             const uint32_t f = tail - head;
             if (f >= nwaves) {
                 for (uint32_t i = head + gwave; i < tail; i += nwaves)
-                    remove_edges(queue[i], lane, 64, k, n, row, col, deg, level, queue, ctl, s_mem, &s_cnt);
+                    remove_edges(queue[i], lane, 64, k, n, row, col, deg, level, queue, &ctl->qc[ph % 3], tail,
+                                 s_mem, &s_cnt);
             } else {
                 const uint32_t per = nwaves / f;
                 const uint32_t i = gwave / per, sub = gwave % per;
                 if (i < f)
                     remove_edges(queue[head + i], sub * 64 + lane, per * 64, k, n, row, col, deg,
-                                 level, queue, ctl, s_mem, &s_cnt);
+                                 level, queue, &ctl->qc[ph % 3], tail, s_mem, &s_cnt);
             }
             // append the block's staged vertices to the queue
             __syncthreads();
             const uint32_t c = s_cnt < kStage ? s_cnt : kStage;
-            if (threadIdx.x == 0) s_base = c ? atomicAdd(&ctl->qtail, c) : 0u;
+            if (threadIdx.x == 0) s_base = c ? tail + atomicAdd(&ctl->qc[ph % 3], c) : 0u;
             __syncthreads();
             for (uint32_t x = threadIdx.x; x < c; x += kBlock) {
                 const uint32_t p = s_base + x;
                 if (p < n) queue[p] = s_mem[x];
             }
             ++rounds;
-            grid_barrier(ctl, nblk, false, snap);
+            grid_barrier(ctl, nblk, bgen++);
             head = tail;
-            tail = snap[0];
+            tail += ld_relaxed(&ctl->qc[ph % 3]);
+            if (gtid == 0) __hip_atomic_store(&ctl->qc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ++ph;
         }
         if (tail >= n || ld_relaxed(&ctl->error)) {
             done = true;
@@ -442,6 +447,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         if (gtid == 0) {
             ctl->kappa = k;
             ctl->rounds = rounds;
+            __hip_atomic_store(&ctl->qtail, tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
@@ -484,7 +490,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             }
         }
     }
-    grid_barrier(ctl, nblk, false, snap);
+    grid_barrier(ctl, nblk, bgen++);
     const unsigned long long lres = __hip_atomic_load(&ctl->lres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t R = (uint32_t)lres, total = (uint32_t)(lres >> 32);
     if (R != n - tail || R > kTail || total > lcol_cap || ld_relaxed(&ctl->error)) {
@@ -507,7 +513,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         }
         if (lane == 0 && c != d) atomicOr(&ctl->error, 4u);
     }
-    grid_barrier(ctl, nblk, false, snap);
+    grid_barrier(ctl, nblk, bgen++);
     if (blockIdx.x != 0 || ld_relaxed(&ctl->error)) return;
     peel_tail(R, tail, k, rounds, rlist, lrow, lcol, lvl, level, queue, ctl, s_mem);
 }
