@@ -28,7 +28,13 @@ constexpr unsigned kBlock = 256;
 constexpr unsigned kWaves = kBlock / 64;
 constexpr uint32_t kCap = 512;    // LDS entries of N+(u) (and of one N+(v)) per wavefront
 constexpr uint32_t kStage = 32;   // walks at least this long search an LDS copy of N+(v)
-constexpr uint32_t kChunk = 8;    // source vertices taken per grab of the work counter
+// Work grabs of one counter, heaviest (highest-ranked) source vertices first: the first kSplitU
+// vertices are split into kParts tickets each (part p takes every kParts-th block of 64 flattened
+// candidates and every kParts-th staged neighbour), the next kSingles are one ticket each, and
+// later tickets are kChunk vertices each.  No wavefront serialises the dense core.
+constexpr uint32_t kSplitU = 4096, kParts = 8;
+constexpr uint32_t kSingles = 16384;
+constexpr uint32_t kChunk = 16;
 constexpr uint32_t kOut = 192;    // triangles a wavefront buffers in LDS before appending them
 
 __device__ __forceinline__ uint32_t find_u32(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -114,11 +120,26 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     TriSink out{s_out[wave], 0, tri, cap, total};
     unsigned long long wave_cand = 0;   // candidates tested, added once per wave
     for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(next_u, kChunk);
-        base = __shfl(base, 0, 64);
-        if (base >= n) break;
-        const uint32_t last = base + kChunk < n ? base + kChunk : n;
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(next_u, 1u);
+        ticket = __shfl(ticket, 0, 64);
+        uint64_t b64;
+        uint32_t span, part = 0, parts = 1;
+        if (ticket < kSplitU * kParts) {
+            b64 = ticket / kParts;
+            part = ticket % kParts;
+            parts = kParts;
+            span = 1;
+        } else if (ticket < kSplitU * kParts + kSingles) {
+            b64 = kSplitU + (ticket - kSplitU * kParts);
+            span = 1;
+        } else {
+            b64 = kSplitU + kSingles + (uint64_t)(ticket - kSplitU * kParts - kSingles) * kChunk;
+            span = kChunk;
+        }
+        if (b64 >= n) break;
+        const uint32_t base = (uint32_t)b64;
+        const uint32_t last = base + span < n ? base + span : n;
         // highest rank first: the dense core, with the longest N+ runs, comes last in the ordering
         for (uint32_t ci = base; ci < last; ++ci) {
         const uint32_t u = n - 1 - ci;
@@ -154,12 +175,12 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
             carry += __shfl(x, 63, 64);
         }
         const uint32_t work = carry;
-        wave_cand += work;
+        if (part == 0) wave_cand += work;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         if (in_lds) {
-            for (uint32_t b = 0; b < work; b += 64) {
+            for (uint32_t b = part * 64; b < work; b += parts * 64) {
                 const uint32_t p = b + lane;
                 bool hit = false;
                 uint32_t i = 0, e_uw = 0, e_vw = 0;
@@ -186,7 +207,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 out.put(hit, __ballot(hit), lane, r0 + i, e_uw, e_vw);
             }
             // long walks into a long N+(v): copy N+(v) into LDS, then search it there
-            for (uint32_t i = 0; i + kStage < du; ++i) {
+            for (uint32_t i = part; i + kStage < du; i += parts) {
                 const uint32_t after = du - i - 1, outv = dv_lds[i];
                 if (!(outv > after && after >= kStage && outv <= kCap)) continue;
                 const uint32_t vb = vb_lds[i];
@@ -208,7 +229,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-        } else {
+        } else if (part == 0) {
             // N+(u) larger than the LDS slice: the same candidates, v by v, on global memory
             for (uint32_t i = 0; i + 1 < du; ++i) {
                 const uint32_t v = nbr[i];
