@@ -133,9 +133,19 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned_out, 64 * sizeof(int64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (c->ev_a) (void)hipEventDestroy(c->ev_a);
         if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+        for (int i = 0; i < 2; ++i) {
+            if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+            if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+        }
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return fail(DT_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
@@ -166,6 +176,12 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
     for (auto &e : ctx->prof_ev)
         if (e) (void)hipEventDestroy(e);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->side[i]) (void)hipStreamSynchronize(ctx->side[i]);
+        if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+        if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_a);
     (void)hipEventDestroy(ctx->ev_b);
     (void)hipStreamDestroy(ctx->stream);

@@ -59,7 +59,7 @@ k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
             for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri<false>(Q.light, i, Q.eoff, Q.key, Q.q, acc);
         } else {
             for (uint64_t j = I.b + wave; j < I.e; j += kBB / 64)
-                medium_item<false>(Q.medium, Q.mitems, j, Q.eoff, Q.key, Q.q, acc, lane);
+                medium_item<false>(Q.medium, Q.mitems, j, Q.eoff, Q.key, Q.q, acc, lane, nullptr);
         }
         block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
         __syncthreads();

@@ -54,12 +54,13 @@ __global__ void __launch_bounds__(BLOCK)
 k_medium(uint64_t n_items, const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
          const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, DQuery q,
          int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
+    __shared__ uint64_t s_vw[BLOCK / 64][kVwCap];
     Acc<CELLS> acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
     for (uint64_t it = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; it < n_items; it += W)
-        medium_item<CELLS>(med, items, it, eoff, key, q, acc, lane);
+        medium_item<CELLS>(med, items, it, eoff, key, q, acc, lane, s_vw[threadIdx.x / 64]);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -435,28 +436,44 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         k_zero<<<1, 64, 0, s>>>(48, cells_dev);
         DT_HIP(hipGetLastError());
     }
+    // The light and medium kernels are independent of the unit and heavy ones (each writes its own
+    // partial slots): when more than one path has work, they run on the context's side streams,
+    // forked from s here and joined back before the reduction, so their latency-bound tails overlap.
+    hipStream_t sl = s, sm = s;
+    const bool fork = ctx->side[0] && ((lg ? 1 : 0) + (mg ? 1 : 0) + ((ug || hg) ? 1 : 0)) >= 2;
+    if (fork) {
+        DT_HIP(hipEventRecord(ctx->ev_fork, s));
+        if (lg) {
+            DT_HIP(hipStreamWaitEvent(ctx->side[0], ctx->ev_fork, 0));
+            sl = ctx->side[0];
+        }
+        if (mg) {
+            DT_HIP(hipStreamWaitEvent(ctx->side[1], ctx->ev_fork, 0));
+            sm = ctx->side[1];
+        }
+    }
     if (lg) {
-        prof_begin(ctx, kProfLight, s);
+        prof_begin(ctx, kProfLight, sl);
         if (cells)
-            k_light<true, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
+            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(S.n_light, S.light.as<uint32_t>(),
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
         else
-            k_light<false, kLightBlock><<<lg, kLightBlock, 0, s>>>(S.n_light, S.light.as<uint32_t>(),
+            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(S.n_light, S.light.as<uint32_t>(),
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
-        prof_end(ctx, kProfLight, s);
+        prof_end(ctx, kProfLight, sl);
         DT_HIP(hipGetLastError());
     }
     if (mg) {
-        prof_begin(ctx, kProfMedium, s);
+        prof_begin(ctx, kProfMedium, sm);
         if (cells)
-            k_medium<true, 256><<<mg, 256, 0, s>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+            k_medium<true, 256><<<mg, 256, 0, sm>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
         else
-            k_medium<false, 256><<<mg, 256, 0, s>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+            k_medium<false, 256><<<mg, 256, 0, sm>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
-        prof_end(ctx, kProfMedium, s);
+        prof_end(ctx, kProfMedium, sm);
         DT_HIP(hipGetLastError());
     }
     if (ug) {
@@ -501,6 +518,16 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         }
         prof_end(ctx, kProfHeavyCount, s);
         DT_HIP(hipGetLastError());
+    }
+    if (fork) {
+        if (lg) {
+            DT_HIP(hipEventRecord(ctx->ev_join[0], sl));
+            DT_HIP(hipStreamWaitEvent(s, ctx->ev_join[0], 0));
+        }
+        if (mg) {
+            DT_HIP(hipEventRecord(ctx->ev_join[1], sm));
+            DT_HIP(hipStreamWaitEvent(s, ctx->ev_join[1], 0));
+        }
     }
     if (!cells) {
         prof_begin(ctx, kProfReduce, s);

@@ -192,17 +192,36 @@ __device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, co
     light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
 }
 
+// keys of the two {v,w} lists a medium work item may copy into LDS (per wavefront)
+constexpr uint32_t kVwCap = 512;
+
 // medium work item `it` = (triangle index into med, first pair); pairs enumerate the unclipped
-// uv and uw runs (each stored as direction 0 then direction 1), edges outside the window skipped
+// uv and uw runs (each stored as direction 0 then direction 1), edges outside the window skipped.
+// Every pair of the item searches the same two (window-clipped) {v,w} lists: when they fit, the
+// wavefront first copies them into its LDS slice vw_lds (when given) so those searches stay on chip.
 template <bool CELLS>
 __device__ __forceinline__ void medium_item(const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
                                             uint64_t it, const uint32_t *__restrict__ eoff,
                                             const uint64_t *__restrict__ key, const DQuery &q,
-                                            Acc<CELLS> &acc, unsigned lane) {
+                                            Acc<CELLS> &acc, unsigned lane, uint64_t *vw_lds) {
     const uint32_t t = items[2 * it], p0 = items[2 * it + 1];
     const uint32_t e_uv = med[3 * (uint64_t)t], e_uw = med[3 * (uint64_t)t + 1], e_vw = med[3 * (uint64_t)t + 2];
     Lists L;
     load_lists(eoff, e_uv, e_uw, e_vw, key, q, L);
+    const uint64_t *zkey = key;
+    const uint32_t n0 = L.hi[4] - L.lo[4], n1 = L.hi[5] - L.lo[5];
+    if (vw_lds && n0 + n1 <= kVwCap) {
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t j = lane; j < n0 + n1; j += 64)
+            vw_lds[j] = j < n0 ? key[L.lo[4] + j] : key[L.lo[5] + (j - n0)];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        L.lo[4] = 0;
+        L.hi[4] = n0;
+        L.lo[5] = n0;
+        L.hi[5] = n0 + n1;
+        zkey = vw_lds;
+    }
     const uint32_t a0 = eoff[2 * e_uv], a1 = eoff[2 * e_uv + 1], a2 = eoff[2 * e_uv + 2];
     const uint32_t b0 = eoff[2 * e_uw], b1 = eoff[2 * e_uw + 1], b2 = eoff[2 * e_uw + 2];
     const uint32_t su0 = a1 - a0, sw0 = b1 - b0, sw = b2 - b0;
@@ -213,12 +232,13 @@ __device__ __forceinline__ void medium_item(const uint32_t *__restrict__ med, co
         const uint64_t kx = key[a0 + a], ky = key[b0 + b];
         if (q.windowed && (kx < q.klo || kx >= q.khi || ky < q.klo || ky >= q.khi)) continue;
         switch ((a >= su0 ? 2 : 0) + (b >= sw0 ? 1 : 0)) {
-            case 0: medium_pair<CELLS, 0, 0>(key, L, q, kx, ky, acc); break;
-            case 1: medium_pair<CELLS, 0, 1>(key, L, q, kx, ky, acc); break;
-            case 2: medium_pair<CELLS, 1, 0>(key, L, q, kx, ky, acc); break;
-            default: medium_pair<CELLS, 1, 1>(key, L, q, kx, ky, acc); break;
+            case 0: medium_pair<CELLS, 0, 0>(zkey, L, q, kx, ky, acc); break;
+            case 1: medium_pair<CELLS, 0, 1>(zkey, L, q, kx, ky, acc); break;
+            case 2: medium_pair<CELLS, 1, 0>(zkey, L, q, kx, ky, acc); break;
+            default: medium_pair<CELLS, 1, 1>(zkey, L, q, kx, ky, acc); break;
         }
     }
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ---------------------------------------------------------------------------------------------

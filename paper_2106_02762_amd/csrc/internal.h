@@ -85,6 +85,9 @@ struct dt_ctx {
     uint32_t batch_light_chunk = 0;          // autotuned on first use (0 = not yet)
     int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
+    // a count's light and medium kernels run on these, forked from and joined to the count's stream
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     // optional per-kernel timing (dt_ctx_set_profiling)
     bool prof = false;
     hipEvent_t prof_ev[2 * DT_PROFILE_SLOTS] = {};
@@ -124,7 +127,7 @@ struct DQuery {
 };
 
 // (uv edge, uw edge) pairs per medium-path work item
-constexpr uint32_t kMediumChunk = 4096;
+constexpr uint32_t kMediumChunk = 1024;
 // Unit triangles: static triangles with exactly one temporal edge on each of their three pairs
 // (the common case in sparse interaction data).  Their ordering pi (Figure 3) and orientation rho
 // (Figure 4) do not depend on the query, so each is stored as one 16-byte record

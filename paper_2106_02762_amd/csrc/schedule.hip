@@ -21,14 +21,18 @@ __device__ __forceinline__ uint32_t ceil_log2_1(uint32_t s) {   // ceil(log2(s +
     return s == 0 ? 0 : 32 - __clz(s);
 }
 
-// class 0 light, 1 medium, 2 heavy, 3 unit; force: 0 by the caps, 1 light, 2 heavy, 3 medium
-__device__ __forceinline__ int tri_class(uint64_t P, uint64_t cap_l, uint64_t cap_m, uint32_t force,
-                                         bool unit) {
+// class 0 light, 1 medium, 2 heavy, 3 unit; force: 0 by the caps, 1 light, 2 heavy, 3 medium.
+// A light lane searches the {v,w} lists in global memory once per pair, so a triangle whose {v,w}
+// pair carries more than kLightVw edges goes to the medium path, whose wavefront shares those
+// searches' list from LDS.
+constexpr uint64_t kLightVw = 64;
+__device__ __forceinline__ int tri_class(uint64_t P, uint64_t s_vw, uint64_t cap_l, uint64_t cap_m,
+                                         uint32_t force, bool unit) {
     if (force == 0 && unit) return 3;
     if (force == 1) return 0;
     if (force == 2) return 2;
     if (force == 3) return P < (1ull << 31) ? 1 : 2;
-    return P <= cap_l ? 0 : (P <= cap_m ? 1 : 2);
+    return P <= cap_l && s_vw <= kLightVw ? 0 : (P <= cap_m ? 1 : 2);
 }
 
 constexpr int kPartWords = 6;   // per block: sum_sigma3 lo, hi, bytes, light, medium, unit bytes
@@ -54,7 +58,7 @@ k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__r
         const uint64_t s_uw = eoff[2 * e_uw + 2] - eoff[2 * e_uw];
         const uint32_t s_vw = eoff[2 * e_vw + 2] - eoff[2 * e_vw];
         const bool unit = unit_ok && s_uv == 1 && s_uw == 1 && s_vw == 1;
-        const int k = tri_class(s_uv * s_uw, cap_l, cap_m, force, unit);
+        const int k = tri_class(s_uv * s_uw, s_vw, cap_l, cap_m, force, unit);
         cls[i] = (uint8_t)k;
         c[0] += k == 0;
         c[1] += k == 1;
