@@ -3,7 +3,7 @@
 // The batch becomes one table of work items, each a bounded piece of one query's work: a run of
 // unit-triangle records, a run of light triangles (one lane per triangle) or a run of medium-path
 // items (one wavefront per item).  A windowed query's unit runs cover only the records whose
-// earliest time can fall in its window.
+// earliest time can fall in its window, its light and medium items only the window cells that can.
 // A persistent grid strides over the table, so graphs of very different sizes and queries with
 // different deltas and windows share the device evenly, and one launch serves the whole batch
 // whatever its composition.  Every item writes its own 8 partial sums (no atomics); a second
@@ -111,6 +111,7 @@ struct BatchRunner {
     uint64_t g_items = 0, g_q = 0;
     std::vector<std::pair<uint32_t, uint32_t>> heavy;   // (query, item slot)
     std::vector<std::pair<uint64_t, uint64_t>> uranges; // unit records of each query
+    std::vector<Ranges> lranges, mranges;              // light and medium parts of each query
     uint64_t n_items = 0, nq = 0;
 
     int init(dt_ctx *c) {
@@ -142,13 +143,22 @@ struct BatchRunner {
         heavy.clear();
         const uint64_t unit_chunk = 4 * (uint64_t)light_chunk;
         uranges.resize(k);
+        lranges.resize(k);
+        mranges.resize(k);
         uint64_t total = 0;
+        auto pieces = [](const Ranges &r, uint64_t len) {
+            uint64_t c = 0;
+            for (uint32_t j = 0; j < r.n; ++j) c += (r.pre[j + 1] - r.pre[j] + len - 1) / len;
+            return c;
+        };
         for (uint64_t i = 0; i < k; ++i) {
             if (empty[i]) continue;
             const Schedule &S = graphs[i]->sched;
             unit_range(graphs[i], qs[i], &uranges[i].first, &uranges[i].second);
-            total += (S.n_light + light_chunk - 1) / light_chunk + (S.n_mitems + kMediumGroup - 1) / kMediumGroup +
-                     (S.n_heavy ? 1 : 0) + (uranges[i].second - uranges[i].first + unit_chunk - 1) / unit_chunk;
+            cell_ranges(S.light_cells, S.cell_shift, qs[i], lranges[i]);
+            cell_ranges(S.mitem_cells, S.cell_shift, qs[i], mranges[i]);
+            total += pieces(lranges[i], light_chunk) + pieces(mranges[i], kMediumGroup) + (S.n_heavy ? 1 : 0) +
+                     (uranges[i].second - uranges[i].first + unit_chunk - 1) / unit_chunk;
         }
         if (total >= 0xffffffffull) return fail(DT_EOVERFLOW, "batch table too large");
         DT_TRY(host_grow(h_items, cap_h_items, total + 1));
@@ -160,17 +170,25 @@ struct BatchRunner {
             h_qfirst[i] = (uint32_t)n;
             dt_graph *g = graphs[i];
             const Schedule &S = g->sched;
-            h_q[i] = BQuery{S.light.as<uint32_t>(), S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+            const bool w = qs[i].windowed;
+            h_q[i] = BQuery{(w ? S.light_w : S.light).as<uint32_t>(), (w ? S.medium_w : S.medium).as<uint32_t>(),
+                            (w ? S.mitems_w : S.mitems).as<uint32_t>(),
                             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), S.unit.as<uint4>(), qs[i],
                             unit_query(qs[i])};
             if (empty[i]) continue;
             for (uint64_t b = uranges[i].first; b < uranges[i].second; b += unit_chunk)
                 h_items[n++] = BItem{(uint32_t)i, 3, (uint32_t)b,
                                      (uint32_t)std::min<uint64_t>(b + unit_chunk, uranges[i].second)};
-            for (uint64_t b = 0; b < S.n_light; b += light_chunk)
-                h_items[n++] = BItem{(uint32_t)i, 0, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + light_chunk, S.n_light)};
-            for (uint64_t b = 0; b < S.n_mitems; b += kMediumGroup)
-                h_items[n++] = BItem{(uint32_t)i, 1, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + kMediumGroup, S.n_mitems)};
+            // light triangles and medium items in the parts the query's window can see
+            auto add = [&](const Ranges &r, uint32_t kind, uint64_t len) {
+                for (uint32_t j = 0; j < r.n; ++j) {
+                    const uint64_t e = r.b[j] + (r.pre[j + 1] - r.pre[j]);
+                    for (uint64_t b = r.b[j]; b < e; b += len)
+                        h_items[n++] = BItem{(uint32_t)i, kind, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + len, e)};
+                }
+            };
+            add(lranges[i], 0, light_chunk);
+            add(mranges[i], 1, kMediumGroup);
             if (S.n_heavy) {
                 heavy.emplace_back((uint32_t)i, (uint32_t)n);
                 h_items[n++] = BItem{(uint32_t)i, 2, 0, 0};

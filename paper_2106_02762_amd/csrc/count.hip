@@ -22,6 +22,10 @@
 //    workgroups.  The formulas are the paper's, restated for keys (t, input index) so that equal
 //    timestamps are handled, with the region bounds written as max/min clamps.
 //
+// A query with a time window walks the windowed copies of the light and medium lists, ordered by
+// window cell, and only the cells that can hold a triangle inside its window (the unit records by
+// their first time likewise).
+//
 // Counts are int64 and summed per lane, per wave, per block, then per launch, with no atomics on
 // the result (cells mode, a diagnostic, uses atomics).
 #include "count_dev.h"
@@ -34,33 +38,38 @@ namespace {
 
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_light(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
         const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
         int64_t *__restrict__ cells) {
     Acc<CELLS> acc;
     acc.cells = cells;
+    const uint64_t n_tri = R.pre[R.n];
     const uint32_t nblk = gridDim.x;
     const uint32_t b = xcd_block(blockIdx.x, nblk);
     const uint64_t per = (n_tri + nblk - 1) / nblk;
     const uint64_t beg = (uint64_t)b * per;
     const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) light_tri<CELLS>(tri, i, eoff, key, q, acc);
+    uint32_t r = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
+        light_tri<CELLS>(tri, range_at(R, r, i), eoff, key, q, acc);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
 // medium path: wave w takes work items w, w + W, w + 2W, ... (each at most kMediumChunk pairs)
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_medium(uint64_t n_items, const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
+k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
          const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, DQuery q,
          int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
     __shared__ uint64_t s_vw[BLOCK / 64][kVwCap];
     Acc<CELLS> acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
+    const uint64_t n_items = R.pre[R.n];
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
+    uint32_t r = 0;
     for (uint64_t it = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; it < n_items; it += W)
-        medium_item<CELLS>(med, items, it, eoff, key, q, acc, lane, s_vw[threadIdx.x / 64]);
+        medium_item<CELLS>(med, items, range_at(R, r, it), eoff, key, q, acc, lane, s_vw[threadIdx.x / 64]);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -420,11 +429,19 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     dt_ctx *ctx = g->ctx;
     Schedule &S = g->sched;
     const bool do_light = parts & 1, do_medium = parts & 2, do_heavy = parts & 4;
-    const unsigned light_grid = (S.n_light && do_light) ? (unsigned)std::min<uint64_t>(
-        (S.n_light + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
+    // the parts of the light and medium lists a windowed query can see
+    Ranges lr, mr;
+    cell_ranges(S.light_cells, S.cell_shift, q, lr);
+    cell_ranges(S.mitem_cells, S.cell_shift, q, mr);
+    const uint64_t nl = lr.pre[lr.n], nmi = mr.pre[mr.n];
+    const uint32_t *light = (q.windowed ? S.light_w : S.light).as<uint32_t>();
+    const uint32_t *medium = (q.windowed ? S.medium_w : S.medium).as<uint32_t>();
+    const uint32_t *mitems = (q.windowed ? S.mitems_w : S.mitems).as<uint32_t>();
+    const unsigned light_grid = (nl && do_light) ? (unsigned)std::min<uint64_t>(
+        (nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
     const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
     const unsigned hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    const unsigned mg = (S.n_mitems && do_medium) ? (unsigned)std::min<uint64_t>((S.n_mitems + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
+    const unsigned mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
     uint64_t ub = 0, ue = 0;
     if (S.n_unit && (parts & 8)) unit_range(g, q, &ub, &ue);
     const unsigned ug = ue > ub ? (unsigned)std::min<uint64_t>((ue - ub + kUnitPerBlock - 1) / kUnitPerBlock,
@@ -455,10 +472,10 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     if (lg) {
         prof_begin(ctx, kProfLight, sl);
         if (cells)
-            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(S.n_light, S.light.as<uint32_t>(),
+            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(lr, light,
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
         else
-            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(S.n_light, S.light.as<uint32_t>(),
+            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(lr, light,
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
         prof_end(ctx, kProfLight, sl);
         DT_HIP(hipGetLastError());
@@ -466,11 +483,11 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     if (mg) {
         prof_begin(ctx, kProfMedium, sm);
         if (cells)
-            k_medium<true, 256><<<mg, 256, 0, sm>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+            k_medium<true, 256><<<mg, 256, 0, sm>>>(mr, medium, mitems,
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
         else
-            k_medium<false, 256><<<mg, 256, 0, sm>>>(S.n_mitems, S.medium.as<uint32_t>(), S.mitems.as<uint32_t>(),
+            k_medium<false, 256><<<mg, 256, 0, sm>>>(mr, medium, mitems,
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
         prof_end(ctx, kProfMedium, sm);

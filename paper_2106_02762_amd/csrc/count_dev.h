@@ -61,6 +61,13 @@ template <> struct Acc<true> {
     }
 };
 
+// position of element j of the ranges R (j < R.pre[R.n]); the cursor r only moves forward, so a
+// thread walking increasing j finds each range once
+__device__ __forceinline__ uint64_t range_at(const Ranges &R, uint32_t &r, uint64_t j) {
+    while (j >= R.pre[r + 1]) ++r;
+    return R.b[r] + (j - R.pre[r]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // searches on key-sorted lists
 // ---------------------------------------------------------------------------------------------

@@ -137,6 +137,22 @@ constexpr uint32_t kMediumChunk = 1024;
 // t1 bucket (t1 >> unit_shift, at most 2^16 buckets) so that a window selects a contiguous range;
 // the host keeps the bucket starts.
 constexpr int64_t kUnitMaxSpan = (int64_t(1) << 31) - 1;
+// Window index of the light and medium lists.  A triangle can hold a temporal triangle inside a
+// window [lo, hi] only if each of its three pairs has an edge inside it, that is only if
+// F <= hi and L >= lo, where F is the latest of the three pairs' first edge times and L the
+// earliest of their last edge times.  Both are cut into kSlices time slices (relative time
+// >> cell_shift, the last slice open-ended) and the lists are ordered by cell
+// slice(F) * kSlices + slice(L), so a window selects at most kSlices contiguous ranges: for every
+// slice f <= slice(hi), the cells (f, l) with l >= slice(lo).
+constexpr int kSliceBits = 5;
+constexpr uint32_t kSlices = 1u << kSliceBits;
+constexpr uint32_t kCells = kSlices * kSlices;
+// up to kSlices ranges [b[r], b[r] + pre[r + 1] - pre[r]) of a list; pre[0] = 0, pre[n] = total
+struct Ranges {
+    uint32_t n;
+    uint64_t b[kSlices];
+    uint64_t pre[kSlices + 1];
+};
 
 // ------------------------------------------------------------------------------------------------
 // build products of one graph (all device arrays unless noted)
@@ -150,6 +166,12 @@ struct Schedule {
     DevMem medium;      // uint32[3 * n_medium]
     DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, first pair) work items
     uint64_t n_mitems = 0;
+    // windowed copies of light, medium and mitems in window-cell order (the originals keep the
+    // enumeration order, whose locality the whole-span count needs)
+    DevMem light_w, medium_w, mitems_w;
+    int cell_shift = 0;                 // time slice of the window index: t >> cell_shift
+    std::vector<uint64_t> light_cells;  // host: first entry of light_w in each cell, then n_light
+    std::vector<uint64_t> mitem_cells;  // host: first entry of mitems_w in each cell, then n_mitems
     DevMem heavy;       // uint32[3 * n_heavy]
     DevMem hslot;       // uint64[n_heavy + 1]: first scratch slot of each heavy triangle
     uint64_t n_slots = 0;
@@ -206,6 +228,9 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t
 int make_schedule(dt_graph *g, DevMem &tri);
 // unit records [*b, *e) that can hold triangles inside the query's window (all when unwindowed)
 void unit_range(const dt_graph *g, const DQuery &q, uint64_t *b, uint64_t *e);
+// the ranges of a cell-ordered list (cell starts ix, kCells + 1 entries) that can hold triangles
+// inside the query's window (the whole list when unwindowed)
+void cell_ranges(const std::vector<uint64_t> &ix, int cell_shift, const DQuery &q, Ranges &r);
 
 // counting
 int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *empty);

@@ -4,7 +4,10 @@
 // triangle goes to the light path (one lane), the medium path (one wavefront) or the heavy path
 // (the prefix-count procedures split over workgroups), decided by P = sigma_uv * sigma_uw, the
 // number of (uv edge, uw edge) pairs the pairwise paths walk.  A medium triangle becomes
-// ceil(P / kMediumChunk) work items of equal size.  Also the graph totals reported in the
+// ceil(P / kMediumChunk) work items of equal size.  Unit records are grouped by their first time
+// and the light and medium lists by window cell (a necessary condition on the pairs' first and
+// last edge times), so that a query with a time window visits only what can fall inside it; the
+// results never depend on this order.  Also the graph totals reported in the
 // statistics: the sum over triangles of the product of the three pair multiplicities (the count at
 // infinite deltas, an overflow bound) and the algorithmic bytes of one whole-graph count.
 #include <algorithm>
@@ -131,14 +134,43 @@ __device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint3
     return make_uint4(t1, t2 - t1, t3 - t2, (uint32_t)(((pi - 1) * 8 + (rho - 1)) << 8) | (uint32_t)(type - 1));
 }
 
+// Window cell of a light or medium triangle: slice of F (the latest first-edge time over its three
+// pairs) times kSlices plus slice of L (the earliest last-edge time).  Each pair's two direction
+// lists are key-sorted, so its first and last edges are at their ends.
+__device__ __forceinline__ uint16_t window_cell(uint32_t e_uv, uint32_t e_uw, uint32_t e_vw,
+                                                const uint32_t *__restrict__ eoff,
+                                                const uint64_t *__restrict__ key, int shift, int cshift) {
+    const uint32_t es[3] = {e_uv, e_uw, e_vw};
+    uint64_t F = 0, L = ~0ull;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1], c = eoff[2 * es[p] + 2];
+        uint64_t first = ~0ull, last = 0;
+        if (a < b) {
+            first = key[a];
+            last = key[b - 1];
+        }
+        if (b < c) {
+            first = key[b] < first ? key[b] : first;
+            last = key[c - 1] > last ? key[c - 1] : last;
+        }
+        F = first > F ? first : F;
+        L = last < L ? last : L;
+    }
+    const uint64_t f = (F >> shift) >> cshift, l = (L >> shift) >> cshift;
+    return (uint16_t)((f < kSlices - 1 ? f : kSlices - 1) * kSlices + (l < kSlices - 1 ? l : kSlices - 1));
+}
+
 // Every triangle to its class's list at base[class][block] + its rank in the block's walk; unit
-// triangles become records (in triangle order) with their t1 bucket as a sort key.
+// triangles become records (in triangle order) with their t1 bucket as a sort key; light and
+// medium triangles also go, with their window cell as a sort key, to the windowed copies.
 __global__ void __launch_bounds__(kBlock)
 k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__restrict__ cls,
             const uint64_t *__restrict__ base, const uint32_t *__restrict__ eoff,
-            const uint64_t *__restrict__ key, int shift, int bshift, uint32_t *__restrict__ light,
-            uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy, uint4 *__restrict__ urec,
-            uint16_t *__restrict__ ubkt) {
+            const uint64_t *__restrict__ key, int shift, int bshift, int cshift, uint32_t *__restrict__ light,
+            uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy, uint4 *__restrict__ lrec,
+            uint16_t *__restrict__ lkey, uint4 *__restrict__ mrec, uint16_t *__restrict__ mkey,
+            uint4 *__restrict__ urec, uint16_t *__restrict__ ubkt) {
     __shared__ unsigned long long s_wave[kBlock / 64];
     const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
     uint64_t run[4] = {base[4 * blockIdx.x], base[4 * blockIdx.x + 1], base[4 * blockIdx.x + 2],
@@ -175,6 +207,10 @@ k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__r
                 dst[0] = e_uv;
                 dst[1] = e_uw;
                 dst[2] = e_vw;
+                if (k < 2) {
+                    (k == 0 ? lrec : mrec)[pos] = make_uint4(e_uv, e_uw, e_vw, 0u);
+                    (k == 0 ? lkey : mkey)[pos] = window_cell(e_uv, e_uw, e_vw, eoff, key, shift, cshift);
+                }
             }
         }
 #pragma unroll
@@ -191,6 +227,32 @@ __global__ void k_unit_starts(uint64_t nu, uint32_t nbk, const uint16_t *__restr
     const int64_t cur = j < nu ? (int64_t)bkt[j] : (int64_t)nbk;
     const int64_t prev = j > 0 ? (int64_t)bkt[j - 1] : -1;
     for (int64_t x = prev + 1; x <= cur; ++x) start[x] = (uint32_t)j;
+}
+
+// first position of every cell in a cell-sorted key array (kCells + 1 entries, the last = n)
+__global__ void k_cell_starts(uint64_t n, const uint16_t *__restrict__ ck, uint64_t *__restrict__ start) {
+    uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j > n) return;
+    const int64_t cur = j < n ? (int64_t)ck[j] : (int64_t)kCells;
+    const int64_t prev = j > 0 ? (int64_t)ck[j - 1] : -1;
+    for (int64_t x = prev + 1; x <= cur; ++x) start[x] = j;
+}
+
+// (e_uv, e_uw, e_vw, -) records back to three words per triangle
+__global__ void k_unpack3(uint64_t n, const uint4 *__restrict__ rec, uint32_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint4 r = rec[i];
+    out[3 * i] = r.x;
+    out[3 * i + 1] = r.y;
+    out[3 * i + 2] = r.z;
+}
+
+// first medium item of every cell: the item base of the cell's first triangle
+__global__ void k_cell_items(const uint64_t *__restrict__ tstart, const uint64_t *__restrict__ ibase,
+                             uint64_t *__restrict__ istart) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c <= kCells) istart[c] = ibase[tstart[c]];
 }
 
 // work items of the medium path: ceil(P / kMediumChunk) per triangle
@@ -234,6 +296,50 @@ __global__ void k_heavy_chunks(uint64_t n_heavy, const uint64_t *__restrict__ nc
         chunks[2 * (cbase[h] + j)] = (uint32_t)h;
         chunks[2 * (cbase[h] + j) + 1] = (uint32_t)(j * chunk);
     }
+}
+
+// Sort n (cell, record) pairs by cell, unpack the records to out (three words per triangle) and
+// write the cell starts (kCells + 1 entries) to start.
+int cell_order(dt_ctx *ctx, uint64_t n, DevMem &ckey, DevMem &rec, DevMem &out, DevMem &start, hipStream_t st) {
+    DevMem k2, r2;
+    DT_TRY(dev_alloc(ctx, start, (uint64_t)(kCells + 1) * 8));
+    DT_TRY(dev_alloc(ctx, k2, n * 2));
+    DT_TRY(dev_alloc(ctx, r2, n * sizeof(uint4)));
+    DT_TRY(sort_pairs_u16_u4(ctx, ckey.as<uint16_t>(), k2.as<uint16_t>(), rec.as<uint4>(), r2.as<uint4>(), n, 16, st));
+    k_cell_starts<<<grid_for(n + 1, kBlock), kBlock, 0, st>>>(n, k2.as<uint16_t>(), start.as<uint64_t>());
+    DT_HIP(hipGetLastError());
+    if (n) {
+        k_unpack3<<<grid_for(n, kBlock), kBlock, 0, st>>>(n, r2.as<uint4>(), out.as<uint32_t>());
+        DT_HIP(hipGetLastError());
+    }
+    return DT_OK;
+}
+
+// Work items of the medium list med (nm triangles) into items, their number to *n_items and each
+// triangle's first item to base (nm + 1 entries).
+int medium_items(dt_ctx *ctx, uint64_t nm, DevMem &med, DevMem &eoff, DevMem &items, uint64_t *n_items,
+                 DevMem &base, hipStream_t st) {
+    DevMem nch;
+    DT_TRY(dev_alloc(ctx, nch, (nm + 1) * 8));
+    DT_TRY(dev_alloc(ctx, base, (nm + 1) * 8));
+    DT_HIP(hipMemsetAsync(nch.ptr, 0, (nm + 1) * 8, st));
+    if (nm) {
+        k_medium_sizes<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, med.as<uint32_t>(), eoff.as<uint32_t>(),
+                                                                nch.as<uint64_t>());
+        DT_HIP(hipGetLastError());
+    }
+    DT_TRY(exclusive_scan_u64(ctx, nch.as<uint64_t>(), base.as<uint64_t>(), nm + 1, st));
+    uint64_t ni = 0;
+    DT_HIP(hipMemcpyAsync(&ni, base.as<uint64_t>() + nm, 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    *n_items = ni;
+    DT_TRY(dev_alloc(ctx, items, ni * 8));
+    if (nm) {
+        k_medium_fill<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, nch.as<uint64_t>(), base.as<uint64_t>(),
+                                                               items.as<uint32_t>());
+        DT_HIP(hipGetLastError());
+    }
+    return DT_OK;
 }
 
 }  // namespace
@@ -297,16 +403,31 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     while (t_bits < 31 && (1ll << t_bits) <= g->span) ++t_bits;
     S.unit_shift = t_bits > 16 ? t_bits - 16 : 0;
     const uint64_t nbk = unit_ok ? ((uint64_t)g->span >> S.unit_shift) + 1 : 1;
-    DevMem urec, ubkt, ubkt2, ustart;
+    // time slices of the window index: span >> cell_shift < kSlices
+    S.cell_shift = 0;
+    while (S.cell_shift < 62 && (g->span >> S.cell_shift) >= (int64_t)kSlices) ++S.cell_shift;
+    DevMem urec, ubkt, ubkt2, ustart, lrec, lkey, mrec, mkey, lstart, mstart;
     DT_TRY(dev_alloc(ctx, urec, nu * sizeof(uint4)));
     DT_TRY(dev_alloc(ctx, ubkt, nu * 2));
+    DT_TRY(dev_alloc(ctx, lrec, S.n_light * sizeof(uint4)));
+    DT_TRY(dev_alloc(ctx, lkey, S.n_light * 2));
+    DT_TRY(dev_alloc(ctx, mrec, nm * sizeof(uint4)));
+    DT_TRY(dev_alloc(ctx, mkey, nm * 2));
     if (nt) {
         k_partition<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), cls.as<uint8_t>(), base.as<uint64_t>(),
-            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, S.unit_shift, S.light.as<uint32_t>(),
-            S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), urec.as<uint4>(), ubkt.as<uint16_t>());
+            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, S.unit_shift, S.cell_shift,
+            S.light.as<uint32_t>(), S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), lrec.as<uint4>(),
+            lkey.as<uint16_t>(), mrec.as<uint4>(), mkey.as<uint16_t>(), urec.as<uint4>(), ubkt.as<uint16_t>());
         DT_HIP(hipGetLastError());
     }
     cls.reset();
+    // the windowed copies of the light and medium lists, in window-cell order
+    DT_TRY(dev_alloc(ctx, S.light_w, S.n_light * 12));
+    DT_TRY(dev_alloc(ctx, S.medium_w, nm * 12));
+    DT_TRY(cell_order(ctx, S.n_light, lkey, lrec, S.light_w, lstart, st));
+    DT_TRY(cell_order(ctx, nm, mkey, mrec, S.medium_w, mstart, st));
+    S.light_cells.resize(kCells + 1);
+    DT_HIP(hipMemcpyAsync(S.light_cells.data(), lstart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
     // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket); the
     // host keeps the bucket starts
     if (nu) {
@@ -323,27 +444,21 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     }
     DT_HIP(hipStreamSynchronize(st));
     urec.reset();
+    // medium work items of both copies (the same totals: the same triangles in another order)
     {
-        DevMem nch, base;
-        DT_TRY(dev_alloc(ctx, nch, (nm + 1) * 8));
-        DT_TRY(dev_alloc(ctx, base, (nm + 1) * 8));
-        DT_HIP(hipMemsetAsync(nch.ptr, 0, (nm + 1) * 8, st));
-        if (nm) {
-            k_medium_sizes<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, S.medium.as<uint32_t>(),
-                                                                    g->eoff.as<uint32_t>(), nch.as<uint64_t>());
-            DT_HIP(hipGetLastError());
-        }
-        DT_TRY(exclusive_scan_u64(ctx, nch.as<uint64_t>(), base.as<uint64_t>(), nm + 1, st));
-        uint64_t ni = 0;
-        DT_HIP(hipMemcpyAsync(&ni, base.as<uint64_t>() + nm, 8, hipMemcpyDeviceToHost, st));
-        DT_HIP(hipStreamSynchronize(st));
+        DevMem base;
+        uint64_t ni = 0, ni_w = 0;
+        DT_TRY(medium_items(ctx, nm, S.medium, g->eoff, S.mitems, &ni, base, st));
+        DT_TRY(medium_items(ctx, nm, S.medium_w, g->eoff, S.mitems_w, &ni_w, base, st));
+        if (ni != ni_w) return fail(DT_EDEVICE, "medium work items of the two orders differ");
         S.n_mitems = ni;
-        DT_TRY(dev_alloc(ctx, S.mitems, ni * 8));
-        if (nm) {
-            k_medium_fill<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, nch.as<uint64_t>(), base.as<uint64_t>(),
-                                                                   S.mitems.as<uint32_t>());
-            DT_HIP(hipGetLastError());
-        }
+        DevMem istart;
+        DT_TRY(dev_alloc(ctx, istart, (uint64_t)(kCells + 1) * 8));
+        k_cell_items<<<grid_for(kCells + 1, kBlock), kBlock, 0, st>>>(mstart.as<uint64_t>(), base.as<uint64_t>(),
+                                                                      istart.as<uint64_t>());
+        DT_HIP(hipGetLastError());
+        S.mitem_cells.resize(kCells + 1);
+        DT_HIP(hipMemcpyAsync(S.mitem_cells.data(), istart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
     }
     // heavy slots and chunks
@@ -377,6 +492,32 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     }
     DT_HIP(hipStreamSynchronize(st));
     return DT_OK;
+}
+
+void cell_ranges(const std::vector<uint64_t> &ix, int cell_shift, const DQuery &q, Ranges &r) {
+    r.n = 0;
+    r.pre[0] = 0;
+    if (ix.size() != kCells + 1 || ix[kCells] == 0) return;
+    auto add = [&](uint64_t b, uint64_t e) {
+        if (e <= b) return;
+        if (r.n && r.b[r.n - 1] + (r.pre[r.n] - r.pre[r.n - 1]) == b) {
+            r.pre[r.n] += e - b;   // adjacent to the previous range
+            return;
+        }
+        r.b[r.n] = b;
+        r.pre[r.n + 1] = r.pre[r.n] + (e - b);
+        ++r.n;
+    };
+    if (!q.windowed) {
+        add(0, ix[kCells]);
+        return;
+    }
+    // relative times [wlo, whi) of the window; cells (f, l) with f <= slice(whi - 1), l >= slice(wlo)
+    const uint64_t wlo = q.klo >> q.shift, whi = q.khi >> q.shift;
+    if (whi <= wlo) return;
+    const uint64_t ql = std::min<uint64_t>(wlo >> cell_shift, kSlices - 1);
+    const uint64_t qh = std::min<uint64_t>((whi - 1) >> cell_shift, kSlices - 1);
+    for (uint64_t f = 0; f <= qh; ++f) add(ix[f * kSlices + ql], ix[f * kSlices + kSlices]);
 }
 
 void unit_range(const dt_graph *g, const DQuery &q, uint64_t *b, uint64_t *e) {

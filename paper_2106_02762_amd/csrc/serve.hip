@@ -19,7 +19,8 @@ uint64_t graph_device_bytes(const dt_graph *g) {
     const DevMem *ms[] = {&g->sx, &g->sy, &g->row, &g->col, &g->ceid, &g->psid, &g->pdir, &g->pkey,
                           &g->pstart, &g->c1, &g->core, &g->rank, &g->order, &g->dag_row, &g->dag_col,
                           &g->eoff, &g->key, &g->sched.light, &g->sched.medium, &g->sched.mitems,
-                          &g->sched.heavy, &g->sched.hslot, &g->sched.chunks, &g->sched.unit};
+                          &g->sched.light_w, &g->sched.medium_w, &g->sched.mitems_w, &g->sched.heavy,
+                          &g->sched.hslot, &g->sched.chunks, &g->sched.unit};
     uint64_t b = 0;
     for (const DevMem *m : ms) b += m->bytes;
     // scratch of the heavy path, taken per query in flight
