@@ -96,13 +96,14 @@ typedef struct {
  * testing its three times against the query (when the graph's time span is below 2^31).  Any other
  * triangle whose two source-incident pairs carry P = sigma_uv * sigma_uw temporal-edge pairs is
  * counted by one lane enumerating those pairs (the pairwise form of Lemma 1) when
- * P <= light_pair_cap and the {v,w} pair carries at most 64 edges, by wavefronts taking the pairs
- * in chunks of 1024 spread over their lanes (with the {v,w} lists in LDS when they fit) when
- * P <= medium_pair_cap, and otherwise by the prefix-count procedures of Algorithms 1-3 split
+ * P <= light_pair_cap and the {v,w} pair carries at most 64 edges, by one lane per edge of the
+ * smaller source-incident pair that walks only the edges of the other pair within d13 of it (found
+ * by binary search; a wavefront spreads those pairs over its lanes) when P <= medium_pair_cap,
+ * and otherwise by the prefix-count procedures of Algorithms 1-3 split
  * into chunks of `heavy_chunk` source edges.  Zero fields keep the default; force_path 1-3 sends
  * every triangle, unit ones included, down one path. */
 typedef struct {
-    uint32_t light_pair_cap;       /* default 64                                                  */
+    uint32_t light_pair_cap;       /* default 4                                                   */
     uint32_t heavy_chunk;          /* default 256 (the only compiled value)                       */
     uint32_t medium_pair_cap;      /* default 2^27, at most 2^30                                  */
     uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;

@@ -2,7 +2,7 @@
 //
 // The batch becomes one table of work items, each a bounded piece of one query's work: a run of
 // unit-triangle records, a run of light triangles (one lane per triangle) or a run of medium-path
-// items (one wavefront per item).  A windowed query's unit runs cover only the records whose
+// entries (one lane per outer edge).  A windowed query's unit runs cover only the records whose
 // earliest time can fall in its window, its light and medium items only the window cells that can.
 // A persistent grid strides over the table, so graphs of very different sizes and queries with
 // different deltas and windows share the device evenly, and one launch serves the whole batch
@@ -25,7 +25,7 @@ using namespace cdev;
 namespace {
 
 constexpr unsigned kBB = 256;
-constexpr uint32_t kMediumGroup = 16;   // medium items per table entry
+constexpr uint32_t kMediumGroup = 1024;   // medium entries (one lane each) per table entry
 
 struct BQuery {
     const uint32_t *light, *medium, *mitems, *eoff;
@@ -58,8 +58,8 @@ k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
         } else if (I.kind == 0) {
             for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri<false>(Q.light, i, Q.eoff, Q.key, Q.q, acc);
         } else {
-            for (uint64_t j = I.b + wave; j < I.e; j += kBB / 64)
-                medium_item<false>(Q.medium, Q.mitems, j, Q.eoff, Q.key, Q.q, acc, lane, nullptr);
+            for (uint64_t b = I.b + 64 * wave; b < I.e; b += kBB)
+                medium_lanes<false>(Q.medium, Q.mitems, b + lane, b + lane < I.e, Q.eoff, Q.key, Q.q, acc, lane);
         }
         block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
         __syncthreads();

@@ -15,6 +15,10 @@
 //    of Lemma 1).  With x, y fixed and ordered, the third edge z on {v,w} is first, middle or last,
 //    and each case is one key range of the vw list found by binary search; that is cells
 //    (pi5|pi6), (pi3|pi4) and (pi1|pi2) respectively.
+//  - medium: one lane per edge x of the triangle's smaller source-incident pair; only the edges y
+//    of the other pair within d13 of x can complete a triangle, so the lane finds those by binary
+//    search, and each wavefront spreads the (x, y) pairs of its lanes evenly over them, each pair
+//    then handled as on the light path.
 //  - heavy: the prefix-count procedures.  For every edge on a uv or uw list a prefix pass stores
 //    the cumulative counts that Algorithms 1-3 need (CEC of Section 5), and a second pass walks
 //    the same edges as e2 (Algorithm 1: pi1/pi2), e1 (Algorithm 2: pi3/pi4) and e2 (Algorithm 3:
@@ -55,21 +59,23 @@ k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
-// medium path: wave w takes work items w, w + W, w + 2W, ... (each at most kMediumChunk pairs)
+// medium path: wave w takes the 64 entries from 64 w on, then those from 64 (w + W) on, ...
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
+k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
          const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, DQuery q,
          int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
-    __shared__ uint64_t s_vw[BLOCK / 64][kVwCap];
     Acc<CELLS> acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
-    const uint64_t n_items = R.pre[R.n];
+    const uint64_t n_ent = R.pre[R.n];
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
     uint32_t r = 0;
-    for (uint64_t it = (uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64; it < n_items; it += W)
-        medium_item<CELLS>(med, items, range_at(R, r, it), eoff, key, q, acc, lane, s_vw[threadIdx.x / 64]);
+    for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
+        const uint64_t j = b + lane;
+        const bool active = j < n_ent;
+        medium_lanes<CELLS>(med, ent, active ? range_at(R, r, j) : 0, active, eoff, key, q, acc, lane);
+    }
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -441,7 +447,7 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         (nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
     const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
     const unsigned hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    const unsigned mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 3) / 4, (uint64_t)ctx->num_cus * 8) : 0;
+    const unsigned mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * 8) : 0;
     uint64_t ub = 0, ue = 0;
     if (S.n_unit && (parts & 8)) unit_range(g, q, &ub, &ue);
     const unsigned ug = ue > ub ? (unsigned)std::min<uint64_t>((ue - ub + kUnitPerBlock - 1) / kUnitPerBlock,

@@ -184,8 +184,7 @@ __device__ __forceinline__ void light_tri(const uint32_t *__restrict__ tri, uint
 }
 
 // ---------------------------------------------------------------------------------------------
-// medium path: the (uv edge, uw edge) pairs of one triangle in chunks of kMediumChunk, one
-// wavefront per chunk, one pair per lane at a time
+// medium path: one lane per edge of a triangle's smaller source-incident pair
 // ---------------------------------------------------------------------------------------------
 template <bool CELLS, int A, int B>
 __device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, const Lists &L,
@@ -199,53 +198,116 @@ __device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, co
     light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
 }
 
-// keys of the two {v,w} lists a medium work item may copy into LDS (per wavefront)
-constexpr uint32_t kVwCap = 512;
+// the outer pair of a medium triangle: the source-incident pair with fewer temporal edges
+// (uv on a tie); the medium path has one entry per outer edge
+__host__ __device__ __forceinline__ bool medium_outer_is_uv(uint32_t s_uv, uint32_t s_uw) { return s_uv <= s_uw; }
 
-// medium work item `it` = (triangle index into med, first pair); pairs enumerate the unclipped
-// uv and uw runs (each stored as direction 0 then direction 1), edges outside the window skipped.
-// Every pair of the item searches the same two (window-clipped) {v,w} lists: when they fit, the
-// wavefront first copies them into its LDS slice vw_lds (when given) so those searches stay on chip.
-template <bool CELLS>
-__device__ __forceinline__ void medium_item(const uint32_t *__restrict__ med, const uint32_t *__restrict__ items,
-                                            uint64_t it, const uint32_t *__restrict__ eoff,
-                                            const uint64_t *__restrict__ key, const DQuery &q,
-                                            Acc<CELLS> &acc, unsigned lane, uint64_t *vw_lds) {
-    const uint32_t t = items[2 * it], p0 = items[2 * it + 1];
-    const uint32_t e_uv = med[3 * (uint64_t)t], e_uw = med[3 * (uint64_t)t + 1], e_vw = med[3 * (uint64_t)t + 2];
-    Lists L;
-    load_lists(eoff, e_uv, e_uw, e_vw, key, q, L);
-    const uint64_t *zkey = key;
-    const uint32_t n0 = L.hi[4] - L.lo[4], n1 = L.hi[5] - L.lo[5];
-    if (vw_lds && n0 + n1 <= kVwCap) {
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t j = lane; j < n0 + n1; j += 64)
-            vw_lds[j] = j < n0 ? key[L.lo[4] + j] : key[L.lo[5] + (j - n0)];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        L.lo[4] = 0;
-        L.hi[4] = n0;
-        L.lo[5] = n0;
-        L.hi[5] = n0 + n1;
-        zkey = vw_lds;
+// first indices in [lo, hi) whose keys are >= K1 and >= K2 (two searches in one loop)
+__device__ __forceinline__ void lower2(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi, uint64_t K1,
+                                       uint64_t K2, uint32_t &r1, uint32_t &r2) {
+    uint32_t l1 = lo, l2 = lo, len1 = hi - lo, len2 = hi - lo;
+    while (len1 | len2) {
+        const uint32_t h1 = len1 >> 1, h2 = len2 >> 1;
+        const bool go1 = len1 && key[l1 + h1] < K1, go2 = len2 && key[l2 + h2] < K2;
+        l1 += go1 ? h1 + 1 : 0;
+        len1 = go1 ? len1 - h1 - 1 : h1;
+        l2 += go2 ? h2 + 1 : 0;
+        len2 = go2 ? len2 - h2 - 1 : h2;
     }
-    const uint32_t a0 = eoff[2 * e_uv], a1 = eoff[2 * e_uv + 1], a2 = eoff[2 * e_uv + 2];
-    const uint32_t b0 = eoff[2 * e_uw], b1 = eoff[2 * e_uw + 1], b2 = eoff[2 * e_uw + 2];
-    const uint32_t su0 = a1 - a0, sw0 = b1 - b0, sw = b2 - b0;
-    const uint32_t np = (a2 - a0) * sw;
-    const uint32_t end = np - p0 < kMediumChunk ? np : p0 + kMediumChunk;
-    for (uint32_t p = p0 + lane; p < end; p += 64) {
-        const uint32_t a = p / sw, b = p - a * sw;
-        const uint64_t kx = key[a0 + a], ky = key[b0 + b];
-        if (q.windowed && (kx < q.klo || kx >= q.khi || ky < q.klo || ky >= q.khi)) continue;
-        switch ((a >= su0 ? 2 : 0) + (b >= sw0 ? 1 : 0)) {
-            case 0: medium_pair<CELLS, 0, 0>(zkey, L, q, kx, ky, acc); break;
-            case 1: medium_pair<CELLS, 0, 1>(zkey, L, q, kx, ky, acc); break;
-            case 2: medium_pair<CELLS, 1, 0>(zkey, L, q, kx, ky, acc); break;
-            default: medium_pair<CELLS, 1, 1>(zkey, L, q, kx, ky, acc); break;
+    r1 = l1;
+    r2 = l2;
+}
+
+// Medium entries: entry e = (triangle index into med, outer edge offset).  Lane l takes entry
+// `e` (when `active`): edge x of the triangle's outer pair (its direction-0 run, then its
+// direction-1 run).  A pair (x, y) with y on the other source-incident pair (the inner one) can only
+// complete a triangle when |t_y - t_x| <= d13 (d12, d23 <= d13 after normalisation), and on each
+// inner direction list those y form one key range (clipped to the window too), found by binary
+// search.  The wavefront then spreads the (x, y) pairs of all its lanes evenly over the lanes
+// (pair j belongs to the last lane whose exclusive prefix of pair counts is <= j), so one outer edge
+// with many close partners does not stall the others.  Every lane of the wavefront must call this.
+template <bool CELLS>
+__device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+                                             uint64_t e, bool active, const uint32_t *__restrict__ eoff,
+                                             const uint64_t *__restrict__ key, const DQuery &q,
+                                             Acc<CELLS> &acc, unsigned lane) {
+    uint64_t kx = 0;
+    uint32_t lo0 = 0, c0 = 0, lo1 = 0, c1 = 0, zb0 = 0, ze0 = 0, zb1 = 0, ze1 = 0, flags = 0;
+    if (active) {
+        const uint32_t t = ent[2 * e], j = ent[2 * e + 1];
+        const uint32_t e_uv = med[3 * (uint64_t)t], e_uw = med[3 * (uint64_t)t + 1], e_vw = med[3 * (uint64_t)t + 2];
+        const uint32_t a0 = eoff[2 * e_uv], a1 = eoff[2 * e_uv + 1], a2 = eoff[2 * e_uv + 2];
+        const uint32_t b0 = eoff[2 * e_uw], b1 = eoff[2 * e_uw + 1], b2 = eoff[2 * e_uw + 2];
+        const bool outer_uv = medium_outer_is_uv(a2 - a0, b2 - b0);
+        const uint32_t o0 = outer_uv ? a0 : b0, o1 = outer_uv ? a1 : b1;
+        const uint32_t i0 = outer_uv ? b0 : a0, i1 = outer_uv ? b1 : a1, i2 = outer_uv ? b2 : a2;
+        const uint32_t ox = o0 + j;
+        flags = (outer_uv ? 1u : 0u) | (ox >= o1 ? 2u : 0u);
+        kx = key[ox];
+        if (kx >= q.klo && kx < q.khi) {
+            const int64_t tx = (int64_t)(kx >> q.shift);
+            uint64_t klo = before_time(tx - q.d13, q), khi = before_time(tx + q.d13 + 1, q);
+            klo = klo > q.klo ? klo : q.klo;
+            khi = khi < q.khi ? khi : q.khi;
+            uint32_t hi0, hi1;
+            lower2(key, i0, i1, klo, khi, lo0, hi0);
+            lower2(key, i1, i2, klo, khi, lo1, hi1);
+            c0 = hi0 - lo0;
+            c1 = hi1 - lo1;
+            if (c0 + c1) {   // the {v,w} lists, clipped to the window
+                zb0 = eoff[2 * e_vw];
+                ze0 = eoff[2 * e_vw + 1];
+                ze1 = eoff[2 * e_vw + 2];
+                zb1 = ze0;
+                if (q.windowed) {
+                    lower2(key, zb0, ze0, q.klo, q.khi, zb0, ze0);
+                    lower2(key, zb1, ze1, q.klo, q.khi, zb1, ze1);
+                }
+            }
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    // exclusive prefix of the lanes' pair counts
+    const uint32_t c = c0 + c1;
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= (unsigned)o) incl += y;
+    }
+    const uint32_t excl = incl - c;
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    const uint32_t kx_lo = (uint32_t)kx, kx_hi = (uint32_t)(kx >> 32);
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t jp = base + lane;
+        const uint32_t jj = jp < total ? jp : total - 1;
+        uint32_t l = 0;   // owner lane of pair jj
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1)
+            if (__shfl(excl, l + step, 64) <= jj) l += step;
+        const uint32_t r = jj - __shfl(excl, l, 64);
+        const uint32_t oc0 = __shfl(c0, l, 64), olo0 = __shfl(lo0, l, 64), olo1 = __shfl(lo1, l, 64);
+        const uint32_t ofl = __shfl(flags, l, 64);
+        const uint64_t okx = ((uint64_t)(uint32_t)__shfl(kx_hi, l, 64) << 32) | (uint32_t)__shfl(kx_lo, l, 64);
+        Lists L;
+        L.lo[4] = __shfl(zb0, l, 64);
+        L.hi[4] = __shfl(ze0, l, 64);
+        L.lo[5] = __shfl(zb1, l, 64);
+        L.hi[5] = __shfl(ze1, l, 64);
+        if (jp >= total) continue;
+        const bool outer_uv = ofl & 1u;
+        const uint32_t x_dir = (ofl >> 1) & 1u, y_dir = r < oc0 ? 0u : 1u;
+        const uint64_t ky = key[r < oc0 ? olo0 + r : olo1 + (r - oc0)];
+        // (uv edge, uw edge) with their directions
+        const uint64_t k_uv = outer_uv ? okx : ky, k_uw = outer_uv ? ky : okx;
+        const uint32_t d_uv = outer_uv ? x_dir : y_dir, d_uw = outer_uv ? y_dir : x_dir;
+        switch (d_uv * 2 + d_uw) {
+            case 0: medium_pair<CELLS, 0, 0>(key, L, q, k_uv, k_uw, acc); break;
+            case 1: medium_pair<CELLS, 0, 1>(key, L, q, k_uv, k_uw, acc); break;
+            case 2: medium_pair<CELLS, 1, 0>(key, L, q, k_uv, k_uw, acc); break;
+            default: medium_pair<CELLS, 1, 1>(key, L, q, k_uv, k_uw, acc); break;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------------

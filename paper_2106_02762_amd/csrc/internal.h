@@ -126,8 +126,6 @@ struct DQuery {
     int windowed;            // 0: klo = 0, khi = ~0
 };
 
-// (uv edge, uw edge) pairs per medium-path work item
-constexpr uint32_t kMediumChunk = 1024;
 // Unit triangles: static triangles with exactly one temporal edge on each of their three pairs
 // (the common case in sparse interaction data).  Their ordering pi (Figure 3) and orientation rho
 // (Figure 4) do not depend on the query, so each is stored as one 16-byte record
@@ -164,7 +162,7 @@ struct Schedule {
     std::vector<uint32_t> unit_index;   // host: first record of each t1 bucket, then n_unit
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
     DevMem medium;      // uint32[3 * n_medium]
-    DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, first pair) work items
+    DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, outer edge) entries
     uint64_t n_mitems = 0;
     // windowed copies of light, medium and mitems in window-cell order (the originals keep the
     // enumeration order, whose locality the whole-span count needs)
@@ -213,7 +211,7 @@ struct dt_graph {
     uint64_t alg_bytes_unit = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{64, 256, 1u << 27, 0, 0};
+    dt_tuning tuning{4, 256, 1u << 27, 0, 0};
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 

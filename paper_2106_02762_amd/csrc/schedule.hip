@@ -3,10 +3,10 @@
 // (its ordering, orientation and type fixed here, Figures 3 and 4 with Table 2); every other static
 // triangle goes to the light path (one lane), the medium path (one wavefront) or the heavy path
 // (the prefix-count procedures split over workgroups), decided by P = sigma_uv * sigma_uw, the
-// number of (uv edge, uw edge) pairs the pairwise paths walk.  A medium triangle becomes
-// ceil(P / kMediumChunk) work items of equal size.  Unit records are grouped by their first time
-// and the light and medium lists by window cell (a necessary condition on the pairs' first and
-// last edge times), so that a query with a time window visits only what can fall inside it; the
+// number of (uv edge, uw edge) pairs the pairwise paths walk.  A medium triangle becomes one entry
+// per edge of its smaller source-incident pair.  Unit records are grouped by their first time and
+// the light and medium lists by window cell (a necessary condition on the pairs' first and last
+// edge times), so that a query with a time window visits only what can fall inside it; the
 // results never depend on this order.  Also the graph totals reported in the
 // statistics: the sum over triangles of the product of the three pair multiplicities (the count at
 // infinite deltas, an overflow bound) and the algorithmic bytes of one whole-graph count.
@@ -255,14 +255,15 @@ __global__ void k_cell_items(const uint64_t *__restrict__ tstart, const uint64_t
     if (c <= kCells) istart[c] = ibase[tstart[c]];
 }
 
-// work items of the medium path: ceil(P / kMediumChunk) per triangle
+// entries of the medium path: one per edge of the outer pair (the source-incident pair with fewer
+// temporal edges)
 __global__ void k_medium_sizes(uint64_t nm, const uint32_t *__restrict__ med, const uint32_t *__restrict__ eoff,
                                uint64_t *__restrict__ nch) {
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nm) return;
     const uint32_t e_uv = med[3 * i], e_uw = med[3 * i + 1];
-    const uint64_t P = (uint64_t)(eoff[2 * e_uv + 2] - eoff[2 * e_uv]) * (eoff[2 * e_uw + 2] - eoff[2 * e_uw]);
-    nch[i] = (P + kMediumChunk - 1) / kMediumChunk;
+    const uint32_t s_uv = eoff[2 * e_uv + 2] - eoff[2 * e_uv], s_uw = eoff[2 * e_uw + 2] - eoff[2 * e_uw];
+    nch[i] = cdev::medium_outer_is_uv(s_uv, s_uw) ? s_uv : s_uw;
 }
 
 __global__ void k_medium_fill(uint64_t nm, const uint64_t *__restrict__ nch, const uint64_t *__restrict__ base,
@@ -271,7 +272,7 @@ __global__ void k_medium_fill(uint64_t nm, const uint64_t *__restrict__ nch, con
     if (i >= nm) return;
     for (uint64_t j = 0; j < nch[i]; ++j) {
         items[2 * (base[i] + j)] = (uint32_t)i;
-        items[2 * (base[i] + j) + 1] = (uint32_t)(j * kMediumChunk);
+        items[2 * (base[i] + j) + 1] = (uint32_t)j;
     }
 }
 
