@@ -259,6 +259,26 @@ def main():
         count_ms[str(dd)] = round(statistics.median(ts[1:]), 4)
     log("count ms", count_ms)
 
+    # a delta sweep (eight triples, the shape of the paper's parameter sweeps) in one pass against
+    # eight separate counts
+    sweep_d = [(x, x, x) for x in (60, 600, 1800, 3600, 7200, 21600, 86400, 604800)]
+    ref_sweep = np.array([dt.dt_count(h, *x) for x in sweep_d])
+    ts_one, ts_sep = [], []
+    for _ in range(11):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        got_sweep = dt.dt_count_sweep(h, sweep_d)
+        ts_one.append((time.perf_counter() - a) * 1e3)
+        a = time.perf_counter()
+        for x in sweep_d:
+            dt.dt_count(h, *x)
+        ts_sep.append((time.perf_counter() - a) * 1e3)
+    sweep = {"deltas": [x[0] for x in sweep_d], "one_pass_ms": round(statistics.median(ts_one[1:]), 4),
+             "separate_ms": round(statistics.median(ts_sep[1:]), 4),
+             "matches_separate": bool((got_sweep == ref_sweep).all())}
+    sweep["speedup"] = round(sweep["separate_ms"] / sweep["one_pass_ms"], 2)
+    log("sweep", sweep)
+
     # roofline of the dominant kernel of the step (event-timed on the library's stream)
     mean = {k: float(np.mean([p[k] for p in prof])) for k in prof[0]}
     heavy_bytes = st["alg_bytes"] - st["alg_bytes_light"] - st["alg_bytes_medium"] - st["alg_bytes_unit"]
@@ -324,6 +344,7 @@ def main():
         "counts": out.tolist(),
         "count_ms": count_ms,
         "count_edges_per_s": round(g.m / (count_ms[str(d)] / 1e3), 1),
+        "sweep": sweep,
         "kernel_ms": {k: round(v, 4) for k, v in mean.items()},
         "build_ms": {"peel": round(st["ms_peel"], 3), "orient": round(st["ms_orient"], 3),
                      "triangles": round(st["ms_triangles"], 3),

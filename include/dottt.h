@@ -158,6 +158,14 @@ int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stre
  * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
 int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);
 
+/* A delta sweep on one graph (the parameter sweeps of Section 6, Figures 1 and 5): the counts of
+ * k delta triples that share one window [t_lo, t_hi], out[8 j + i] = type i + 1 of queries[j],
+ * equal to k separate dt_count calls.  Each pass over the triangles counts up to 8 triples, so
+ * their records and lists are read from HBM once per 8 queries instead of once per query.
+ * queries: host dt_query[k], k >= 1, all with the same t_lo and t_hi (otherwise DT_EINVAL);
+ * out: host int64[8 k].  Synchronous on the context's stream. */
+int dt_count_sweep(dt_graph *g, uint64_t k, const dt_query *queries, int64_t *out);
+
 /* Batched counting: query i on graphs[i] for i < k (graphs may repeat), all in one persistent
  * launch over a shared work table.  out: host int64[k][8]. */
 int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,

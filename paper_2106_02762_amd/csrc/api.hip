@@ -1,4 +1,5 @@
 // The C ABI (include/dottt.h): contexts, graph load / build / statistics, counts.
+#include <algorithm>
 #include <cstring>
 
 #include "internal.h"
@@ -171,6 +172,7 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     ctx->batch = nullptr;
     ctx->scratch.partials.reset();
     ctx->scratch.heavy_vals.reset();
+    ctx->scratch.sweep_partials.reset();
     ctx->out8.reset();
     pool_trim(ctx, 0);
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
@@ -327,6 +329,33 @@ int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]) {
     DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     DT_HIP(hipStreamSynchronize(ctx->stream));
     memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
+    return DT_OK;
+}
+
+int dt_count_sweep(dt_graph *g, uint64_t k, const dt_query *queries, int64_t *out) {
+    clear_error();
+    if (!queries || !out) return fail(DT_EINVAL, "null queries or output");
+    for (uint64_t j = 1; j < k; ++j)
+        if (queries[j].t_lo != queries[0].t_lo || queries[j].t_hi != queries[0].t_hi)
+            return fail(DT_EINVAL, "the queries of a sweep share one window (query %llu differs)",
+                        (unsigned long long)j);
+    for (uint64_t b = 0; b < k; b += kSweepMax) {
+        const uint32_t kk = (uint32_t)std::min<uint64_t>(kSweepMax, k - b);
+        DQuery dq[kSweepMax];
+        bool empty = false;
+        for (uint32_t j = 0; j < kk; ++j) DT_TRY(count_guarded(g, &queries[b + j], &dq[j], &empty));
+        if (empty || g->n_tri == 0) {
+            for (uint64_t i = 0; i < 8ull * kk; ++i) out[8 * b + i] = 0;
+            continue;
+        }
+        dt_ctx *ctx = g->ctx;
+        DeviceGuard dg(ctx->device);
+        DT_TRY(count_sweep_enqueue(g, dq, kk, ctx->out8.as<int64_t>(), ctx->stream, ctx->scratch));
+        DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, 8 * kk * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
+        DT_HIP(hipStreamSynchronize(ctx->stream));
+        memcpy(out + 8 * b, ctx->pinned_out, 8 * kk * sizeof(int64_t));
+    }
     return DT_OK;
 }
 

@@ -382,6 +382,142 @@ __global__ void k_zero(uint64_t n, int64_t *__restrict__ p) {
     if (i < n) p[i] = 0;
 }
 
+// ---------------------------------------------------------------------------------------------
+// sweeps: several delta triples (one window) per visit of the triangle data
+// ---------------------------------------------------------------------------------------------
+struct SweepQ {
+    DQuery q[kSweepMax];
+    UQuery u[kSweepMax];
+    uint32_t k;
+};
+
+// partial slot of block `slot` for query j: part + 8 (K slot + j)
+template <unsigned BLOCK>
+__device__ __forceinline__ void sweep_store(const int64_t (&t)[8], int64_t *__restrict__ part, uint64_t slot,
+                                            uint32_t k, uint32_t j) {
+    block_store<BLOCK>(t, part + 8 * (slot * k + j));
+    __syncthreads();   // the next store reuses block_store's LDS
+}
+
+// unit records: each record is read once and tested against every delta triple.  A wavefront
+// takes 64 records at a time; for each triple the lanes' pass/fail bits form one 64-bit ballot, as
+// do the lanes of each type.  Lane l keeps the wavefront's count of (triple l / 8, type l % 8): it
+// adds the popcount of that triple's ballot masked by that type's ballot.
+template <unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_unit_sweep(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, SweepQ Q, int64_t *__restrict__ part,
+             uint64_t slot0) {
+    static_assert(kSweepMax * 8 == 64, "one counter per lane");
+    __shared__ uint32_t s_cnt[BLOCK / 64][64];
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    const uint32_t my_j = lane >> 3, my_t = lane & 7;
+    const uint64_t n = end - beg;
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b = beg + (uint64_t)blockIdx.x * per;
+    const uint64_t e = b + per < end ? b + per : end;
+    uint32_t cnt = 0;
+    auto test = [&](const uint4 r, bool valid) {
+        const uint32_t g13 = r.y + r.z, ty = r.w & 7u;
+        uint64_t tsel = 0, jsel = 0;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t) {
+            const uint64_t m = __ballot(valid && ty == t);
+            tsel = my_t == t ? m : tsel;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kSweepMax; ++j) {
+            if (j < Q.k) {
+                const UQuery &u = Q.u[j];
+                const uint64_t m = __ballot(valid && r.y <= u.d12 && r.z <= u.d23 && g13 <= u.d13 &&
+                                            r.x >= u.wlo && r.x + g13 < u.whi);
+                jsel = my_j == j ? m : jsel;
+            }
+        }
+        cnt += (uint32_t)__popcll(jsel & tsel);
+    };
+    // two records per lane in flight; the loop bounds are the same for the whole wavefront
+    uint64_t base = b + 64 * wave;
+    for (; base + BLOCK < e; base += 2 * BLOCK) {
+        const uint64_t i0 = base + lane, i1 = base + BLOCK + lane;
+        const bool v1 = i1 < e;
+        const uint4 r0 = rec[i0];
+        const uint4 r1 = v1 ? rec[i1] : make_uint4(0u, 0u, 0u, 0u);
+        test(r0, true);
+        test(r1, v1);
+    }
+    if (base < e) {
+        const uint64_t i0 = base + lane;
+        const bool v0 = i0 < e;
+        test(v0 ? rec[i0] : make_uint4(0u, 0u, 0u, 0u), v0);
+    }
+    s_cnt[wave][lane] = cnt;
+    __syncthreads();
+    if (threadIdx.x < 8 * Q.k) {
+        int64_t v = 0;
+#pragma unroll
+        for (unsigned w = 0; w < BLOCK / 64; ++w) v += s_cnt[w][threadIdx.x];
+        part[8 * ((slot0 + blockIdx.x) * Q.k + threadIdx.x / 8) + threadIdx.x % 8] = v;
+    }
+}
+
+// light triangles: the block's triangles once per delta triple, the repeats served from cache
+template <unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_light_sweep(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
+              const uint64_t *__restrict__ key, SweepQ Q, int64_t *__restrict__ part, uint64_t slot0) {
+    const uint64_t n_tri = R.pre[R.n];
+    const uint32_t nblk = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nblk);
+    const uint64_t per = (n_tri + nblk - 1) / nblk;
+    const uint64_t beg = (uint64_t)b * per;
+    const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
+    for (uint32_t j = 0; j < Q.k; ++j) {
+        Acc<false> acc;
+        uint32_t r = 0;
+        for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
+            light_tri<false>(tri, range_at(R, r, i), eoff, key, Q.q[j], acc);
+        sweep_store<BLOCK>(acc.t, part, slot0 + blockIdx.x, Q.k, j);
+    }
+}
+
+// medium entries: the block's entries once per delta triple
+template <unsigned BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_medium_sweep(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+               const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, SweepQ Q,
+               int64_t *__restrict__ part, uint64_t slot0) {
+    const unsigned lane = threadIdx.x & 63;
+    const uint64_t n_ent = R.pre[R.n];
+    const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
+    for (uint32_t j = 0; j < Q.k; ++j) {
+        Acc<false> acc;
+        uint32_t r = 0;
+        for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
+            const uint64_t x = b + lane;
+            const bool active = x < n_ent;
+            medium_lanes<false>(med, ent, active ? range_at(R, r, x) : 0, active, eoff, key, Q.q[j], acc, lane);
+        }
+        sweep_store<BLOCK>(acc.t, part, slot0 + blockIdx.x, Q.k, j);
+    }
+}
+
+// out[8 j + i] (+)= sum over slots of part[8 (K slot + j) + i]; block j for query j
+__global__ void __launch_bounds__(256)
+k_reduce_sweep(uint64_t n_slot, uint32_t k, const int64_t *__restrict__ part, int64_t *__restrict__ out, int add) {
+    const uint32_t j = blockIdx.x;
+    int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint64_t i = threadIdx.x; i < n_slot; i += 256) {
+#pragma unroll
+        for (int x = 0; x < 8; ++x) t[x] += part[8 * (i * k + j) + x];
+    }
+    __shared__ int64_t s_prev[8];
+    if (threadIdx.x < 8) s_prev[threadIdx.x] = add ? out[8 * j + threadIdx.x] : 0;
+    __syncthreads();
+    block_store<256>(t, out + 8 * j);
+    __syncthreads();
+    if (threadIdx.x < 8) out[8 * j + threadIdx.x] += s_prev[threadIdx.x];
+}
+
 constexpr unsigned kLightBlock = 256;
 constexpr unsigned kUnitBlock = 256;
 constexpr uint64_t kUnitPerBlock = 16384;   // records per workgroup at least (64 per thread)
@@ -558,6 +694,93 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         prof_end(ctx, kProfReduce, s);
         DT_HIP(hipGetLastError());
     }
+    return DT_OK;
+}
+
+// A sweep: k <= kSweepMax queries with one window.  The unit, light and medium kernels visit each
+// triangle's data once per pass and count it for every delta triple (records and lists are read
+// from HBM once; the repeats of a block's light and medium triangles hit the caches); the rare heavy
+// triangles are counted per query first, and the reduction adds the rest to those sums.
+int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_dev, hipStream_t s, Scratch &sc) {
+    dt_ctx *ctx = g->ctx;
+    Schedule &S = g->sched;
+    if (k == 0 || k > kSweepMax) return fail(DT_EINVAL, "a sweep pass takes 1..%u queries", kSweepMax);
+    SweepQ Q{};
+    Q.k = k;
+    for (uint32_t j = 0; j < k; ++j) {
+        Q.q[j] = qs[j];
+        Q.u[j] = unit_query(qs[j]);
+    }
+    const DQuery &q0 = qs[0];   // the window (and so every range) is the same for all k
+    // heavy triangles: one count per query, written to out_dev
+    const bool heavy = S.n_chunks > 0;
+    if (heavy)
+        for (uint32_t j = 0; j < k; ++j) DT_TRY(count_enqueue(g, qs[j], out_dev + 8 * j, s, false, nullptr, sc, 4));
+    Ranges lr, mr;
+    cell_ranges(S.light_cells, S.cell_shift, q0, lr);
+    cell_ranges(S.mitem_cells, S.cell_shift, q0, mr);
+    const uint64_t nl = lr.pre[lr.n], nmi = mr.pre[mr.n];
+    const uint32_t *light = (q0.windowed ? S.light_w : S.light).as<uint32_t>();
+    const uint32_t *medium = (q0.windowed ? S.medium_w : S.medium).as<uint32_t>();
+    const uint32_t *mitems = (q0.windowed ? S.mitems_w : S.mitems).as<uint32_t>();
+    const unsigned lg = nl ? (unsigned)std::min<uint64_t>((nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
+    const unsigned lgx = lg ? ((lg + 7) / 8) * 8 : 0;
+    const unsigned mg = nmi ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * 8) : 0;
+    uint64_t ub = 0, ue = 0;
+    if (S.n_unit) unit_range(g, q0, &ub, &ue);
+    const unsigned ug = ue > ub ? (unsigned)std::min<uint64_t>((ue - ub + kUnitPerBlock - 1) / kUnitPerBlock,
+                                                               (uint64_t)ctx->num_cus * 8) : 0;
+    const uint64_t n_slot = (uint64_t)ug + lgx + mg;
+    DT_TRY(ensure(ctx, sc.sweep_partials, (n_slot + 1) * k * 8 * sizeof(int64_t)));
+    int64_t *part = sc.sweep_partials.as<int64_t>();
+    // the light and medium passes run on the side streams, beside the unit pass (as in a count)
+    hipStream_t sl = s, sm = s;
+    const bool fork = ctx->side[0] && ((ug ? 1 : 0) + (lgx ? 1 : 0) + (mg ? 1 : 0)) >= 2;
+    if (fork) {
+        DT_HIP(hipEventRecord(ctx->ev_fork, s));
+        if (lgx) {
+            DT_HIP(hipStreamWaitEvent(ctx->side[0], ctx->ev_fork, 0));
+            sl = ctx->side[0];
+        }
+        if (mg) {
+            DT_HIP(hipStreamWaitEvent(ctx->side[1], ctx->ev_fork, 0));
+            sm = ctx->side[1];
+        }
+    }
+    if (ug) {
+        prof_begin(ctx, kProfUnit, s);
+        k_unit_sweep<kUnitBlock><<<ug, kUnitBlock, 0, s>>>(ub, ue, S.unit.as<uint4>(), Q, part, 0);
+        prof_end(ctx, kProfUnit, s);
+        DT_HIP(hipGetLastError());
+    }
+    if (lgx) {
+        prof_begin(ctx, kProfLight, sl);
+        k_light_sweep<kLightBlock><<<lgx, kLightBlock, 0, sl>>>(lr, light, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
+                                                                Q, part, ug);
+        prof_end(ctx, kProfLight, sl);
+        DT_HIP(hipGetLastError());
+    }
+    if (mg) {
+        prof_begin(ctx, kProfMedium, sm);
+        k_medium_sweep<256><<<mg, 256, 0, sm>>>(mr, medium, mitems, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
+                                                Q, part, (uint64_t)ug + lgx);
+        prof_end(ctx, kProfMedium, sm);
+        DT_HIP(hipGetLastError());
+    }
+    if (fork) {
+        if (lgx) {
+            DT_HIP(hipEventRecord(ctx->ev_join[0], sl));
+            DT_HIP(hipStreamWaitEvent(s, ctx->ev_join[0], 0));
+        }
+        if (mg) {
+            DT_HIP(hipEventRecord(ctx->ev_join[1], sm));
+            DT_HIP(hipStreamWaitEvent(s, ctx->ev_join[1], 0));
+        }
+    }
+    prof_begin(ctx, kProfReduce, s);
+    k_reduce_sweep<<<k, 256, 0, s>>>(n_slot, k, part, out_dev, heavy ? 1 : 0);
+    prof_end(ctx, kProfReduce, s);
+    DT_HIP(hipGetLastError());
     return DT_OK;
 }
 

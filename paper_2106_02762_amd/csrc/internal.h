@@ -67,7 +67,7 @@ struct DevMem {
 namespace dt {
 // scratch of one count in flight: per-block partial sums and the heavy path's prefix arrays
 struct Scratch {
-    DevMem partials, heavy_vals;
+    DevMem partials, heavy_vals, sweep_partials;
 };
 struct BatchRunner;
 }  // namespace dt
@@ -237,6 +237,11 @@ int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *emp
 // the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
                   int64_t *cells_dev, Scratch &sc, unsigned parts = 15);
+// delta triples counted in one pass of a sweep
+constexpr uint32_t kSweepMax = 8;
+// Enqueue the counts of k <= kSweepMax queries that share one window (and so one set of list
+// ranges) in one pass over the triangles: out_dev[8 j + i] = type i + 1 of query j.
+int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_dev, hipStream_t s, Scratch &sc);
 void destroy_batch_runner(BatchRunner *r);
 int make_batch_runner(dt_ctx *ctx, BatchRunner **out);
 // plan the item table of k queries and enqueue it on the runner's stream (asynchronous)
