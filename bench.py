@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--delta", type=int, default=3600)
     ap.add_argument("--cpu-window-frac", type=float, default=0.25,
                     help="oracle sample: edges in the first fraction of the time span")
+    ap.add_argument("--cpu-dottt-frac", type=float, default=0.25,
+                    help="CPU DOTTT sample (one thread): edges in the first fraction of the span")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=512,
                     help="graphs of the batched workload (0 skips the batched and served parts)")
@@ -303,7 +305,7 @@ def main():
     count_kernels = {k: round(mean[k], 4) for k in ("unit", "light", "medium", "heavy_prefix",
                                                      "heavy_count", "reduce")}
 
-    cpu = None
+    cpu = cpu_dottt = None
     if not args.no_cpu:
         import oracle
         lo = int(g.t.min())
@@ -321,6 +323,20 @@ def main():
                          f"({ms_sample} of {g.m} edges), deltas ({d},{d},{d})",
                "gpu_matches_oracle": bool((got == want).all())}
         log("cpu baseline", cpu)
+        # the paper's own algorithm, sequential (its setting), on a smaller sample
+        hi2 = lo + int((int(g.t.max()) - lo) * args.cpu_dottt_frac)
+        keep2 = (g.t >= lo) & (g.t <= hi2)
+        a = time.perf_counter()
+        want2, core_s = oracle.cpu_dottt(g.n, g.src, g.dst, g.t, d, d, d, lo, hi2, seconds=True)
+        dottt_s = time.perf_counter() - a
+        got2 = dt.dt_count(h, d, d, d, lo, hi2)
+        cpu_dottt = {"value": round(int(keep2.sum()) / dottt_s, 1), "unit": "temporal edges/s", "cores": 1,
+                     "kind": "cpu_dottt", "seconds": round(dottt_s, 3),
+                     "seconds_after_extraction": round(core_s, 3),
+                     "sample": f"edges with t in the first {args.cpu_dottt_frac:g} of the span "
+                               f"({int(keep2.sum())} of {g.m} edges), deltas ({d},{d},{d})",
+                     "gpu_matches": bool((got2 == want2).all())}
+        log("cpu dottt", cpu_dottt)
 
     batched = served = None
     if args.batch_graphs > 0:
@@ -361,6 +377,7 @@ def main():
                            "alg_bytes": st["alg_bytes"],
                            "achieved_GBs": round(st["alg_bytes"] / (count_ms[str(d)] / 1e3) / 1e9, 2)},
         "cpu_baseline": cpu,
+        "cpu_dottt": cpu_dottt,
         "batched": batched,
         "served": served,
     }

@@ -1,8 +1,9 @@
-"""Python access to the plain CPU oracle (dottt_oracle.c).
+"""Python access to the plain CPU oracle (dottt_oracle.c) and to CPU DOTTT (cpu_dottt.c), the
+paper's own method run sequentially on the CPU.
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's CPU-baseline leg are
 the only callers.  The GPU library never imports or links this package, and this package never
-imports the GPU library.
+imports the GPU library.  The two C files share no code with each other either.
 """
 from __future__ import annotations
 
@@ -15,7 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dottt_oracle.c")
 _LIB = os.path.join(_HERE, "libdottt_oracle.so")
+_SRC_CPU = os.path.join(_HERE, "cpu_dottt.c")
+_LIB_CPU = os.path.join(_HERE, "libcpu_dottt.so")
 _lib = None
+_lib_cpu = None
 
 INT64_MAX = (1 << 63) - 1
 INT64_MIN = -(1 << 63)
@@ -37,14 +41,20 @@ class _Stats(ctypes.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP) into oracle/libdottt_oracle.so."""
-    global _lib
+    """Compile the oracle with gcc (OpenMP) into oracle/libdottt_oracle.so and CPU DOTTT (one
+    thread) into oracle/libcpu_dottt.so."""
+    global _lib, _lib_cpu
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-Wall", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
         _lib = None
+    if force or not os.path.exists(_LIB_CPU):
+        tmp = _LIB_CPU + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC_CPU])
+        os.replace(tmp, _LIB_CPU)
+        _lib_cpu = None
     return _LIB
 
 
@@ -127,3 +137,32 @@ def triangles(n, src, dst, t, t_lo=INT64_MIN, t_hi=INT64_MAX):
     if k2 != k:
         raise OracleError("triangle count changed between calls")
     return out[:k]
+
+
+def _load_cpu():
+    global _lib_cpu
+    if _lib_cpu is None:
+        if not os.path.exists(_LIB_CPU):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_CPU)
+        P = ctypes.c_void_p
+        lib.cpu_dottt_count.argtypes = [ctypes.c_uint32, ctypes.c_uint64, P, P, P, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double)]
+        lib.cpu_dottt_count.restype = ctypes.c_int
+        _lib_cpu = lib
+    return _lib_cpu
+
+
+def cpu_dottt(n, src, dst, t, d13, d12, d23, t_lo=INT64_MIN, t_hi=INT64_MAX, seconds=False):
+    """Per-type counts (int64[8]) by the paper's own algorithm on one CPU thread; with
+    seconds=True also the time of its ordering, enumeration and counting steps."""
+    src, dst, t = _arrs(src, dst, t)
+    ty = np.zeros(8, dtype=np.int64)
+    sec = ctypes.c_double(0.0)
+    rc = _load_cpu().cpu_dottt_count(int(n), int(src.shape[0]), _ptr(src), _ptr(dst), _ptr(t),
+                                     int(d13), int(d12), int(d23), int(t_lo), int(t_hi),
+                                     ty.ctypes.data, ctypes.byref(sec))
+    if rc != 0:
+        raise OracleError(f"cpu_dottt_count failed: {rc}")
+    return (ty, sec.value) if seconds else ty
