@@ -249,6 +249,22 @@ def main():
     value = g.m / (ms_step / 1e3)
     log(f"step {ms_step:.2f} ms -> {value:.3e} edges/s")
 
+    # the one-shot path: ordering, orientation and enumeration that counts as it goes (no stored
+    # triangle list); it drops the build, which is made again afterwards
+    ts = []
+    for _ in range(args.steps + 1):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        o1 = dt.dt_count_oneshot(h, d, d, d)
+        ts.append((time.perf_counter() - a) * 1e3)
+    p1 = dt.dt_ctx_last_profile(ctx)
+    oneshot = {"ms": round(statistics.median(ts[1:]), 3),
+               "edges_per_s": round(g.m / (statistics.median(ts[1:]) / 1e3), 1),
+               "fused_enumerate_count_ms": round(p1["tri_fill"], 3),
+               "matches_step": bool((o1 == out).all())}
+    log("oneshot", oneshot)
+    dt.dt_graph_build(h)
+
     # count alone on the resident build, per delta (the count does not depend on delta)
     count_ms = {}
     for dd in (600, 3600, 86400):
@@ -361,6 +377,7 @@ def main():
         "count_ms": count_ms,
         "count_edges_per_s": round(g.m / (count_ms[str(d)] / 1e3), 1),
         "sweep": sweep,
+        "oneshot": oneshot,
         "kernel_ms": {k: round(v, 4) for k, v in mean.items()},
         "build_ms": {"peel": round(st["ms_peel"], 3), "orient": round(st["ms_orient"], 3),
                      "triangles": round(st["ms_triangles"], 3),

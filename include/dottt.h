@@ -158,6 +158,16 @@ int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stre
  * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
 int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);
 
+/* One-shot count: the whole method for one query from the loaded graph -- degeneracy ordering,
+ * orientation, and triangle enumeration that counts each triangle as it is found (Algorithm 4 with
+ * the enumeration of Section 5 in one pass), without storing the triangle list: a triangle with
+ * one temporal edge per pair is tested at once, a light one counted pairwise by its lane, and only
+ * the few others are kept for the medium and heavy paths.  For graphs whose triangle list would
+ * not fit and for single queries.  The result equals dt_count's.  Any earlier build is dropped
+ * (dt_count then returns DT_ENOTBUILT until dt_graph_build); the graph's ordering is replaced.
+ * out: host int64[8].  Synchronous on the context's stream. */
+int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]);
+
 /* A delta sweep on one graph (the parameter sweeps of Section 6, Figures 1 and 5): the counts of
  * k delta triples that share one window [t_lo, t_hi], out[8 j + i] = type i + 1 of queries[j],
  * equal to k separate dt_count calls.  Each pass over the triangles counts up to 8 triples, so

@@ -332,6 +332,54 @@ int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]) {
     return DT_OK;
 }
 
+int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]) {
+    clear_error();
+    DT_TRY(check_graph(g, false));
+    if (!out) return fail(DT_EINVAL, "null output");
+    DQuery dq;
+    bool empty = false;
+    DT_TRY(normalise_query(g, q, &dq, &empty));
+    for (int i = 0; i < 8; ++i) out[i] = 0;
+    if (empty) return DT_OK;
+    dt_ctx *ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    // the cached products of an earlier build refer to the ordering about to be replaced
+    g->built = false;
+    g->sched = Schedule();
+    g->n_tri = 0;
+    double t0 = now_ms();
+    DT_TRY(peel(g));
+    double t1 = now_ms();
+    DT_TRY(orient(g));
+    double t2 = now_ms();
+    int64_t *o = ctx->out8.as<int64_t>();
+    DevMem rest;
+    uint64_t n_rest = 0, ntri = 0, cand = 0;
+    DT_TRY(fused_count(g, dq, o, rest, &n_rest, &ntri, &cand));
+    g->tri_candidates = cand;
+    int rc = DT_OK;
+    if (n_rest) {
+        // the triangles for the medium and heavy paths: a schedule of their own, then a count
+        g->n_tri = n_rest;
+        rc = make_schedule(g, rest);
+        if (rc == DT_OK) rc = count_enqueue(g, dq, o + 8, ctx->stream, false, nullptr, ctx->scratch);
+    } else {
+        DT_HIP(hipMemsetAsync(o + 8, 0, 8 * sizeof(int64_t), ctx->stream));
+    }
+    if (rc == DT_OK) {
+        DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+        DT_HIP(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < 8; ++i) out[i] = ctx->pinned_out[i] + ctx->pinned_out[8 + i];
+    }
+    g->sched = Schedule();
+    g->n_tri = ntri;
+    g->ms_peel = t1 - t0;
+    g->ms_orient = t2 - t1;
+    g->ms_tri = now_ms() - t2;
+    g->ms_sched = 0;
+    return rc;
+}
+
 int dt_count_sweep(dt_graph *g, uint64_t k, const dt_query *queries, int64_t *out) {
     clear_error();
     if (!queries || !out) return fail(DT_EINVAL, "null queries or output");

@@ -697,6 +697,10 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     return DT_OK;
 }
 
+void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipStream_t s) {
+    k_reduce<<<1, 256, 0, s>>>(n_part, part, out8_dev);
+}
+
 // A sweep: k <= kSweepMax queries with one window.  The unit, light and medium kernels visit each
 // triangle's data once per pass and count it for every delta triple (records and lists are read
 // from HBM once; the repeats of a block's light and medium triangles hit the caches); the rare heavy

@@ -310,6 +310,39 @@ __device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, c
     }
 }
 
+// light triangles: P <= light_pair_cap and at most kLightVw edges on {v,w}
+constexpr uint64_t kLightVw = 64;
+
+// The unit record of triangle (e_uv, e_uw, e_vw), each pair holding one temporal edge: the edge's
+// key sits at eoff[2e] whichever its direction; the direction bit is 1 (towards the earlier vertex
+// of u < v < w) when the pair's forward part [eoff[2e], eoff[2e+1]) is empty.
+__device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint32_t e_vw,
+                                             const uint32_t *__restrict__ eoff,
+                                             const uint64_t *__restrict__ key, int shift) {
+    const uint32_t es[3] = {e_uv, e_uw, e_vw};
+    uint64_t k[3];
+    int dir[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1];
+        k[p] = key[a];
+        dir[p] = a == b ? 1 : 0;
+    }
+    // pairs in key order: first, second, third (0 = uv, 1 = uw, 2 = vw)
+    int o0 = 0, o1 = 1, o2 = 2;
+    if (k[o1] < k[o0]) { int x = o0; o0 = o1; o1 = x; }
+    if (k[o2] < k[o1]) { int x = o1; o1 = o2; o2 = x; }
+    if (k[o1] < k[o0]) { int x = o0; o0 = o1; o1 = x; }
+    // Figure 3: pi1 (uv, uw, vw), pi2 (uw, uv, vw), pi3 (uv, vw, uw), pi4 (uw, vw, uv),
+    // pi5 (vw, uv, uw), pi6 (vw, uw, uv)
+    const int pi = o0 == 0 ? (o1 == 1 ? 1 : 3) : (o0 == 1 ? (o1 == 0 ? 2 : 4) : (o1 == 0 ? 5 : 6));
+    const int rho = rho_of(dir[0], dir[1], dir[2]);
+    const int type = psi_of(pi, rho);
+    const uint32_t t1 = (uint32_t)(k[o0] >> shift), t2 = (uint32_t)(k[o1] >> shift),
+                   t3 = (uint32_t)(k[o2] >> shift);
+    return make_uint4(t1, t2 - t1, t3 - t2, (uint32_t)(((pi - 1) * 8 + (rho - 1)) << 8) | (uint32_t)(type - 1));
+}
+
 // ---------------------------------------------------------------------------------------------
 // unit path: one record per triangle with one temporal edge on each pair
 // ---------------------------------------------------------------------------------------------

@@ -224,6 +224,11 @@ int orient(dt_graph *g);
 // every static triangle as (e_uv, e_uw, e_vw) DAG edge ids; *ntri and *cand (candidates tested)
 int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand);
 int make_schedule(dt_graph *g, DevMem &tri);
+// One-shot pass: enumerate the triangles of the oriented graph and count the unit and light ones
+// for query q as they are found (sum to out8_dev); the others go to `rest` (*n_rest triangles,
+// three DAG edge ids each).  *ntri: all static triangles; *cand: candidates tested.
+int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, uint64_t *n_rest, uint64_t *ntri,
+                uint64_t *cand);
 // unit records [*b, *e) that can hold triangles inside the query's window (all when unwindowed)
 void unit_range(const dt_graph *g, const DQuery &q, uint64_t *b, uint64_t *e);
 // the ranges of a cell-ordered list (cell starts ix, kCells + 1 entries) that can hold triangles
@@ -237,6 +242,8 @@ int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *emp
 // the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
                   int64_t *cells_dev, Scratch &sc, unsigned parts = 15);
+// sum of n_part int64[8] partials into out8_dev, on stream s
+void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipStream_t s);
 // delta triples counted in one pass of a sweep
 constexpr uint32_t kSweepMax = 8;
 // Enqueue the counts of k <= kSweepMax queries that share one window (and so one set of list

@@ -25,17 +25,15 @@ __device__ __forceinline__ uint32_t ceil_log2_1(uint32_t s) {   // ceil(log2(s +
 }
 
 // class 0 light, 1 medium, 2 heavy, 3 unit; force: 0 by the caps, 1 light, 2 heavy, 3 medium.
-// A light lane searches the {v,w} lists in global memory once per pair, so a triangle whose {v,w}
-// pair carries more than kLightVw edges goes to the medium path, whose wavefront shares those
-// searches' list from LDS.
-constexpr uint64_t kLightVw = 64;
+// A light lane searches the {v,w} lists once per pair, so a triangle whose {v,w} pair carries more
+// than kLightVw edges goes to the medium path, which walks only the pairs within d13.
 __device__ __forceinline__ int tri_class(uint64_t P, uint64_t s_vw, uint64_t cap_l, uint64_t cap_m,
                                          uint32_t force, bool unit) {
     if (force == 0 && unit) return 3;
     if (force == 1) return 0;
     if (force == 2) return 2;
     if (force == 3) return P < (1ull << 31) ? 1 : 2;
-    return P <= cap_l && s_vw <= kLightVw ? 0 : (P <= cap_m ? 1 : 2);
+    return P <= cap_l && s_vw <= cdev::kLightVw ? 0 : (P <= cap_m ? 1 : 2);
 }
 
 constexpr int kPartWords = 6;   // per block: sum_sigma3 lo, hi, bytes, light, medium, unit bytes
@@ -104,36 +102,6 @@ k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__r
     }
 }
 
-// The unit record of triangle (e_uv, e_uw, e_vw), each pair holding one temporal edge: the edge's
-// key sits at eoff[2e] whichever its direction; the direction bit is 1 (towards the earlier vertex
-// of u < v < w) when the pair's forward part [eoff[2e], eoff[2e+1]) is empty.
-__device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint32_t e_vw,
-                                             const uint32_t *__restrict__ eoff,
-                                             const uint64_t *__restrict__ key, int shift) {
-    const uint32_t es[3] = {e_uv, e_uw, e_vw};
-    uint64_t k[3];
-    int dir[3];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1];
-        k[p] = key[a];
-        dir[p] = a == b ? 1 : 0;
-    }
-    // pairs in key order: first, second, third (0 = uv, 1 = uw, 2 = vw)
-    int o0 = 0, o1 = 1, o2 = 2;
-    if (k[o1] < k[o0]) { int x = o0; o0 = o1; o1 = x; }
-    if (k[o2] < k[o1]) { int x = o1; o1 = o2; o2 = x; }
-    if (k[o1] < k[o0]) { int x = o0; o0 = o1; o1 = x; }
-    // Figure 3: pi1 (uv, uw, vw), pi2 (uw, uv, vw), pi3 (uv, vw, uw), pi4 (uw, vw, uv),
-    // pi5 (vw, uv, uw), pi6 (vw, uw, uv)
-    const int pi = o0 == 0 ? (o1 == 1 ? 1 : 3) : (o0 == 1 ? (o1 == 0 ? 2 : 4) : (o1 == 0 ? 5 : 6));
-    const int rho = cdev::rho_of(dir[0], dir[1], dir[2]);
-    const int type = cdev::psi_of(pi, rho);
-    const uint32_t t1 = (uint32_t)(k[o0] >> shift), t2 = (uint32_t)(k[o1] >> shift),
-                   t3 = (uint32_t)(k[o2] >> shift);
-    return make_uint4(t1, t2 - t1, t3 - t2, (uint32_t)(((pi - 1) * 8 + (rho - 1)) << 8) | (uint32_t)(type - 1));
-}
-
 // Window cell of a light or medium triangle: slice of F (the latest first-edge time over its three
 // pairs) times kSlices plus slice of L (the earliest last-edge time).  Each pair's two direction
 // lists are key-sorted, so its first and last edges are at their ends.
@@ -199,7 +167,7 @@ k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__r
             const uint64_t pos = run[k] + (((before + x - f) >> (16 * k)) & 0xffffull);
             const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
             if (k == 3) {
-                const uint4 r = unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
+                const uint4 r = cdev::unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
                 urec[pos] = r;
                 ubkt[pos] = (uint16_t)(r.x >> bshift);
             } else {

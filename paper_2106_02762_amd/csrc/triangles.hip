@@ -18,7 +18,7 @@
 // same steps on global memory.
 #include <algorithm>
 
-#include "internal.h"
+#include "count_dev.h"
 
 namespace dt {
 
@@ -66,14 +66,71 @@ __device__ __forceinline__ uint32_t owner(const uint32_t *pre, uint32_t du, uint
     return lo - 1;
 }
 
+// What the one-shot (fused) pass needs to count triangles as it finds them.
+struct FusedArgs {
+    const uint32_t *eoff;
+    const uint64_t *key;
+    DQuery q;
+    cdev::UQuery u;
+    uint32_t unit_ok;              // unit records are exact (time span below 2^31)
+    uint64_t cap_l;                // light rule: P <= cap_l and at most kLightVw {v,w} edges
+    int shift;
+    uint32_t *rest;                // other triangles, three DAG edge ids each
+    uint64_t rest_cap;
+    unsigned long long *rest_n;
+    int64_t *part;                 // int64[8] per wavefront of the grid
+    unsigned long long *s3;        // sum of sigma_uv sigma_uw sigma_vw, 128 bits (low, high)
+};
+
 // Buffered output: a wavefront collects its triangles in LDS and appends them to the list with one
-// atomic per kOut triangles.  Positions past `cap` are counted but not written.
+// atomic per kOut triangles.  Positions past `cap` are counted but not written.  In the one-shot
+// pass (FUSED) a full buffer is counted instead: each lane takes every 64th buffered triangle;
+// one with a single temporal edge per pair is tested as a unit record, a light one is counted
+// pairwise in the lane, and the others go to the rest list for the medium and heavy paths.
+template <bool FUSED>
 struct TriSink {
     uint32_t *buf;      // LDS, 3 * kOut words
     uint32_t n;         // triangles buffered
     uint32_t *tri;
     uint64_t cap;
     unsigned long long *total;
+    const FusedArgs *fa;
+    int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long s3lo = 0, s3hi = 0;
+
+    __device__ __forceinline__ void count_one(uint32_t a, uint32_t b, uint32_t c) {
+        const FusedArgs &F = *fa;
+        const uint32_t *eoff = F.eoff;
+        const uint64_t s_uv = eoff[2 * a + 2] - eoff[2 * a], s_uw = eoff[2 * b + 2] - eoff[2 * b],
+                       s_vw = eoff[2 * c + 2] - eoff[2 * c];
+        const unsigned __int128 p3 = (unsigned __int128)(s_uv * s_uw) * s_vw;
+        const unsigned long long lo = (unsigned long long)p3;
+        s3lo += lo;
+        s3hi += (unsigned long long)(p3 >> 64) + (s3lo < lo ? 1ull : 0ull);
+        if (F.unit_ok && s_uv == 1 && s_uw == 1 && s_vw == 1) {
+            uint32_t cc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            cdev::unit_one<false>(cdev::unit_record(a, b, c, eoff, F.key, F.shift), F.u, cc, nullptr);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += cc[j];
+        } else if (s_uv * s_uw <= F.cap_l && s_vw <= cdev::kLightVw) {
+            cdev::Acc<false> A;
+            cdev::Lists L;
+            cdev::load_lists(eoff, a, b, c, F.key, F.q, L);
+            cdev::light_pairs<false, 0, 0>(F.key, L, F.q, A);
+            cdev::light_pairs<false, 0, 1>(F.key, L, F.q, A);
+            cdev::light_pairs<false, 1, 0>(F.key, L, F.q, A);
+            cdev::light_pairs<false, 1, 1>(F.key, L, F.q, A);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += A.t[j];
+        } else {
+            const unsigned long long r = atomicAdd(F.rest_n, 1ull);
+            if (r < F.rest_cap) {
+                F.rest[3 * r] = a;
+                F.rest[3 * r + 1] = b;
+                F.rest[3 * r + 2] = c;
+            }
+        }
+    }
 
     __device__ __forceinline__ void flush(unsigned lane) {
         if (n == 0) return;
@@ -81,9 +138,13 @@ struct TriSink {
         __builtin_amdgcn_wave_barrier();
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
-        base = __shfl(base, 0, 64);
-        for (uint32_t x = lane; x < 3 * n; x += 64)
-            if (base + x / 3 < cap) tri[3 * base + x] = buf[x];
+        if (FUSED) {
+            for (uint32_t x = lane; x < n; x += 64) count_one(buf[3 * x], buf[3 * x + 1], buf[3 * x + 2]);
+        } else {
+            base = __shfl(base, 0, 64);
+            for (uint32_t x = lane; x < 3 * n; x += 64)
+                if (base + x / 3 < cap) tri[3 * base + x] = buf[x];
+        }
         __builtin_amdgcn_wave_barrier();
         n = 0;
     }
@@ -104,10 +165,11 @@ struct TriSink {
     }
 };
 
+template <bool FUSED>
 __global__ void __launch_bounds__(kBlock)
 k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
       uint32_t *__restrict__ tri, uint64_t cap, unsigned long long *__restrict__ total,
-      unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand) {
+      unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa) {
     __shared__ uint32_t s_nbr[kWaves][kCap];
     __shared__ uint32_t s_pre[kWaves][kCap + 1];
     __shared__ uint32_t s_vb[kWaves][kCap];
@@ -117,7 +179,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
     uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *vb_lds = s_vb[wave], *dv_lds = s_dv[wave],
              *vn_lds = s_vn[wave];
-    TriSink out{s_out[wave], 0, tri, cap, total};
+    TriSink<FUSED> out{s_out[wave], 0, tri, cap, total, &fa};
     unsigned long long wave_cand = 0;   // candidates tested, added once per wave
     for (;;) {
         uint32_t ticket = 0;
@@ -252,6 +314,26 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     }
     out.flush(lane);
     if (lane == 0) atomicAdd(cand, wave_cand);
+    if (FUSED) {
+        // this wavefront's sums: its partial slot, and the 128-bit multiplicity sum with carry
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t v = cdev::wave_sum((long long)out.acc[j]);
+            if (lane == 0) fa.part[8 * ((uint64_t)blockIdx.x * kWaves + wave) + j] = v;
+        }
+        unsigned long long lo = out.s3lo, hi = out.s3hi;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+            const unsigned long long sum = lo + lo2;
+            hi = hi + hi2 + (sum < lo ? 1ull : 0ull);
+            lo = sum;
+        }
+        if (lane == 0) {
+            const unsigned long long old = atomicAdd(&fa.s3[0], lo);
+            atomicAdd(&fa.s3[1], hi + (old + lo < old ? 1ull : 0ull));
+        }
+    }
 }
 
 }  // namespace
@@ -273,8 +355,8 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint
         DT_HIP(hipMemsetAsync(ctr.ptr, 0, 32, st));
         unsigned long long *c64 = reinterpret_cast<unsigned long long *>(ctr.as<uint8_t>() + 8);
         prof_begin(ctx, kProfTriFill, st);
-        k_tri<<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
-                                       tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1);
+        k_tri<false><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
+                                              tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1, FusedArgs{});
         prof_end(ctx, kProfTriFill, st);
         DT_HIP(hipGetLastError());
         uint64_t h[2] = {0, 0};
@@ -285,6 +367,62 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint
         if (h[0] <= cap) return DT_OK;
         cap = h[0];
         tri.reset();
+    }
+    return fail(DT_EDEVICE, "triangle enumeration changed between passes");
+}
+
+int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, uint64_t *n_rest, uint64_t *ntri_out,
+                uint64_t *cand_out) {
+    dt_ctx *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    *n_rest = *ntri_out = *cand_out = 0;
+    const unsigned grid = (unsigned)ctx->num_cus * 8;
+    const uint64_t n_part = (uint64_t)grid * kWaves;
+    DevMem ctr, part;
+    DT_TRY(dev_alloc(ctx, ctr, 256));
+    DT_TRY(dev_alloc(ctx, part, n_part * 8 * sizeof(int64_t)));
+    FusedArgs fa{};
+    fa.eoff = g->eoff.as<uint32_t>();
+    fa.key = g->key.as<uint64_t>();
+    fa.q = q;
+    fa.u = cdev::unit_query(q);
+    fa.unit_ok = g->span <= kUnitMaxSpan ? 1u : 0u;
+    fa.cap_l = g->tuning.light_pair_cap;
+    fa.shift = g->shift;
+    fa.part = part.as<int64_t>();
+    // the rest list: sized at an eighth of the static pairs, the pass runs again when it overflows
+    uint64_t rcap = std::max<uint64_t>(g->m_s / 8, 1ull << 16);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        DT_TRY(dev_alloc(ctx, rest, rcap * 12));
+        // counters: [0] next ticket (32-bit), [1] triangles, [2] candidates, [3] rest, [4..5] sum of products
+        DT_HIP(hipMemsetAsync(ctr.ptr, 0, 64, st));
+        unsigned long long *c64 = reinterpret_cast<unsigned long long *>(ctr.as<uint8_t>() + 8);
+        fa.rest = rest.as<uint32_t>();
+        fa.rest_cap = rcap;
+        fa.rest_n = c64 + 2;
+        fa.s3 = c64 + 3;
+        prof_begin(ctx, kProfTriFill, st);
+        if (n)
+            k_tri<true><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), nullptr, 0,
+                                                 c64, ctr.as<unsigned>(), c64 + 1, fa);
+        else
+            DT_HIP(hipMemsetAsync(part.ptr, 0, n_part * 8 * sizeof(int64_t), st));
+        prof_end(ctx, kProfTriFill, st);
+        DT_HIP(hipGetLastError());
+        uint64_t h[5] = {0, 0, 0, 0, 0};
+        DT_HIP(hipMemcpyAsync(h, c64, 40, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipStreamSynchronize(st));
+        if (h[2] <= rcap) {
+            *ntri_out = h[0];
+            *cand_out = h[1];
+            *n_rest = h[2];
+            if (h[4] != 0 || (h[3] >> 63)) return fail(DT_EOVERFLOW, "the sum of multiplicity products exceeds 2^63; counts may not fit int64");
+            count_reduce(n_part, part.as<int64_t>(), out8_dev, st);
+            return DT_OK;
+        }
+        rcap = h[2];
+        rest.reset();
     }
     return fail(DT_EDEVICE, "triangle enumeration changed between passes");
 }

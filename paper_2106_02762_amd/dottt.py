@@ -30,7 +30,7 @@ INT64_MIN = -(1 << 63)
 ENTRY_POINTS = (
     "dt_strerror", "dt_last_error", "dt_ctx_create", "dt_ctx_destroy", "dt_ctx_memory",
     "dt_graph_load", "dt_graph_load_device", "dt_graph_build", "dt_graph_set_tuning",
-    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_cells", "dt_count_sweep", "dt_count_batch",
+    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
     "dt_graph_order", "dt_graph_triangles", "dt_graph_free", "dt_server_start",
     "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stop",
     "dt_ctx_set_profiling", "dt_ctx_last_profile",
@@ -108,6 +108,7 @@ def library():
         "dt_count": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_async": (I, [P, ctypes.POINTER(dt_query), P, P]),
         "dt_count_cells": (I, [P, ctypes.POINTER(dt_query), P]),
+        "dt_count_oneshot": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_sweep": (I, [P, U64, P, P]),
         "dt_count_batch": (I, [P, U64, P, P, P]),
         "dt_graph_order": (I, [P, P, P]),
@@ -241,6 +242,14 @@ def dt_count_cells(g, d13, d12, d23, t_lo=INT64_MIN, t_hi=DT_INF):
     out = np.zeros(48, dtype=np.int64)
     _check(library().dt_count_cells(g, ctypes.byref(q), out.ctypes.data), "dt_count_cells")
     return out.reshape(6, 8)
+
+
+def dt_count_oneshot(g, d13, d12, d23, t_lo=INT64_MIN, t_hi=DT_INF):
+    """Ordering, orientation and a fused enumerate-and-count pass for one query; int64[8]."""
+    q = make_query(d13, d12, d23, t_lo, t_hi)
+    out = np.zeros(8, dtype=np.int64)
+    _check(library().dt_count_oneshot(g, ctypes.byref(q), out.ctypes.data), "dt_count_oneshot")
+    return out
 
 
 def dt_count_sweep(g, deltas, t_lo=INT64_MIN, t_hi=DT_INF):
