@@ -1,18 +1,22 @@
 // Degeneracy ordering by a parallel k-core peel (Section 3: "removing a vertex with minimum degree
 // repeatedly"; the degeneracy is the largest core number).
 //
-// Level k removes every remaining vertex whose remaining degree is <= k, in rounds: the vertices
-// found by a scan of the remaining ones, then those whose degree falls to k while their
-// neighbours are removed.  A vertex's position in the ordering is the order in which it joined the
-// removal queue.  When v joins, at most k of its neighbours are still unqueued, and every
-// neighbour that comes after v in the ordering is one of them, so the out-degree of v in G_prec
-// is at most k = core(v) <= degeneracy, the property Theorem 1's bound rests on.  (Different
-// removal orders give different orientations but the same counts: each static triangle is
-// counted once under its own naming u < v < w.)
+// Level k removes every remaining vertex whose remaining degree is <= k: the vertices found by a
+// scan of the remaining ones, then those whose degree falls to k while their neighbours are
+// removed.  A vertex takes its position in the ordering no later than the start of its own
+// removal, and positions are handed out in time order.  When v is queued at most k of its
+// neighbours are not yet removed; a neighbour placed after v started its removal after v was
+// placed, hence after v was queued, so it is one of those: the out-degree of v in G_prec is at
+// most k = core(v) <= degeneracy, the property Theorem 1's bound rests on.  (Different removal
+// orders give different orientations but the same counts: each static triangle is counted once
+// under its own naming u < v < w.)
 //
 // The whole peel is one cooperative (co-resident) grid of a few blocks: levels and rounds are
 // separated by grid barriers instead of kernel launches and host round trips, since power-law
-// graphs need thousands of rounds, most with frontiers of a few vertices.  A barrier's cost grows
+// graphs need thousands of removal steps, most with frontiers of a few vertices.  Within a level,
+// a block removes the vertices its own removals queued right away (a cascade local to the block,
+// with workgroup barriers only), so a grid round usually ends a level; only vertices queued past a
+// full staging list wait for another round.  A barrier's cost grows
 // with the number of blocks that meet at it, so the grid is small and wide (32 blocks of 1024
 // threads), and the barrier is a monotonic arrival counter that every block polls.  Counters that
 // decide the next step (queue positions taken in a phase, survivors of a level scan) rotate over
@@ -32,14 +36,18 @@ namespace dt {
 namespace {
 
 constexpr unsigned kBlock = 1024;
-constexpr unsigned kGridBlocks = 32;
+constexpr unsigned kGridBlocks = 32;   // blocks of the latency-bound levels
+constexpr unsigned kGridWide = 256;    // blocks while more than kWideUntil vertices remain
+constexpr uint32_t kWideUntil = 1000000;   // measured best on the 61M-edge graph (0.3M: +0.5 ms)
 constexpr uint32_t kTail = 16384;   // most vertices the one-workgroup finish takes (16-bit ids)
 // LDS of a peel block.  The one-workgroup finish keeps there the local CSR rows (kTail + 1
 // words), the degrees (16-bit, two per word), the queue of local ids (16-bit) and a removed-vertex
 // bitmap; on the grid the same words stage the vertices a block queues in one round.
 constexpr uint32_t kRowWords = kTail + 1, kDegWords = kTail / 2, kQWords = kTail / 2, kRemWords = kTail / 32;
 constexpr uint32_t kLdsWords = kRowWords + kDegWords + kQWords + kRemWords;
-constexpr uint32_t kStage = kLdsWords;
+// on the grid the words hold two staging halves: the vertices a block is removing and those their
+// removal queues
+constexpr uint32_t kStage = kLdsWords / 2;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr long kSpinLimit = 1l << 26;
 // degree of a vertex queued during removal rounds: negative, and it stays negative under the
@@ -49,6 +57,7 @@ constexpr int kRemoved = -(1 << 30);
 struct PeelCtl {
     unsigned int qtail;      // vertices queued in all (written at the end)
     unsigned int qc[3];      // per grid phase mod 3: queue positions taken in that phase
+    unsigned int ovc[3];     // per grid phase mod 3: vertices that phase queued past a full stage
     unsigned int arrived;    // barrier arrivals (only ever increases)
     unsigned int error;      // a barrier gave up waiting, or a consistency check failed
     unsigned int rounds;     // removal rounds
@@ -65,15 +74,15 @@ __device__ __forceinline__ int ld_relaxed(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier number `gen` (every block calls barriers 0, 1, 2, ... in the same order).  Arrivals
-// only ever increase, so barrier gen is complete once nblk * (gen + 1) blocks have arrived: each
-// block's first thread publishes its block's writes, arrives, and polls the count; no block has to
-// release the others.  A barrier that waits far longer than any peel could take sets an error
-// flag and lets its block go.
-__device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, unsigned gen) {
+// Grid barrier.  Arrivals only ever increase, and every block passes the same barriers in the same
+// order with the same participants, so a barrier is complete once `target` arrivals (the running
+// sum of the participants of every barrier so far) have been counted: each block's first thread
+// publishes its block's writes, arrives, and polls the count; no block has to release the others.
+// A barrier that waits far longer than any peel could take sets an error flag and lets its block
+// go.
+__device__ void grid_barrier(PeelCtl *ctl, unsigned target) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned target = nblk * (gen + 1);
         __threadfence();
         const unsigned a = atomicAdd(&ctl->arrived, 1u) + 1;
         if (a < target) {
@@ -92,21 +101,21 @@ __device__ void grid_barrier(PeelCtl *ctl, unsigned nblk, unsigned gen) {
     __syncthreads();
 }
 
-// A vertex whose degree a removal took from k + 1 to k joins the block's staging list; the block
-// appends the list to the queue with one atomic at the end of the round (any order of the
-// vertices queued in one round is a valid ordering: each has at most k neighbours that are not
-// removed before the round ends).  A full staging list sends the rest straight to the queue.
-__device__ __forceinline__ void enqueue(uint32_t v, uint32_t k, uint32_t n, uint32_t *level,
-                                        uint32_t *queue, int *deg, unsigned *qc, uint32_t qbase,
-                                        uint32_t *s_stage, unsigned *s_cnt) {
+// A vertex whose degree a removal took from k + 1 to k joins the block's staging list, which the
+// same block removes next (its position in the ordering is taken then); a full staging list sends
+// the rest to the overflow list, which the next grid phase takes.
+__device__ __forceinline__ void enqueue(uint32_t v, uint32_t k, uint32_t n, uint32_t *level, int *deg,
+                                        unsigned *ovc, uint32_t *ovf, unsigned *err, uint32_t *s_stage,
+                                        unsigned *s_cnt) {
     level[v] = k;
     __hip_atomic_store(&deg[v], kRemoved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t p = atomicAdd(s_cnt, 1u);
     if (p < kStage) {
         s_stage[p] = v;
     } else {
-        const uint32_t q = qbase + atomicAdd(qc, 1u);
-        if (q < n) queue[q] = v;
+        const uint32_t o = atomicAdd(ovc, 1u);
+        if (o < n) ovf[o] = v;
+        else atomicOr(err, 8u);
     }
 }
 
@@ -119,29 +128,35 @@ __device__ __forceinline__ unsigned wave_min(unsigned x) {
     return x;
 }
 
-__device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_t stride, uint32_t k,
-                                             uint32_t n, const uint32_t *__restrict__ row,
-                                             const uint32_t *__restrict__ col, int *__restrict__ deg,
-                                             uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
-                                             unsigned *qc, uint32_t qbase, uint32_t *s_stage,
-                                             unsigned *s_cnt) {
-    const uint32_t e = row[v + 1];
-    uint32_t j = row[v] + first;
+// remove the adjacency entries [b, e) of one vertex (this lane: first, first + stride, ...)
+__device__ __forceinline__ void remove_range(uint32_t b, uint32_t e, uint32_t first, uint32_t stride, uint32_t k,
+                                             uint32_t n, const uint32_t *__restrict__ col, int *__restrict__ deg,
+                                             uint32_t *__restrict__ level, unsigned *ovc, uint32_t *ovf,
+                                             unsigned *err, uint32_t *s_stage, unsigned *s_cnt) {
+    uint32_t j = b + first;
     // four independent decrements in flight per lane
     for (; j + 3 * stride < e; j += 4 * stride) {
         const uint32_t x0 = col[j], x1 = col[j + stride], x2 = col[j + 2 * stride], x3 = col[j + 3 * stride];
         const int o0 = atomicSub(&deg[x0], 1), o1 = atomicSub(&deg[x1], 1), o2 = atomicSub(&deg[x2], 1),
                   o3 = atomicSub(&deg[x3], 1);
-        if (o0 == (int)k + 1) enqueue(x0, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
-        if (o1 == (int)k + 1) enqueue(x1, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
-        if (o2 == (int)k + 1) enqueue(x2, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
-        if (o3 == (int)k + 1) enqueue(x3, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
+        if (o0 == (int)k + 1) enqueue(x0, k, n, level, deg, ovc, ovf, err, s_stage, s_cnt);
+        if (o1 == (int)k + 1) enqueue(x1, k, n, level, deg, ovc, ovf, err, s_stage, s_cnt);
+        if (o2 == (int)k + 1) enqueue(x2, k, n, level, deg, ovc, ovf, err, s_stage, s_cnt);
+        if (o3 == (int)k + 1) enqueue(x3, k, n, level, deg, ovc, ovf, err, s_stage, s_cnt);
     }
     for (; j < e; j += stride) {
         const uint32_t x = col[j];
         const int old = atomicSub(&deg[x], 1);
-        if (old == (int)k + 1) enqueue(x, k, n, level, queue, deg, qc, qbase, s_stage, s_cnt);
+        if (old == (int)k + 1) enqueue(x, k, n, level, deg, ovc, ovf, err, s_stage, s_cnt);
     }
+}
+
+__device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_t stride, uint32_t k,
+                                             uint32_t n, const uint32_t *__restrict__ row,
+                                             const uint32_t *__restrict__ col, int *__restrict__ deg,
+                                             uint32_t *__restrict__ level, unsigned *ovc, uint32_t *ovf,
+                                             unsigned *err, uint32_t *s_stage, unsigned *s_cnt) {
+    remove_range(row[v], row[v + 1], first, stride, k, n, col, deg, level, ovc, ovf, err, s_stage, s_cnt);
 }
 
 // The last vertices: one workgroup finishes the peel on the subgraph they induce, with local
@@ -296,13 +311,16 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
        int *__restrict__ deg, uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
        uint32_t *__restrict__ alive_a, uint32_t *__restrict__ alive_b, uint32_t *__restrict__ loc,
        uint32_t *__restrict__ rlist, uint32_t *__restrict__ lrow, uint32_t *__restrict__ lvl,
-       uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, PeelCtl *__restrict__ ctl) {
-    const unsigned nblk = gridDim.x;
+       uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, uint32_t *__restrict__ ovf0,
+       uint32_t *__restrict__ ovf1, PeelCtl *__restrict__ ctl) {
+    // the whole grid takes part until few vertices remain; then the first kGridBlocks blocks go on
+    unsigned nblk = gridDim.x;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t gsize = nblk * kBlock;
-    const uint32_t gwave = gtid / 64, nwaves = gsize / 64, lane = threadIdx.x & 63;
+    uint32_t gsize = nblk * kBlock;
+    const uint32_t gwave = gtid / 64, lane = threadIdx.x & 63;
+    uint32_t nwaves = gsize / 64;
     const uint64_t below = (1ull << lane) - 1;
-    unsigned bgen = 0;   // barriers passed
+    unsigned btarget = 0;   // arrivals that complete the next barrier, less its participants
     __shared__ __attribute__((aligned(16))) uint32_t s_mem[kLdsWords];
     __shared__ unsigned s_cnt, s_base;
 
@@ -315,7 +333,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     }
     if (gtid == 0)
         for (int x = 0; x < 3; ++x) ctl->scan[x][1] = 0xffffffffu;
-    grid_barrier(ctl, nblk, bgen++);
+    grid_barrier(ctl, btarget += nblk);
 
     // tail: vertices queued before the current grid phase (a scan or a round); phase ph takes its
     // queue positions tail + [0, qc[ph % 3]) and every block adds the final count after the phase's
@@ -375,7 +393,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
                 }
             }
         }
-        grid_barrier(ctl, nblk, bgen++);
+        grid_barrier(ctl, btarget += nblk);
         tail += ld_relaxed(&ctl->qc[ph % 3]);
         const uint32_t na2 = ld_relaxed(&ctl->scan[lv % 3][0]), md = ld_relaxed(&ctl->scan[lv % 3][1]);
         // the counters of the previous level were read by every block before this barrier: clear
@@ -384,44 +402,115 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             __hip_atomic_store(&ctl->scan[(lv + 2) % 3][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->scan[(lv + 2) % 3][1], 0xffffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->qc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->ovc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ++lv;
         ++ph;
+        // few vertices left: the later levels are latency-bound, and a barrier costs more the
+        // more blocks meet at it, so only the first kGridBlocks blocks go on
+        if (nblk > kGridBlocks && na2 < kWideUntil) {
+            if (blockIdx.x >= kGridBlocks) return;
+            nblk = kGridBlocks;
+            gsize = nblk * kBlock;
+            nwaves = gsize / 64;
+        }
         // no survivors: every remaining vertex is queued at this level, and removing them can
         // queue nothing more
         if (na2 == 0) head = tail;
-        // rounds: remove queue[head, tail).  A frontier of at least one vertex per wavefront is
-        // split by vertex; a smaller one gives each vertex an equal share of the wavefronts.
-        while (head < tail) {
-            if (threadIdx.x == 0) s_cnt = 0;
-            __syncthreads();
-            const uint32_t f = tail - head;
-            if (f >= nwaves) {
-                for (uint32_t i = head + gwave; i < tail; i += nwaves)
-                    remove_edges(queue[i], lane, 64, k, n, row, col, deg, level, queue, &ctl->qc[ph % 3], tail,
-                                 s_mem, &s_cnt);
-            } else {
-                const uint32_t per = nwaves / f;
-                const uint32_t i = gwave / per, sub = gwave % per;
-                if (i < f)
-                    remove_edges(queue[head + i], sub * 64 + lane, per * 64, k, n, row, col, deg,
-                                 level, queue, &ctl->qc[ph % 3], tail, s_mem, &s_cnt);
+        // Rounds.  The frontier of the first is the scan's picks, queue[head, tail); each block
+        // removes its share and then, without a grid barrier, removes the vertices that its own
+        // removals queued (its staging list), step after step, until it queues nothing more; those
+        // take their queue positions when their removal starts.  Only vertices queued past a full
+        // staging list wait for the next round (overflow list; their positions are the round's
+        // first).  A frontier of at least one vertex per wavefront is split by vertex; a smaller one
+        // gives each vertex an equal share of the wavefronts.
+        // Any order of removal within a level is a degeneracy ordering as long as every vertex
+        // takes its position no later than its removal starts: a neighbour placed after it was not
+        // yet removed when it was queued, so it counts among the at most k neighbours it had then.
+        {
+            uint32_t nf = tail - head;
+            const uint32_t *fl = queue + head;
+            bool first = true;
+            while (nf > 0) {
+                uint32_t *ovf_out = (ph & 1) ? ovf1 : ovf0;
+                unsigned *ovc = &ctl->ovc[ph % 3];
+                const uint32_t qbase = first ? tail : tail + nf;
+                if (!first)
+                    for (uint32_t i = gtid; i < nf; i += gsize)
+                        if (tail + i < n) queue[tail + i] = fl[i];
+                uint32_t *stage = s_mem, *front = s_mem + kStage;
+                if (threadIdx.x == 0) s_cnt = 0;
+                __syncthreads();
+                if (nf >= nwaves) {
+                    for (uint32_t i = gwave; i < nf; i += nwaves)
+                        remove_edges(fl[i], lane, 64, k, n, row, col, deg, level, ovc, ovf_out, &ctl->error,
+                                     stage, &s_cnt);
+                } else {
+                    const uint32_t per = nwaves / nf;
+                    const uint32_t i = gwave / per, sub = gwave % per;
+                    if (i < nf)
+                        remove_edges(fl[i], sub * 64 + lane, per * 64, k, n, row, col, deg, level, ovc, ovf_out,
+                                     &ctl->error, stage, &s_cnt);
+                }
+                // the block's own cascade
+                for (uint32_t steps = 0;; ++steps) {
+                    __syncthreads();
+                    const uint32_t c = s_cnt < kStage ? s_cnt : kStage;
+                    if (c == 0 || steps > n) break;
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        s_base = qbase + atomicAdd(&ctl->qc[ph % 3], c);
+                        s_cnt = 0;
+                    }
+                    uint32_t *t = stage;
+                    stage = front;
+                    front = t;
+                    // this wavefront's first vertex and its adjacency bounds, read while the
+                    // positions are being taken (reads only: its removal starts after them)
+                    constexpr uint32_t kBW = kBlock / 64;
+                    const uint32_t wave = threadIdx.x / 64;
+                    const uint32_t per = c >= kBW ? 1 : kBW / c;
+                    const uint32_t i0 = wave / per, sub = wave % per;
+                    uint32_t rb = 0, re = 0;
+                    if (i0 < c) {
+                        const uint32_t v0 = front[i0];
+                        rb = row[v0];
+                        re = row[v0 + 1];
+                    }
+                    __syncthreads();
+                    for (uint32_t x = threadIdx.x; x < c; x += kBlock) {
+                        const uint32_t p = s_base + x;
+                        if (p < n) queue[p] = front[x];
+                    }
+                    if (c >= kBW) {
+                        if (i0 < c)
+                            remove_range(rb, re, lane, 64, k, n, col, deg, level, ovc, ovf_out, &ctl->error, stage,
+                                         &s_cnt);
+                        for (uint32_t i = i0 + kBW; i < c; i += kBW)
+                            remove_edges(front[i], lane, 64, k, n, row, col, deg, level, ovc, ovf_out, &ctl->error,
+                                         stage, &s_cnt);
+                    } else if (i0 < c) {
+                        remove_range(rb, re, sub * 64 + lane, per * 64, k, n, col, deg, level, ovc, ovf_out,
+                                     &ctl->error, stage, &s_cnt);
+                    }
+                }
+                ++rounds;
+                grid_barrier(ctl, btarget += nblk);
+                tail = qbase + ld_relaxed(&ctl->qc[ph % 3]);
+                head = tail;
+                nf = ld_relaxed(ovc);
+                fl = ovf_out;
+                first = false;
+                if (gtid == 0) {
+                    __hip_atomic_store(&ctl->qc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ctl->ovc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                ++ph;
+                if (nf > n) {   // cannot happen: a vertex is queued once
+                    if (gtid == 0) atomicOr(&ctl->error, 8u);
+                    nf = 0;
+                }
             }
-            // append the block's staged vertices to the queue
-            __syncthreads();
-            const uint32_t c = s_cnt < kStage ? s_cnt : kStage;
-            if (threadIdx.x == 0) s_base = c ? tail + atomicAdd(&ctl->qc[ph % 3], c) : 0u;
-            __syncthreads();
-            for (uint32_t x = threadIdx.x; x < c; x += kBlock) {
-                const uint32_t p = s_base + x;
-                if (p < n) queue[p] = s_mem[x];
-            }
-            ++rounds;
-            grid_barrier(ctl, nblk, bgen++);
-            head = tail;
-            tail += ld_relaxed(&ctl->qc[ph % 3]);
-            if (gtid == 0) __hip_atomic_store(&ctl->qc[(ph + 2) % 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ++ph;
         }
         if (tail >= n || ld_relaxed(&ctl->error)) {
             done = true;
@@ -490,7 +579,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             }
         }
     }
-    grid_barrier(ctl, nblk, bgen++);
+    grid_barrier(ctl, btarget += nblk);
     const unsigned long long lres = __hip_atomic_load(&ctl->lres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t R = (uint32_t)lres, total = (uint32_t)(lres >> 32);
     if (R != n - tail || R > kTail || total > lcol_cap || ld_relaxed(&ctl->error)) {
@@ -513,7 +602,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         }
         if (lane == 0 && c != d) atomicOr(&ctl->error, 4u);
     }
-    grid_barrier(ctl, nblk, bgen++);
+    grid_barrier(ctl, btarget += nblk);
     if (blockIdx.x != 0 || ld_relaxed(&ctl->error)) return;
     peel_tail(R, tail, k, rounds, rlist, lrow, lcol, lvl, level, queue, ctl, s_mem);
 }
@@ -529,10 +618,12 @@ int peel(dt_graph *g) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
-    DevMem deg, alive, alive2, ctlm, loc, rlist, lrow, lvl, lcol;
+    DevMem deg, alive, alive2, ctlm, loc, rlist, lrow, lvl, lcol, ovf0, ovf1;
     DT_TRY(dev_alloc(ctx, deg, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, alive2, (uint64_t)n * 4));
+    DT_TRY(dev_alloc(ctx, ovf0, (uint64_t)n * 4));
+    DT_TRY(dev_alloc(ctx, ovf1, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, g->core, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, g->order, (uint64_t)n * 4));
     DT_TRY(dev_alloc(ctx, g->rank, (uint64_t)n * 4));
@@ -555,7 +646,7 @@ int peel(dt_graph *g) {
     int per_cu = 0;
     DT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_peel, kBlock, 0));
     if (per_cu <= 0) return fail(DT_EDEVICE, "peel kernel cannot be resident");
-    unsigned grid = kGridBlocks;
+    unsigned grid = kGridWide;
     if (grid > (unsigned)ctx->num_cus * (unsigned)per_cu) grid = (unsigned)ctx->num_cus * (unsigned)per_cu;
     DT_HIP(hipMemsetAsync(ctlm.ptr, 0, sizeof(PeelCtl), st));
     uint32_t *level = g->core.as<uint32_t>();
@@ -570,7 +661,9 @@ int peel(dt_graph *g) {
     uint16_t *lc = lcol.as<uint16_t>();
     uint64_t lcap = lcol_cap;
     uint32_t tcap = tail_cap;
-    void *args[] = {&nn, &row, &col, &degp, &level, &queue, &aa, &ab, &locp, &rl, &lb, &ld, &lc, &lcap, &tcap, &ctl};
+    uint32_t *o0 = ovf0.as<uint32_t>(), *o1 = ovf1.as<uint32_t>();
+    void *args[] = {&nn, &row, &col, &degp, &level, &queue, &aa, &ab, &locp, &rl, &lb, &ld, &lc, &lcap, &tcap,
+                    &o0, &o1, &ctl};
     prof_begin(ctx, kProfPeel, st);
     DT_HIP(hipLaunchCooperativeKernel((const void *)k_peel, dim3(grid), dim3(kBlock), args, 0, st));
     prof_end(ctx, kProfPeel, st);

@@ -1,6 +1,7 @@
-"""GPU parity of the core peel (the degeneracy ordering of Section 3) in its three regimes: the
-whole peel on the cooperative grid (peel_tail = 1), the whole peel in one workgroup (graphs of at
-most 16384 vertices), and the grid handing its last vertices to one workgroup.  Core numbers must
+"""GPU parity of the core peel (the degeneracy ordering of Section 3) in its regimes: the whole
+peel on the cooperative grid (peel_tail = 1), the whole peel in one workgroup (graphs of at most
+16384 vertices), the grid handing its last vertices to one workgroup, and (on a 600K-vertex graph)
+the full-width grid for the first levels before the narrow one.  Core numbers must
 equal the oracle's exactly (they are unique, unlike the ordering), the ordering must be a
 permutation, and every vertex must have at most core(v) neighbours after it in the ordering (the
 out-degree bound Theorem 1 uses)."""
@@ -52,9 +53,13 @@ def _check(ctx, g, peel_tail, ocore, pairs, query):
         dt.dt_graph_free(h)
 
 
-@pytest.mark.parametrize("name", ["scaled", "batch5", "plain_tiny", "tiny"])
+@pytest.mark.parametrize("name", ["large", "scaled", "batch5", "plain_tiny", "tiny"])
 def test_peel_regimes_match_oracle(ctx, name):
-    if name == "scaled":
+    if name == "large":
+        g = synth.plain_full(n=600_000, ms=8_000_000)    # the whole grid first, then 32 blocks
+        tails = [0, 1]
+        q = (3600, 3600, 3600, dt.INT64_MIN, INF)
+    elif name == "scaled":
         g = synth.plain_full(n=60_000, ms=800_000)       # grid, then one workgroup
         tails = [0, 1, 100, 16384]
         q = (3600, 3600, 3600, dt.INT64_MIN, INF)
