@@ -37,8 +37,10 @@ namespace {
 
 constexpr unsigned kBlock = 1024;
 constexpr unsigned kGridBlocks = 32;   // blocks of the latency-bound levels
-constexpr unsigned kGridWide = 256;    // blocks while more than kWideUntil vertices remain
+constexpr unsigned kGridWide = 256;    // blocks while at least kWideUntil vertices remain
 constexpr uint32_t kWideUntil = 1000000;   // measured best on the 61M-edge graph (0.3M: +0.5 ms)
+constexpr unsigned kGridMid = 64;      // blocks while at least kMidUntil vertices remain
+constexpr uint32_t kMidUntil = 200000;   // 0.1M-0.4M and 128 blocks measured alike
 constexpr uint32_t kTail = 16384;   // most vertices the one-workgroup finish takes (16-bit ids)
 // LDS of a peel block.  The one-workgroup finish keeps there the local CSR rows (kTail + 1
 // words), the degrees (16-bit, two per word), the queue of local ids (16-bit) and a removed-vertex
@@ -313,7 +315,8 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
        uint32_t *__restrict__ rlist, uint32_t *__restrict__ lrow, uint32_t *__restrict__ lvl,
        uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, uint32_t *__restrict__ ovf0,
        uint32_t *__restrict__ ovf1, PeelCtl *__restrict__ ctl) {
-    // the whole grid takes part until few vertices remain; then the first kGridBlocks blocks go on
+    // the whole grid takes part while many vertices remain, then the first kGridMid blocks, then
+    // the first kGridBlocks
     unsigned nblk = gridDim.x;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     uint32_t gsize = nblk * kBlock;
@@ -407,12 +410,15 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         ++lv;
         ++ph;
         // few vertices left: the later levels are latency-bound, and a barrier costs more the
-        // more blocks meet at it, so only the first kGridBlocks blocks go on
-        if (nblk > kGridBlocks && na2 < kWideUntil) {
-            if (blockIdx.x >= kGridBlocks) return;
-            nblk = kGridBlocks;
-            gsize = nblk * kBlock;
-            nwaves = gsize / 64;
+        // more blocks meet at it, so the grid narrows in two steps (only ever narrows)
+        {
+            const unsigned want = na2 >= kWideUntil ? kGridWide : (na2 >= kMidUntil ? kGridMid : kGridBlocks);
+            if (want < nblk) {
+                if (blockIdx.x >= want) return;
+                nblk = want;
+                gsize = nblk * kBlock;
+                nwaves = gsize / 64;
+            }
         }
         // no survivors: every remaining vertex is queued at this level, and removing them can
         // queue nothing more
