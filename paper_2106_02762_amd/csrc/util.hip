@@ -152,7 +152,9 @@ int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::radix_sort_pairs(tmp.ptr, bytes, kin, kout, vin, vout, n, 0u,
                                      (unsigned)end_bit, s));
-    DT_HIP(hipStreamSynchronize(s));
+    // the temporary goes back to the context's cache, whose blocks are reused in stream order on
+    // the context's stream only: another stream must finish with it first
+    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
@@ -166,7 +168,9 @@ int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::radix_sort_pairs(tmp.ptr, bytes, kin, kout, vin, vout, n, 0u,
                                      (unsigned)end_bit, s));
-    DT_HIP(hipStreamSynchronize(s));
+    // the temporary goes back to the context's cache, whose blocks are reused in stream order on
+    // the context's stream only: another stream must finish with it first
+    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
@@ -178,6 +182,7 @@ int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const ui
     DevMem tmp;
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::radix_sort_pairs(tmp.ptr, bytes, kin, kout, vin, vout, n, 0u, (unsigned)end_bit, s));
+    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
@@ -188,7 +193,9 @@ int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n,
     DevMem tmp;
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::exclusive_scan(tmp.ptr, bytes, in, out, 0u, n, rocprim::plus<uint32_t>(), s));
-    DT_HIP(hipStreamSynchronize(s));
+    // the temporary goes back to the context's cache, whose blocks are reused in stream order on
+    // the context's stream only: another stream must finish with it first
+    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
@@ -201,7 +208,9 @@ int exclusive_scan_u64(dt_ctx *ctx, const uint64_t *in, uint64_t *out, size_t n,
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::exclusive_scan(tmp.ptr, bytes, in, out, (uint64_t)0, n,
                                    rocprim::plus<uint64_t>(), s));
-    DT_HIP(hipStreamSynchronize(s));
+    // the temporary goes back to the context's cache, whose blocks are reused in stream order on
+    // the context's stream only: another stream must finish with it first
+    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
