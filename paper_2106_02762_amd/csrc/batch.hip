@@ -56,10 +56,10 @@ k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc.t[j] = c[j];
         } else if (I.kind == 0) {
-            for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri<false>(Q.light, i, Q.eoff, Q.key, Q.q, acc);
+            for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri(Q.light, i, Q.eoff, Q.key, Q.q, acc);
         } else {
             for (uint64_t b = I.b + 64 * wave; b < I.e; b += kBB)
-                medium_lanes<false>(Q.medium, Q.mitems, b + lane, b + lane < I.e, Q.eoff, Q.key, Q.q, acc, lane);
+                medium_lanes(Q.medium, Q.mitems, b + lane, b + lane < I.e, Q.eoff, Q.key, Q.q, acc, lane);
         }
         block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
         __syncthreads();

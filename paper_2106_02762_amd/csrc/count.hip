@@ -55,7 +55,7 @@ k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__
     const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
     uint32_t r = 0;
     for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
-        light_tri<CELLS>(tri, range_at(R, r, i), eoff, key, q, acc);
+        light_tri(tri, range_at(R, r, i), eoff, key, q, acc);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -74,7 +74,7 @@ k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict_
     for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
         const uint64_t j = b + lane;
         const bool active = j < n_ent;
-        medium_lanes<CELLS>(med, ent, active ? range_at(R, r, j) : 0, active, eoff, key, q, acc, lane);
+        medium_lanes(med, ent, active ? range_at(R, r, j) : 0, active, eoff, key, q, acc, lane);
     }
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
@@ -389,14 +389,58 @@ struct SweepQ {
     DQuery q[kSweepMax];
     UQuery u[kSweepMax];
     uint32_t k;
+    int64_t d13max;   // largest d13 of the k triples
 };
 
-// partial slot of block `slot` for query j: part + 8 (K slot + j)
+// adds a sweep's contributions to one triple's eight LDS counters (of this wavefront)
+struct AccSweep {
+    unsigned long long *s;
+    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
+        if (v) atomicAdd(&s[first ? CA::type : CB::type], (unsigned long long)v);
+    }
+    template <class C> __device__ __forceinline__ void add(int64_t v) {
+        if (v) atomicAdd(&s[C::type], (unsigned long long)v);
+    }
+};
+
+// The (uv, uw) pairs of one light triangle's direction lists A, B, each tested against every
+// triple: the enumeration and the keys are shared, the searches that depend on the deltas are not.
+template <int A, int B>
+__device__ __forceinline__ void light_pairs_sweep(const uint64_t *__restrict__ key, const Lists &L, const SweepQ &Q,
+                                                  unsigned long long *sw) {
+    const uint32_t xb = L.lo[A], xe = L.hi[A], yb = L.lo[2 + B], ye = L.hi[2 + B];
+    const int shift = Q.q[0].shift;
+    for (uint32_t ix = xb; ix < xe; ++ix) {
+        const uint64_t kx = key[ix];
+        for (uint32_t iy = yb; iy < ye; ++iy) {
+            const uint64_t ky = key[iy];
+            const bool uv_first = kx < ky;
+            const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
+            const int64_t t_lo = (int64_t)(k_lo >> shift), t_hi = (int64_t)(k_hi >> shift);
+            const int64_t gap = t_hi - t_lo;
+            if (gap > Q.d13max) continue;
+            for (uint32_t j = 0; j < Q.k; ++j) {
+                const DQuery &q = Q.q[j];
+                if (gap > q.d13) continue;
+                AccSweep a{sw + 8 * j};
+                light_third<A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, a);
+                light_third<A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, a);
+            }
+        }
+    }
+}
+
+// a block's sweep counters (per wavefront, [8 j + type]) to its partial slots
 template <unsigned BLOCK>
-__device__ __forceinline__ void sweep_store(const int64_t (&t)[8], int64_t *__restrict__ part, uint64_t slot,
-                                            uint32_t k, uint32_t j) {
-    block_store<BLOCK>(t, part + 8 * (slot * k + j));
-    __syncthreads();   // the next store reuses block_store's LDS
+__device__ __forceinline__ void sweep_flush(unsigned long long (*s_sw)[kSweepMax * 8], uint32_t k,
+                                            int64_t *__restrict__ part, uint64_t slot) {
+    __syncthreads();
+    if (threadIdx.x < 8 * k) {
+        unsigned long long v = 0;
+#pragma unroll
+        for (unsigned w = 0; w < BLOCK / 64; ++w) v += s_sw[w][threadIdx.x];
+        part[8 * (slot * k + threadIdx.x / 8) + threadIdx.x % 8] = (int64_t)v;
+    }
 }
 
 // unit records: each record is read once and tested against every delta triple.  A wavefront
@@ -416,8 +460,11 @@ k_unit_sweep(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, SweepQ Q
     const uint64_t b = beg + (uint64_t)blockIdx.x * per;
     const uint64_t e = b + per < end ? b + per : end;
     uint32_t cnt = 0;
+    // the window is the same for every triple: test it once per record
+    const uint32_t wlo = Q.u[0].wlo, whi = Q.u[0].whi;
     auto test = [&](const uint4 r, bool valid) {
         const uint32_t g13 = r.y + r.z, ty = r.w & 7u;
+        valid = valid && r.x >= wlo && r.x + g13 < whi;
         uint64_t tsel = 0, jsel = 0;
 #pragma unroll
         for (uint32_t t = 0; t < 8; ++t) {
@@ -428,8 +475,7 @@ k_unit_sweep(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, SweepQ Q
         for (uint32_t j = 0; j < kSweepMax; ++j) {
             if (j < Q.k) {
                 const UQuery &u = Q.u[j];
-                const uint64_t m = __ballot(valid && r.y <= u.d12 && r.z <= u.d23 && g13 <= u.d13 &&
-                                            r.x >= u.wlo && r.x + g13 < u.whi);
+                const uint64_t m = __ballot(valid && r.y <= u.d12 && r.z <= u.d23 && g13 <= u.d13);
                 jsel = my_j == j ? m : jsel;
             }
         }
@@ -460,45 +506,64 @@ k_unit_sweep(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, SweepQ Q
     }
 }
 
-// light triangles: the block's triangles once per delta triple, the repeats served from cache
+// light triangles: each lane's triangles once, every pair tested against every triple
 template <unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_light_sweep(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
               const uint64_t *__restrict__ key, SweepQ Q, int64_t *__restrict__ part, uint64_t slot0) {
+    __shared__ unsigned long long s_sw[BLOCK / 64][kSweepMax * 8];
+    for (unsigned x = threadIdx.x; x < (BLOCK / 64) * kSweepMax * 8; x += BLOCK) (&s_sw[0][0])[x] = 0;
+    __syncthreads();
+    unsigned long long *sw = s_sw[threadIdx.x / 64];
     const uint64_t n_tri = R.pre[R.n];
     const uint32_t nblk = gridDim.x;
     const uint32_t b = xcd_block(blockIdx.x, nblk);
     const uint64_t per = (n_tri + nblk - 1) / nblk;
     const uint64_t beg = (uint64_t)b * per;
     const uint64_t end = beg + per < n_tri ? beg + per : n_tri;
-    for (uint32_t j = 0; j < Q.k; ++j) {
-        Acc<false> acc;
-        uint32_t r = 0;
-        for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
-            light_tri<false>(tri, range_at(R, r, i), eoff, key, Q.q[j], acc);
-        sweep_store<BLOCK>(acc.t, part, slot0 + blockIdx.x, Q.k, j);
+    uint32_t r = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK) {
+        const uint64_t t = range_at(R, r, i);
+        Lists L;
+        load_lists(eoff, tri[3 * t], tri[3 * t + 1], tri[3 * t + 2], key, Q.q[0], L);   // one window
+        light_pairs_sweep<0, 0>(key, L, Q, sw);
+        light_pairs_sweep<0, 1>(key, L, Q, sw);
+        light_pairs_sweep<1, 0>(key, L, Q, sw);
+        light_pairs_sweep<1, 1>(key, L, Q, sw);
     }
+    sweep_flush<BLOCK>(s_sw, Q.k, part, slot0 + blockIdx.x);
 }
 
-// medium entries: the block's entries once per delta triple
+// medium entries: each entry's close pairs found once, for the largest d13 of the triples, and
+// every pair tested against every triple
 template <unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_medium_sweep(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
                const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, SweepQ Q,
                int64_t *__restrict__ part, uint64_t slot0) {
+    __shared__ unsigned long long s_sw[BLOCK / 64][kSweepMax * 8];
+    for (unsigned x = threadIdx.x; x < (BLOCK / 64) * kSweepMax * 8; x += BLOCK) (&s_sw[0][0])[x] = 0;
+    __syncthreads();
+    unsigned long long *sw = s_sw[threadIdx.x / 64];
     const unsigned lane = threadIdx.x & 63;
     const uint64_t n_ent = R.pre[R.n];
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
-    for (uint32_t j = 0; j < Q.k; ++j) {
-        Acc<false> acc;
-        uint32_t r = 0;
-        for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
-            const uint64_t x = b + lane;
-            const bool active = x < n_ent;
-            medium_lanes<false>(med, ent, active ? range_at(R, r, x) : 0, active, eoff, key, Q.q[j], acc, lane);
-        }
-        sweep_store<BLOCK>(acc.t, part, slot0 + blockIdx.x, Q.k, j);
+    DQuery qr = Q.q[0];   // the window, and the widest closeness
+    qr.d13 = Q.d13max;
+    uint32_t r = 0;
+    for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
+        const uint64_t x = b + lane;
+        const bool active = x < n_ent;
+        medium_lanes_eval(med, ent, active ? range_at(R, r, x) : 0, active, eoff, key, qr,
+                          [&](int combo, const Lists &L, uint64_t k_uv, uint64_t k_uw) {
+                              for (uint32_t j = 0; j < Q.k; ++j) {
+                                  AccSweep a{sw + 8 * j};
+                                  medium_pair_any(combo, key, L, Q.q[j], k_uv, k_uw, a);
+                              }
+                          },
+                          lane);
     }
+    sweep_flush<BLOCK>(s_sw, Q.k, part, slot0 + blockIdx.x);
 }
 
 // out[8 j + i] (+)= sum over slots of part[8 (K slot + j) + i]; block j for query j
@@ -702,8 +767,9 @@ void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipSt
 }
 
 // A sweep: k <= kSweepMax queries with one window.  The unit, light and medium kernels visit each
-// triangle's data once per pass and count it for every delta triple (records and lists are read
-// from HBM once; the repeats of a block's light and medium triangles hit the caches); the rare heavy
+// triangle's data once per pass and count it for every delta triple: records and lists are read
+// once, the light path enumerates each triangle's pairs once, the medium path finds each entry's
+// close pairs once (for the largest d13); only the delta-dependent searches repeat.  The rare heavy
 // triangles are counted per query first, and the reduction adds the rest to those sums.
 int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_dev, hipStream_t s, Scratch &sc) {
     dt_ctx *ctx = g->ctx;
@@ -711,9 +777,11 @@ int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_
     if (k == 0 || k > kSweepMax) return fail(DT_EINVAL, "a sweep pass takes 1..%u queries", kSweepMax);
     SweepQ Q{};
     Q.k = k;
+    Q.d13max = 0;
     for (uint32_t j = 0; j < k; ++j) {
         Q.q[j] = qs[j];
         Q.u[j] = unit_query(qs[j]);
+        Q.d13max = qs[j].d13 > Q.d13max ? qs[j].d13 : Q.d13max;
     }
     const DQuery &q0 = qs[0];   // the window (and so every range) is the same for all k
     // heavy triangles: one count per query, written to out_dev

@@ -121,11 +121,11 @@ __device__ __forceinline__ void load_lists(const uint32_t *__restrict__ eoff, ui
 // ---------------------------------------------------------------------------------------------
 // light path: one lane per triangle, every (uv edge, uw edge) pair
 // ---------------------------------------------------------------------------------------------
-template <bool CELLS, int A, int B, int C>
+template <int A, int B, int C, class ACC>
 __device__ __forceinline__ void light_third(const uint64_t *__restrict__ key, const Lists &L,
                                             const DQuery &q, bool uv_first, uint64_t k_lo,
                                             uint64_t k_hi, int64_t t_lo, int64_t t_hi, int64_t gap,
-                                            Acc<CELLS> &acc) {
+                                            ACC &acc) {
     const uint32_t zb = L.lo[4 + C], ze = L.hi[4 + C];
     if (zb == ze) return;
     const uint32_t below_lo = lower(key, zb, ze, k_lo);   // z with key < k_lo
@@ -150,9 +150,9 @@ __device__ __forceinline__ void light_third(const uint64_t *__restrict__ key, co
     }
 }
 
-template <bool CELLS, int A, int B>
+template <int A, int B, class ACC>
 __device__ __forceinline__ void light_pairs(const uint64_t *__restrict__ key, const Lists &L,
-                                            const DQuery &q, Acc<CELLS> &acc) {
+                                            const DQuery &q, ACC &acc) {
     const uint32_t xb = L.lo[A], xe = L.hi[A], yb = L.lo[2 + B], ye = L.hi[2 + B];
     for (uint32_t ix = xb; ix < xe; ++ix) {
         const uint64_t kx = key[ix];
@@ -163,39 +163,39 @@ __device__ __forceinline__ void light_pairs(const uint64_t *__restrict__ key, co
             const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
             const int64_t gap = t_hi - t_lo;
             if (gap > q.d13) continue;   // d12, d23 <= d13: no z completes this pair
-            light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-            light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+            light_third<A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+            light_third<A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
         }
     }
 }
 
 // one light triangle: every (uv edge, uw edge) pair by one lane
-template <bool CELLS>
+template <class ACC>
 __device__ __forceinline__ void light_tri(const uint32_t *__restrict__ tri, uint64_t i,
                                           const uint32_t *__restrict__ eoff,
                                           const uint64_t *__restrict__ key, const DQuery &q,
-                                          Acc<CELLS> &acc) {
+                                          ACC &acc) {
     Lists L;
     load_lists(eoff, tri[3 * i], tri[3 * i + 1], tri[3 * i + 2], key, q, L);
-    light_pairs<CELLS, 0, 0>(key, L, q, acc);
-    light_pairs<CELLS, 0, 1>(key, L, q, acc);
-    light_pairs<CELLS, 1, 0>(key, L, q, acc);
-    light_pairs<CELLS, 1, 1>(key, L, q, acc);
+    light_pairs<0, 0>(key, L, q, acc);
+    light_pairs<0, 1>(key, L, q, acc);
+    light_pairs<1, 0>(key, L, q, acc);
+    light_pairs<1, 1>(key, L, q, acc);
 }
 
 // ---------------------------------------------------------------------------------------------
 // medium path: one lane per edge of a triangle's smaller source-incident pair
 // ---------------------------------------------------------------------------------------------
-template <bool CELLS, int A, int B>
+template <int A, int B, class ACC>
 __device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, const Lists &L,
-                                            const DQuery &q, uint64_t kx, uint64_t ky, Acc<CELLS> &acc) {
+                                            const DQuery &q, uint64_t kx, uint64_t ky, ACC &acc) {
     const bool uv_first = kx < ky;
     const uint64_t k_lo = uv_first ? kx : ky, k_hi = uv_first ? ky : kx;
     const int64_t t_lo = (int64_t)(k_lo >> q.shift), t_hi = (int64_t)(k_hi >> q.shift);
     const int64_t gap = t_hi - t_lo;
     if (gap > q.d13) return;
-    light_third<CELLS, A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
-    light_third<CELLS, A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+    light_third<A, B, 0>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
+    light_third<A, B, 1>(key, L, q, uv_first, k_lo, k_hi, t_lo, t_hi, gap, acc);
 }
 
 // the outer pair of a medium triangle: the source-incident pair with fewer temporal edges
@@ -226,11 +226,13 @@ __device__ __forceinline__ void lower2(const uint64_t *__restrict__ key, uint32_
 // search.  The wavefront then spreads the (x, y) pairs of all its lanes evenly over the lanes
 // (pair j belongs to the last lane whose exclusive prefix of pair counts is <= j), so one outer edge
 // with many close partners does not stall the others.  Every lane of the wavefront must call this.
-template <bool CELLS>
-__device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
-                                             uint64_t e, bool active, const uint32_t *__restrict__ eoff,
-                                             const uint64_t *__restrict__ key, const DQuery &q,
-                                             Acc<CELLS> &acc, unsigned lane) {
+// Each pair goes to eval(direction combination 2 d_uv + d_uw, its {v,w} lists, uv key, uw key);
+// q gives the window and the d13 of the closeness test.
+template <class EVAL>
+__device__ __forceinline__ void medium_lanes_eval(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+                                                  uint64_t e, bool active, const uint32_t *__restrict__ eoff,
+                                                  const uint64_t *__restrict__ key, const DQuery &q, EVAL &&eval,
+                                                  unsigned lane) {
     uint64_t kx = 0;
     uint32_t lo0 = 0, c0 = 0, lo1 = 0, c1 = 0, zb0 = 0, ze0 = 0, zb1 = 0, ze1 = 0, flags = 0;
     if (active) {
@@ -301,13 +303,33 @@ __device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, c
         // (uv edge, uw edge) with their directions
         const uint64_t k_uv = outer_uv ? okx : ky, k_uw = outer_uv ? ky : okx;
         const uint32_t d_uv = outer_uv ? x_dir : y_dir, d_uw = outer_uv ? y_dir : x_dir;
-        switch (d_uv * 2 + d_uw) {
-            case 0: medium_pair<CELLS, 0, 0>(key, L, q, k_uv, k_uw, acc); break;
-            case 1: medium_pair<CELLS, 0, 1>(key, L, q, k_uv, k_uw, acc); break;
-            case 2: medium_pair<CELLS, 1, 0>(key, L, q, k_uv, k_uw, acc); break;
-            default: medium_pair<CELLS, 1, 1>(key, L, q, k_uv, k_uw, acc); break;
-        }
+        eval(d_uv * 2 + d_uw, L, k_uv, k_uw);
     }
+}
+
+// one (uv, uw) pair of given direction combination for query q
+template <class ACC>
+__device__ __forceinline__ void medium_pair_any(int combo, const uint64_t *__restrict__ key, const Lists &L,
+                                                const DQuery &q, uint64_t k_uv, uint64_t k_uw, ACC &acc) {
+    switch (combo) {
+        case 0: medium_pair<0, 0>(key, L, q, k_uv, k_uw, acc); break;
+        case 1: medium_pair<0, 1>(key, L, q, k_uv, k_uw, acc); break;
+        case 2: medium_pair<1, 0>(key, L, q, k_uv, k_uw, acc); break;
+        default: medium_pair<1, 1>(key, L, q, k_uv, k_uw, acc); break;
+    }
+}
+
+// the medium path for one query into accumulator acc
+template <class ACC>
+__device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+                                             uint64_t e, bool active, const uint32_t *__restrict__ eoff,
+                                             const uint64_t *__restrict__ key, const DQuery &q, ACC &acc,
+                                             unsigned lane) {
+    medium_lanes_eval(med, ent, e, active, eoff, key, q,
+                      [&](int combo, const Lists &L, uint64_t k_uv, uint64_t k_uw) {
+                          medium_pair_any(combo, key, L, q, k_uv, k_uw, acc);
+                      },
+                      lane);
 }
 
 // light triangles: P <= light_pair_cap and at most kLightVw edges on {v,w}

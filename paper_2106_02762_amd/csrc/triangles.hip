@@ -116,10 +116,10 @@ struct TriSink {
             cdev::Acc<false> A;
             cdev::Lists L;
             cdev::load_lists(eoff, a, b, c, F.key, F.q, L);
-            cdev::light_pairs<false, 0, 0>(F.key, L, F.q, A);
-            cdev::light_pairs<false, 0, 1>(F.key, L, F.q, A);
-            cdev::light_pairs<false, 1, 0>(F.key, L, F.q, A);
-            cdev::light_pairs<false, 1, 1>(F.key, L, F.q, A);
+            cdev::light_pairs<0, 0>(F.key, L, F.q, A);
+            cdev::light_pairs<0, 1>(F.key, L, F.q, A);
+            cdev::light_pairs<1, 0>(F.key, L, F.q, A);
+            cdev::light_pairs<1, 1>(F.key, L, F.q, A);
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc[j] += A.t[j];
         } else {
