@@ -11,17 +11,18 @@
 // orders give different orientations but the same counts: each static triangle is counted once
 // under its own naming u < v < w.)
 //
-// The whole peel is one cooperative (co-resident) grid of a few blocks: levels and rounds are
-// separated by grid barriers instead of kernel launches and host round trips, since power-law
-// graphs need thousands of removal steps, most with frontiers of a few vertices.  Within a level,
-// a block removes the vertices its own removals queued right away (a cascade local to the block,
-// with workgroup barriers only), so a grid round usually ends a level; only vertices queued past a
-// full staging list wait for another round.  A barrier's cost grows
-// with the number of blocks that meet at it, so the grid is small and wide (32 blocks of 1024
-// threads), and the barrier is a monotonic arrival counter that every block polls.  Counters that
-// decide the next step (queue positions taken in a phase, survivors of a level scan) rotate over
-// three slots, so a fast block starting the next phase never changes what a slow block reads, and
-// every block takes the same branch.  A vertex is queued at most
+// The whole peel is one cooperative (co-resident) grid: levels and rounds are separated by grid
+// barriers instead of kernel launches and host round trips, since power-law graphs need thousands
+// of removal steps, most with frontiers of a few vertices.  Within a level, a block removes the
+// vertices its own removals queued right away (a cascade local to the block, with workgroup
+// barriers only), so a grid round usually ends a level; only vertices queued past a full staging
+// list wait for another round.  The first levels remove most of the graph and are bound by work,
+// the later ones by latency, and a barrier's cost grows with the number of blocks that meet at it:
+// the grid starts with one block of 1024 threads per CU and narrows to 64, then 32 blocks as
+// vertices run out.  The barrier is a monotonic arrival counter that every block polls.  Counters
+// that decide the next step (queue positions taken in a phase, survivors of a level scan) rotate
+// over three slots, so a fast block starting the next phase never changes what a slow block reads,
+// and every block takes the same branch.  A vertex is queued at most
 // once: by the level scan when its degree is <= k (no decrement runs during a scan), or by the
 // single decrement that takes its degree from k + 1 to k (degrees only fall, and a queued vertex
 // already has degree <= k, so no later decrement can see k + 1 again); a vertex queued by a
