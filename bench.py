@@ -33,10 +33,10 @@ def log(*a):
 
 # source file of each event-timed kernel (the HBM traffic measured for a kernel is reported only
 # while its source is unchanged since the counters were taken)
-KERNEL_SOURCE = {"peel": "peel.hip", "relayout": "orient.hip", "tri_count": "triangles.hip",
-                 "tri_fill": "triangles.hip", "light": "count.hip", "medium": "count.hip",
-                 "unit": "count.hip", "heavy_prefix": "count.hip", "heavy_count": "count.hip",
-                 "reduce": "count.hip"}
+KERNEL_SOURCE = {"peel": "peel.hip", "peel_adj": "peel.hip", "peel_tail": "peel.hip",
+                 "relayout": "orient.hip", "tri_count": "triangles.hip", "tri_fill": "triangles.hip",
+                 "light": "count.hip", "medium": "count.hip", "unit": "count.hip",
+                 "heavy_prefix": "count.hip", "heavy_count": "count.hip", "reduce": "count.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_full_graph.md")
 
 
@@ -47,12 +47,18 @@ def measured_traffic(kernel):
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    fields = {}
+    # records of "- key: `value`" lines, each starting with its "- kernel:" line
+    records, fields = {}, None
     for line in open(TRAFFIC_FILE):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
-            fields[k.strip()] = v.strip().strip("`")
-    if fields.get("kernel") != kernel or kernel not in KERNEL_SOURCE:
+            k, v = k.strip(), v.strip().strip("`")
+            if k == "kernel":
+                fields = records.setdefault(v, {})
+            if fields is not None:
+                fields[k] = v
+    fields = records.get(kernel, {})
+    if not fields or kernel not in KERNEL_SOURCE:
         return None
     src = os.path.join(ROOT, "paper_2106_02762_amd", "csrc", KERNEL_SOURCE[kernel])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
@@ -302,6 +308,8 @@ def main():
     heavy_bytes = st["alg_bytes"] - st["alg_bytes_light"] - st["alg_bytes_medium"] - st["alg_bytes_unit"]
     alg = {
         "peel": st["alg_bytes_peel"],
+        "peel_adj": 0,
+        "peel_tail": 0,
         "relayout": 25 * st["m_loaded"],
         "tri_count": 4 * (st["m_static"] + st["tri_candidates"]),
         "tri_fill": 4 * (st["m_static"] + st["tri_candidates"]) + 12 * st["n_static_triangles"],

@@ -195,11 +195,12 @@ int dt_graph_free(dt_graph *g);
 
 /* Diagnostics: when profiling is on, the library records HIP events on the stream each kernel is
  * launched on, around the main kernels of the last build and the last count of the context:
- *   ms[0] core peel, ms[1] store re-layout, ms[2] triangle count pass, ms[3] triangle fill pass,
- *   ms[4] light count, ms[5] heavy prefix pass, ms[6] heavy count pass, ms[7] final reduction,
- *   ms[8] medium count, ms[9] unit-triangle count.
+ *   ms[0] core peel on the cooperative grid, ms[1] store re-layout, ms[2] triangle count pass,
+ *   ms[3] triangle fill pass, ms[4] light count, ms[5] heavy prefix pass, ms[6] heavy count pass,
+ *   ms[7] final reduction, ms[8] medium count, ms[9] unit-triangle count, ms[10] the peel's
+ *   local adjacency of its last vertices, ms[11] the peel's one-workgroup finish.
  * dt_ctx_last_profile waits for those events and reports their elapsed times (0 if not run). */
-#define DT_PROFILE_SLOTS 10
+#define DT_PROFILE_SLOTS 12
 int dt_ctx_set_profiling(dt_ctx *ctx, int enable);
 int dt_ctx_last_profile(dt_ctx *ctx, float ms[DT_PROFILE_SLOTS]);
 

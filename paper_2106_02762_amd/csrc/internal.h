@@ -106,7 +106,8 @@ void pool_trim(dt_ctx *ctx, uint64_t keep_bytes);   // free cached blocks down t
 
 // profiling marks around one kernel launch (no-ops unless profiling is on)
 enum ProfSlot { kProfPeel = 0, kProfRelayout, kProfTriCount, kProfTriFill, kProfLight,
-                kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium, kProfUnit };
+                kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium, kProfUnit, kProfPeelAdj,
+                kProfPeelTail };
 inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
     if (c->prof) { (void)hipEventRecord(c->prof_ev[2 * slot], s); c->prof_used[slot] = true; }
 }

@@ -67,6 +67,8 @@ struct PeelCtl {
     unsigned int kappa;      // largest level that removed a vertex
     unsigned int nlvl;       // levels recorded by the one-workgroup finish
     unsigned long long lres; // hand-over: local ids (low word) and adjacency entries (high word) given out
+    unsigned int ho;         // 1: the grid handed its last vertices over (the state below is set)
+    unsigned int ho_tail, ho_k, ho_rounds;   // queue positions taken, level and rounds at the hand-over
     unsigned int scan[3][2]; // per level mod 3: survivors of the level scan, their smallest degree
 };
 
@@ -593,10 +595,30 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         if (gtid == 0) atomicOr(&ctl->error, 4u);
         return;
     }
-    if (gtid == 0) lrow[R] = total;
-    for (uint32_t l = gwave; l < R; l += nwaves) {
+    if (gtid == 0) {
+        lrow[R] = total;
+        ctl->ho_tail = tail;
+        ctl->ho_k = k;
+        ctl->ho_rounds = rounds;
+        ctl->ho = 1;
+    }
+}
+
+// The hand-over's local adjacency: for every local vertex, its remaining neighbours' local ids,
+// found by a scan of its whole row with one wavefront.  A launch of its own on the whole device
+// (the grid has narrowed by then, and the rows of the last vertices, hubs, are long).
+__global__ void __launch_bounds__(256)
+k_local_adj(const uint32_t *__restrict__ row, const uint32_t *__restrict__ col, const int *__restrict__ deg,
+            const uint32_t *__restrict__ loc, const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lrow,
+            uint16_t *__restrict__ lcol, PeelCtl *__restrict__ ctl) {
+    if (!ctl->ho || ctl->error) return;
+    const uint32_t R = (uint32_t)ctl->lres;
+    const unsigned lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
+    const uint32_t nwaves = gridDim.x * (256 / 64);
+    for (uint32_t l = blockIdx.x * (256 / 64) + threadIdx.x / 64; l < R; l += nwaves) {
         const uint32_t v = rlist[l], b = lrow[l];
-        const uint32_t d = (uint32_t)ld_relaxed(&deg[v]);
+        const uint32_t d = (uint32_t)deg[v];
         const uint32_t e = row[v + 1];
         uint32_t c = 0;
         for (uint32_t j0 = row[v]; j0 < e; j0 += 64) {
@@ -609,9 +631,17 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         }
         if (lane == 0 && c != d) atomicOr(&ctl->error, 4u);
     }
-    grid_barrier(ctl, btarget += nblk);
-    if (blockIdx.x != 0 || ld_relaxed(&ctl->error)) return;
-    peel_tail(R, tail, k, rounds, rlist, lrow, lcol, lvl, level, queue, ctl, s_mem);
+}
+
+// the one-workgroup finish after a hand-over
+__global__ void __launch_bounds__(kBlock)
+k_peel_finish(const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lrow, const uint16_t *__restrict__ lcol,
+              uint32_t *__restrict__ lvl, uint32_t *__restrict__ level, uint32_t *__restrict__ queue,
+              PeelCtl *__restrict__ ctl) {
+    __shared__ __attribute__((aligned(16))) uint32_t s_mem[kLdsWords];
+    if (!ctl->ho || ctl->error) return;
+    peel_tail((uint32_t)ctl->lres, ctl->ho_tail, ctl->ho_k, ctl->ho_rounds, rlist, lrow, lcol, lvl, level, queue, ctl,
+              s_mem);
 }
 
 __global__ void k_finish(uint32_t n, const uint32_t *__restrict__ queue, uint32_t *__restrict__ rank) {
@@ -674,6 +704,14 @@ int peel(dt_graph *g) {
     prof_begin(ctx, kProfPeel, st);
     DT_HIP(hipLaunchCooperativeKernel((const void *)k_peel, dim3(grid), dim3(kBlock), args, 0, st));
     prof_end(ctx, kProfPeel, st);
+    prof_begin(ctx, kProfPeelAdj, st);
+    k_local_adj<<<(unsigned)ctx->num_cus * 8, 256, 0, st>>>(row, col, degp, locp, rl, lb, lc, ctl);
+    prof_end(ctx, kProfPeelAdj, st);
+    DT_HIP(hipGetLastError());
+    prof_begin(ctx, kProfPeelTail, st);
+    k_peel_finish<<<1, kBlock, 0, st>>>(rl, lb, lc, ld, level, queue, ctl);
+    prof_end(ctx, kProfPeelTail, st);
+    DT_HIP(hipGetLastError());
     PeelCtl h{};
     DT_HIP(hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));

@@ -36,7 +36,7 @@ ENTRY_POINTS = (
     "dt_ctx_set_profiling", "dt_ctx_last_profile",
 )
 PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
-                 "heavy_count", "reduce", "medium", "unit")
+                 "heavy_count", "reduce", "medium", "unit", "peel_adj", "peel_tail")
 
 
 class DtError(RuntimeError):
