@@ -170,15 +170,16 @@ __global__ void __launch_bounds__(kBlock)
 k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
       uint32_t *__restrict__ tri, uint64_t cap, unsigned long long *__restrict__ total,
       unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa) {
+    // per wavefront: N+(u), the run starts and (16-bit) lengths of each N+(v), and one slice that
+    // holds the prefix of walk lengths during the flattened walks and then a staged N+(v) copy
     __shared__ uint32_t s_nbr[kWaves][kCap];
     __shared__ uint32_t s_pre[kWaves][kCap + 1];
     __shared__ uint32_t s_vb[kWaves][kCap];
-    __shared__ uint32_t s_dv[kWaves][kCap];
-    __shared__ uint32_t s_vn[kWaves][kCap];
+    __shared__ uint16_t s_dv[kWaves][kCap];
     __shared__ uint32_t s_out[kWaves][3 * kOut];
     const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-    uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *vb_lds = s_vb[wave], *dv_lds = s_dv[wave],
-             *vn_lds = s_vn[wave];
+    uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *vb_lds = s_vb[wave], *vn_lds = s_pre[wave];
+    uint16_t *dv_lds = s_dv[wave];
     TriSink<FUSED> out{s_out[wave], 0, tri, cap, total, &fa};
     unsigned long long wave_cand = 0;   // candidates tested, added once per wave
     for (;;) {
@@ -222,7 +223,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 if (in_lds) {
                     nbr_lds[i] = v;
                     vb_lds[i] = vb;
-                    dv_lds[i] = outv;
+                    dv_lds[i] = (uint16_t)(outv < 0xffffu ? outv : 0xffffu);
                 }
                 const bool staged = outv > after && after >= kStage && outv <= kCap;
                 dv = in_lds ? (staged ? 0 : (outv < after ? outv : after)) : (i + 1 < du ? outv : 0);
@@ -249,7 +250,8 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 if (p < work) {
                     i = owner(pre_lds, du, p);
                     const uint32_t j = p - pre_lds[i];
-                    const uint32_t vb = vb_lds[i], outv = dv_lds[i];
+                    const uint32_t vb = vb_lds[i];
+                    const uint32_t outv = dv_lds[i] != 0xffffu ? dv_lds[i] : dag_row[nbr_lds[i] + 1] - vb;
                     if (outv <= du - i - 1) {
                         // walk N+(v), search N+(u) after v in LDS
                         const uint32_t w = dag_col[vb + j];
@@ -270,7 +272,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
             }
             // long walks into a long N+(v): copy N+(v) into LDS, then search it there
             for (uint32_t i = part; i + kStage < du; i += parts) {
-                const uint32_t after = du - i - 1, outv = dv_lds[i];
+                const uint32_t after = du - i - 1, outv = dv_lds[i];   // 0xffff: longer than any stage
                 if (!(outv > after && after >= kStage && outv <= kCap)) continue;
                 const uint32_t vb = vb_lds[i];
                 wave_cand += after;
