@@ -166,7 +166,7 @@ struct TriSink {
 };
 
 template <bool FUSED>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 4)   // four wavefronts per SIMD (the LDS allows four blocks per CU)
 k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
       uint32_t *__restrict__ tri, uint64_t cap, unsigned long long *__restrict__ total,
       unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa) {
