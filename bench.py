@@ -33,7 +33,7 @@ def log(*a):
 
 # source file of each event-timed kernel (the HBM traffic measured for a kernel is reported only
 # while its source is unchanged since the counters were taken)
-KERNEL_SOURCE = {"peel": "peel.hip", "peel_adj": "peel.hip", "peel_tail": "peel.hip",
+KERNEL_SOURCE = {"peel": "peel.hip", "peel_adj": "peel.hip", "peel_tail": "peel.hip", "core": "core.hip",
                  "relayout": "orient.hip", "tri_count": "triangles.hip", "tri_fill": "triangles.hip",
                  "light": "count.hip", "medium": "count.hip", "unit": "count.hip",
                  "heavy_prefix": "count.hip", "heavy_count": "count.hip", "reduce": "count.hip"}
@@ -310,6 +310,7 @@ def main():
         "peel": st["alg_bytes_peel"],
         "peel_adj": 0,
         "peel_tail": 0,
+        "core": st["alg_bytes_peel"],
         "relayout": 25 * st["m_loaded"],
         "tri_count": 4 * (st["m_static"] + st["tri_candidates"]),
         "tri_fill": 4 * (st["m_static"] + st["tri_candidates"]) + 12 * st["n_static_triangles"],

@@ -109,9 +109,14 @@ typedef struct {
     uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;
                                       2: every triangle heavy; 3: every triangle medium
                                       (diagnostics and tests)                                     */
-    uint32_t peel_tail;            /* the core peel hands the last peel_tail vertices to one
+    uint32_t peel_tail;            /* the level peel hands the last peel_tail vertices to one
                                       workgroup (default and at most 16384; 1 keeps every level
                                       on the whole grid); read by the next dt_graph_build        */
+    uint32_t order_method;         /* 0: the level-by-level core peel (default); 1: core numbers
+                                      by h-index iteration, then every shell peeled at once.
+                                      Both give the exact core numbers and an ordering with at
+                                      most core(v) neighbours after each v; read by the next
+                                      build or one-shot count                                    */
 } dt_tuning;
 
 const char *dt_strerror(int code);
@@ -198,9 +203,10 @@ int dt_graph_free(dt_graph *g);
  *   ms[0] core peel on the cooperative grid, ms[1] store re-layout, ms[2] triangle count pass,
  *   ms[3] triangle fill pass, ms[4] light count, ms[5] heavy prefix pass, ms[6] heavy count pass,
  *   ms[7] final reduction, ms[8] medium count, ms[9] unit-triangle count, ms[10] the peel's
- *   local adjacency of its last vertices, ms[11] the peel's one-workgroup finish.
+ *   local adjacency of its last vertices, ms[11] the peel's one-workgroup finish, ms[12] core
+ *   numbers and shell rounds (order_method 1; ms[0], ms[10] and ms[11] belong to method 0).
  * dt_ctx_last_profile waits for those events and reports their elapsed times (0 if not run). */
-#define DT_PROFILE_SLOTS 12
+#define DT_PROFILE_SLOTS 13
 int dt_ctx_set_profiling(dt_ctx *ctx, int enable);
 int dt_ctx_last_profile(dt_ctx *ctx, float ms[DT_PROFILE_SLOTS]);
 

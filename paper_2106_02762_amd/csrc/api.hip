@@ -217,7 +217,7 @@ int dt_graph_build(dt_graph *g) {
     DeviceGuard dg(g->ctx->device);
     g->built = false;
     double t0 = now_ms();
-    DT_TRY(peel(g));
+    DT_TRY(order_vertices(g));
     double t1 = now_ms();
     DT_TRY(orient(g));
     double t2 = now_ms();
@@ -250,6 +250,8 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     nt.force_path = tu->force_path;
     if (tu->peel_tail > 16384) return fail(DT_EINVAL, "peel_tail must be at most 16384");
     if (tu->peel_tail) nt.peel_tail = tu->peel_tail;
+    if (tu->order_method > 1) return fail(DT_EINVAL, "order_method must be 0 or 1");
+    nt.order_method = tu->order_method;
     if (nt.heavy_chunk != 256) return fail(DT_EINVAL, "heavy_chunk must be 256 in this version");
     if (nt.medium_pair_cap > (1u << 30)) return fail(DT_EINVAL, "medium_pair_cap must be at most 2^30");
     g->tuning = nt;
@@ -348,7 +350,7 @@ int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]) {
     g->sched = Schedule();
     g->n_tri = 0;
     double t0 = now_ms();
-    DT_TRY(peel(g));
+    DT_TRY(order_vertices(g));
     double t1 = now_ms();
     DT_TRY(orient(g));
     double t2 = now_ms();

@@ -107,7 +107,7 @@ void pool_trim(dt_ctx *ctx, uint64_t keep_bytes);   // free cached blocks down t
 // profiling marks around one kernel launch (no-ops unless profiling is on)
 enum ProfSlot { kProfPeel = 0, kProfRelayout, kProfTriCount, kProfTriFill, kProfLight,
                 kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium, kProfUnit, kProfPeelAdj,
-                kProfPeelTail };
+                kProfPeelTail, kProfCore };
 inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
     if (c->prof) { (void)hipEventRecord(c->prof_ev[2 * slot], s); c->prof_used[slot] = true; }
 }
@@ -212,7 +212,7 @@ struct dt_graph {
     uint64_t alg_bytes_unit = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{4, 256, 1u << 27, 0, 0};
+    dt_tuning tuning{4, 256, 1u << 27, 0, 0, 0};
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 
@@ -220,7 +220,9 @@ namespace dt {
 
 // build phases (each returns a DT_* code)
 int load_graph(dt_graph *g, const uint32_t *src_dev, const uint32_t *dst_dev, const int64_t *t_dev);
-int peel(dt_graph *g);
+int peel(dt_graph *g);         // level-by-level core peel (order_method 0)
+int core_order(dt_graph *g);   // h-index core numbers, then shell rounds (order_method 1)
+int order_vertices(dt_graph *g);   // the ordering by the graph's order_method
 int orient(dt_graph *g);
 // every static triangle as (e_uv, e_uw, e_vw) DAG edge ids; *ntri and *cand (candidates tested)
 int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand);

@@ -36,7 +36,7 @@ ENTRY_POINTS = (
     "dt_ctx_set_profiling", "dt_ctx_last_profile",
 )
 PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
-                 "heavy_count", "reduce", "medium", "unit", "peel_adj", "peel_tail")
+                 "heavy_count", "reduce", "medium", "unit", "peel_adj", "peel_tail", "core")
 
 
 class DtError(RuntimeError):
@@ -73,7 +73,7 @@ class dt_stats(ctypes.Structure):
 class dt_tuning(ctypes.Structure):
     _fields_ = [("light_pair_cap", ctypes.c_uint32), ("heavy_chunk", ctypes.c_uint32),
                 ("medium_pair_cap", ctypes.c_uint32), ("force_path", ctypes.c_uint32),
-                ("peel_tail", ctypes.c_uint32)]
+                ("peel_tail", ctypes.c_uint32), ("order_method", ctypes.c_uint32)]
 
 
 class dt_server_cfg(ctypes.Structure):
@@ -207,11 +207,12 @@ def dt_graph_build(g):
 
 
 def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0,
-                        peel_tail=0):
+                        peel_tail=0, order_method=0):
     """force_path: 0 unit records and the caps, 1 all light, 2 all heavy, 3 all medium.
-    peel_tail: vertices the core peel leaves to one workgroup (next build; 0 keeps the setting)."""
+    peel_tail: vertices the level peel leaves to one workgroup (next build; 0 keeps the setting).
+    order_method: 0 the level-by-level peel, 1 h-index core numbers and shell rounds."""
     tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path),
-                   int(peel_tail))
+                   int(peel_tail), int(order_method))
     _check(library().dt_graph_set_tuning(g, ctypes.byref(tu)), "dt_graph_set_tuning")
 
 
