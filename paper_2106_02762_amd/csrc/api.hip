@@ -137,6 +137,7 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_relay[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -145,6 +146,7 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
         for (int i = 0; i < 2; ++i) {
             if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
             if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+            if (c->ev_relay[i]) (void)hipEventDestroy(c->ev_relay[i]);
         }
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -182,6 +184,7 @@ int dt_ctx_destroy(dt_ctx *ctx) {
         if (ctx->side[i]) (void)hipStreamSynchronize(ctx->side[i]);
         if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
         if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
+        if (ctx->ev_relay[i]) (void)hipEventDestroy(ctx->ev_relay[i]);
     }
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_a);
@@ -219,11 +222,19 @@ int dt_graph_build(dt_graph *g) {
     double t0 = now_ms();
     DT_TRY(order_vertices(g));
     double t1 = now_ms();
-    DT_TRY(orient(g));
+    DT_TRY(orient(g, true));
     double t2 = now_ms();
     DevMem tri;
     uint64_t ntri = 0, cand = 0;
-    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    {
+        // the store's re-layout runs beside the enumeration, which does not read it
+        struct Join {
+            dt_graph *g;
+            ~Join() { (void)relayout_join(g); }
+        } join{g};
+        DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+        DT_TRY(relayout_join(g));
+    }
     g->n_tri = ntri;
     g->tri_candidates = cand;
     g->alg_bytes_tri = 4 * (g->m_s + cand) + 12 * ntri;

@@ -88,6 +88,8 @@ struct dt_ctx {
     // a count's light and medium kernels run on these, forked from and joined to the count's stream
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    // a build's re-layout of the temporal store runs on side[0] next to the enumeration: fork, done
+    hipEvent_t ev_relay[2] = {nullptr, nullptr};
     // optional per-kernel timing (dt_ctx_set_profiling)
     bool prof = false;
     hipEvent_t prof_ev[2 * DT_PROFILE_SLOTS] = {};
@@ -206,6 +208,8 @@ struct dt_graph {
     dt::DevMem eoff;            // uint32[2 m_s + 1]: DAG edge d: tail->head edges [eoff[2d], eoff[2d+1]),
                                 //                    head->tail edges [eoff[2d+1], eoff[2d+2])
     dt::DevMem key;             // uint64[m]: keys in that layout
+    bool relay_pending = false; // key is still being written on the context's side[0] stream
+    dt::DevMem relay_tmp[2];    // inputs of that re-layout, held until it is joined
     uint64_t n_tri = 0;
     unsigned __int128 sum_sigma3 = 0;
     uint64_t alg_bytes = 0, alg_bytes_light = 0, alg_bytes_medium = 0, alg_bytes_peel = 0, alg_bytes_tri = 0;
@@ -223,10 +227,13 @@ int load_graph(dt_graph *g, const uint32_t *src_dev, const uint32_t *dst_dev, co
 int peel(dt_graph *g);         // level-by-level core peel (order_method 0)
 int core_order(dt_graph *g);   // h-index core numbers, then shell rounds (order_method 1)
 int order_vertices(dt_graph *g);   // the ordering by the graph's order_method
-int orient(dt_graph *g);
+int orient(dt_graph *g, bool overlap = false);   // overlap: re-layout on side[0], see relayout_join
 // every static triangle as (e_uv, e_uw, e_vw) DAG edge ids; *ntri and *cand (candidates tested)
 int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand);
 int make_schedule(dt_graph *g, DevMem &tri);
+// orders the context's stream after a re-layout that orient(g, true) left running on side[0]
+// (no-op otherwise) and releases its temporaries; to be called before anything reads g->key
+int relayout_join(dt_graph *g);
 // One-shot pass: enumerate the triangles of the oriented graph and count the unit and light ones
 // for query q as they are found (sum to out8_dev); the others go to `rest` (*n_rest triangles,
 // three DAG edge ids each).  *ntri: all static triangles; *cand: candidates tested.

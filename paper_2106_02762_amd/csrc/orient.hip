@@ -7,7 +7,9 @@
 // each run (at most the degeneracy long) is sorted by one wavefront.  DAG edges are numbered in
 // (tail, head) order, and the
 // temporal edges of DAG edge d are stored at [eoff[2d], eoff[2d+2]): first those directed
-// tail -> head, then head -> tail, each in key order (a scatter by rank, no re-sort).  All edges at one source vertex u are then
+// tail -> head, then head -> tail, each in key order (a scatter by rank, no re-sort).  The
+// enumeration of triangles reads only the offsets, so a build moves the keys on a side stream
+// while it runs.  All edges at one source vertex u are then
 // one contiguous stretch of the store, which is exactly what the counting of all triangles with
 // source u walks (Section 5: only {u,v} and {u,w} are enumerated).
 #include "internal.h"
@@ -226,7 +228,19 @@ __global__ void k_relayout(uint64_t m, const uint32_t *__restrict__ psid, const 
 
 }  // namespace
 
-int orient(dt_graph *g) {
+int relayout_join(dt_graph *g) {
+    if (!g->relay_pending) return DT_OK;
+    g->relay_pending = false;
+    const hipError_t e = hipStreamWaitEvent(g->ctx->stream, g->ctx->ev_relay[1], 0);
+    // released in stream order on the context's stream, now behind the re-layout
+    g->relay_tmp[0].reset();
+    g->relay_tmp[1].reset();
+    if (e != hipSuccess) return fail(DT_EDEVICE, "hipStreamWaitEvent failed: %s", hipGetErrorString(e));
+    return DT_OK;
+}
+
+int orient(dt_graph *g, bool overlap) {
+    DT_TRY(relayout_join(g));   // (a build joins its own re-layout before returning)
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint64_t ms = g->m_s, m = g->m;
@@ -278,12 +292,25 @@ int orient(dt_graph *g) {
     }
     DT_TRY(exclusive_scan_u32(ctx, gsize.as<uint32_t>(), g->eoff.as<uint32_t>(), ngroups + 1, st));
     if (m) {
-        prof_begin(ctx, kProfRelayout, st);
-        k_relayout<<<grid_for(m, kBlock), kBlock, 0, st>>>(m, g->psid.as<uint32_t>(), g->pdir.as<uint8_t>(),
+        // with overlap the re-layout goes to side[0] and keeps its two temporaries alive until
+        // relayout_join; nothing on the context's stream reads g->key before that
+        hipStream_t rs = overlap && ctx->side[0] ? ctx->side[0] : st;
+        if (rs != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
+            DT_HIP(hipStreamWaitEvent(rs, ctx->ev_relay[0], 0));
+        }
+        prof_begin(ctx, kProfRelayout, rs);
+        k_relayout<<<grid_for(m, kBlock), kBlock, 0, rs>>>(m, g->psid.as<uint32_t>(), g->pdir.as<uint8_t>(),
             g->pstart.as<uint32_t>(), g->c1.as<uint32_t>(), dag_of.as<uint32_t>(), sflip.as<uint8_t>(),
             g->eoff.as<uint32_t>(), g->pkey.as<uint64_t>(), g->key.as<uint64_t>());
-        prof_end(ctx, kProfRelayout, st);
+        prof_end(ctx, kProfRelayout, rs);
         DT_HIP(hipGetLastError());
+        if (rs != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[1], rs));
+            g->relay_tmp[0] = std::move(dag_of);
+            g->relay_tmp[1] = std::move(sflip);
+            g->relay_pending = true;
+        }
     }
     unsigned mo = 0;
     DT_HIP(hipMemcpyAsync(&mo, scal.ptr, 4, hipMemcpyDeviceToHost, st));
