@@ -132,6 +132,7 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, hip_device);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned_out, 64 * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned_stage, kPinnedStage, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
@@ -149,6 +150,8 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
             if (c->ev_relay[i]) (void)hipEventDestroy(c->ev_relay[i]);
         }
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->pinned_out) (void)hipHostFree(c->pinned_out);
+        if (c->pinned_stage) (void)hipHostFree(c->pinned_stage);
         if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return fail(DT_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
@@ -158,6 +161,7 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
     if (rc != DT_OK) {
         (void)hipStreamDestroy(c->stream);
         (void)hipHostFree(c->pinned_out);
+        (void)hipHostFree(c->pinned_stage);
         delete c;
         return rc;
     }
@@ -178,6 +182,7 @@ int dt_ctx_destroy(dt_ctx *ctx) {
     ctx->out8.reset();
     pool_trim(ctx, 0);
     if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
+    if (ctx->pinned_stage) (void)hipHostFree(ctx->pinned_stage);
     for (auto &e : ctx->prof_ev)
         if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i) {

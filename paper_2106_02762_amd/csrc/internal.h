@@ -19,6 +19,8 @@
 
 namespace dt {
 
+constexpr size_t kPinnedStage = 512 * 1024;
+
 // ------------------------------------------------------------------------------------------------
 // errors
 // ------------------------------------------------------------------------------------------------
@@ -84,6 +86,7 @@ struct dt_ctx {
     dt::BatchRunner *batch = nullptr;        // dt_count_batch's runner (created on first use)
     uint32_t batch_light_chunk = 0;          // autotuned on first use (0 = not yet)
     int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
+    uint8_t *pinned_stage = nullptr;     // kPinnedStage bytes of pinned host memory for a build's read-backs
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
     // a count's light and medium kernels run on these, forked from and joined to the count's stream
     hipStream_t side[2] = {nullptr, nullptr};

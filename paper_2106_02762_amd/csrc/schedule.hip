@@ -11,6 +11,7 @@
 // statistics: the sum over triangles of the product of the three pair multiplicities (the count at
 // infinite deltas, an overflow bound) and the algorithmic bytes of one whole-graph count.
 #include <algorithm>
+#include <cstring>
 
 #include "count_dev.h"
 
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(kBlock)
 k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
            uint64_t cap_l, uint64_t cap_m, uint32_t force, uint32_t unit_ok, uint8_t *__restrict__ cls,
            uint32_t *__restrict__ bcnt, uint64_t *__restrict__ part) {
-    __shared__ unsigned long long s_w[kPartWords][kBlock];
+    __shared__ unsigned long long s_w[kPartWords][kBlock / 64];
     __shared__ unsigned s_cnt[4];
     if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -81,24 +82,104 @@ k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__r
 #pragma unroll
     for (int x = 0; x < 4; ++x)
         if (c[x]) atomicAdd(&s_cnt[x], c[x]);
-    s_w[0][threadIdx.x] = (unsigned long long)acc;
-    s_w[1][threadIdx.x] = (unsigned long long)(acc >> 64);
-    s_w[2][threadIdx.x] = bytes;
-    s_w[3][threadIdx.x] = bytes_light;
-    s_w[4][threadIdx.x] = bytes_medium;
-    s_w[5][threadIdx.x] = bytes_unit;
+    // block sums: within each wavefront by shuffles (the 128-bit sum as two words with carry), then
+    // over the wavefronts
+    unsigned long long lo = (unsigned long long)acc, hi = (unsigned long long)(acc >> 64);
+    unsigned long long w[kPartWords - 2] = {bytes, bytes_light, bytes_medium, bytes_unit};
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        const unsigned long long s = lo + lo2;
+        hi += hi2 + (s < lo ? 1ull : 0ull);
+        lo = s;
+#pragma unroll
+        for (int x = 0; x < kPartWords - 2; ++x) w[x] += __shfl_xor(w[x], o, 64);
+    }
+    const unsigned wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_w[0][wave] = lo;
+        s_w[1][wave] = hi;
+        for (int x = 2; x < kPartWords; ++x) s_w[x][wave] = w[x - 2];
+    }
     __syncthreads();
     if (threadIdx.x < 4) bcnt[4 * blockIdx.x + threadIdx.x] = s_cnt[threadIdx.x];
     if (threadIdx.x == 0) {
         unsigned __int128 t = 0;
-        unsigned long long w[kPartWords] = {0, 0, 0, 0, 0, 0};
-        for (unsigned j = 0; j < kBlock; ++j) {
+        unsigned long long tw[kPartWords] = {0, 0, 0, 0, 0, 0};
+        for (unsigned j = 0; j < kBlock / 64; ++j) {
             t += ((unsigned __int128)s_w[1][j] << 64) | s_w[0][j];
-            for (int x = 2; x < kPartWords; ++x) w[x] += s_w[x][j];
+            for (int x = 2; x < kPartWords; ++x) tw[x] += s_w[x][j];
         }
         part[kPartWords * blockIdx.x] = (uint64_t)t;
         part[kPartWords * blockIdx.x + 1] = (uint64_t)(t >> 64);
-        for (int x = 2; x < kPartWords; ++x) part[kPartWords * blockIdx.x + x] = w[x];
+        for (int x = 2; x < kPartWords; ++x) part[kPartWords * blockIdx.x + x] = tw[x];
+    }
+}
+
+// One workgroup: every classify block's first position in each class list (base, [block][class])
+// and the totals: tot[0..3] class sizes, tot[4..5] the 128-bit sum of sigma products, tot[6..9]
+// the byte totals.
+__global__ void __launch_bounds__(kBlock)
+k_cls_totals(unsigned nblk, const uint32_t *__restrict__ bcnt, const uint64_t *__restrict__ part,
+             uint64_t *__restrict__ base, uint64_t *__restrict__ tot) {
+    __shared__ unsigned long long s_tot[kBlock];
+    const unsigned tid = threadIdx.x;
+    const unsigned per = (nblk + kBlock - 1) / kBlock;
+    const unsigned b0 = min(tid * per, nblk), b1 = min(b0 + per, nblk);
+    for (int c = 0; c < 4; ++c) {
+        unsigned long long mine = 0;
+        for (unsigned b = b0; b < b1; ++b) mine += bcnt[4 * b + c];
+        s_tot[tid] = mine;
+        __syncthreads();
+        // exclusive prefix over threads (Hillis-Steele on the LDS copy)
+        for (unsigned o = 1; o < kBlock; o <<= 1) {
+            const unsigned long long y = tid >= o ? s_tot[tid - o] : 0ull;
+            __syncthreads();
+            s_tot[tid] += y;
+            __syncthreads();
+        }
+        unsigned long long run = s_tot[tid] - mine;
+        for (unsigned b = b0; b < b1; ++b) {
+            base[4 * b + c] = run;
+            run += bcnt[4 * b + c];
+        }
+        if (tid == kBlock - 1) tot[c] = s_tot[tid];
+        __syncthreads();
+    }
+    // the sums of the blocks' partial words, each thread over its blocks, then by shuffles
+    unsigned __int128 t = 0;
+    unsigned long long w[kPartWords] = {0, 0, 0, 0, 0, 0};
+    for (unsigned b = b0; b < b1; ++b) {
+        t += ((unsigned __int128)part[kPartWords * b + 1] << 64) | part[kPartWords * b];
+        for (int x = 2; x < kPartWords; ++x) w[x] += part[kPartWords * b + x];
+    }
+    unsigned long long lo = (unsigned long long)t, hi = (unsigned long long)(t >> 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+        const unsigned long long sum = lo + lo2;
+        hi += hi2 + (sum < lo ? 1ull : 0ull);
+        lo = sum;
+#pragma unroll
+        for (int x = 2; x < kPartWords; ++x) w[x] += __shfl_xor(w[x], o, 64);
+    }
+    __shared__ unsigned long long s_part[kBlock / 64][kPartWords];
+    if ((tid & 63) == 0) {
+        s_part[tid / 64][0] = lo;
+        s_part[tid / 64][1] = hi;
+        for (int x = 2; x < kPartWords; ++x) s_part[tid / 64][x] = w[x];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned __int128 tt = 0;
+        unsigned long long tw[kPartWords] = {0, 0, 0, 0, 0, 0};
+        for (unsigned j = 0; j < kBlock / 64; ++j) {
+            tt += ((unsigned __int128)s_part[j][1] << 64) | s_part[j][0];
+            for (int x = 2; x < kPartWords; ++x) tw[x] += s_part[j][x];
+        }
+        tot[4] = (uint64_t)tt;
+        tot[5] = (uint64_t)(tt >> 64);
+        for (int x = 2; x < kPartWords; ++x) tot[4 + x] = tw[x];
     }
 }
 
@@ -284,11 +365,11 @@ int cell_order(dt_ctx *ctx, uint64_t n, DevMem &ckey, DevMem &rec, DevMem &out, 
     return DT_OK;
 }
 
-// Work items of the medium list med (nm triangles) into items, their number to *n_items and each
-// triangle's first item to base (nm + 1 entries).
-int medium_items(dt_ctx *ctx, uint64_t nm, DevMem &med, DevMem &eoff, DevMem &items, uint64_t *n_items,
-                 DevMem &base, hipStream_t st) {
-    DevMem nch;
+// Work items of the medium list med (nm triangles): medium_sizes enqueues each triangle's item
+// count (nch) and first item (base, nm + 1 entries) and the total's read-back to *total (pinned
+// host memory, valid after the stream is synchronised); medium_fill then writes the items.
+int medium_sizes(dt_ctx *ctx, uint64_t nm, DevMem &med, DevMem &eoff, DevMem &nch, DevMem &base, uint64_t *total,
+                 hipStream_t st) {
     DT_TRY(dev_alloc(ctx, nch, (nm + 1) * 8));
     DT_TRY(dev_alloc(ctx, base, (nm + 1) * 8));
     DT_HIP(hipMemsetAsync(nch.ptr, 0, (nm + 1) * 8, st));
@@ -298,10 +379,11 @@ int medium_items(dt_ctx *ctx, uint64_t nm, DevMem &med, DevMem &eoff, DevMem &it
         DT_HIP(hipGetLastError());
     }
     DT_TRY(exclusive_scan_u64(ctx, nch.as<uint64_t>(), base.as<uint64_t>(), nm + 1, st));
-    uint64_t ni = 0;
-    DT_HIP(hipMemcpyAsync(&ni, base.as<uint64_t>() + nm, 8, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipStreamSynchronize(st));
-    *n_items = ni;
+    DT_HIP(hipMemcpyAsync(total, base.as<uint64_t>() + nm, 8, hipMemcpyDeviceToHost, st));
+    return DT_OK;
+}
+
+int medium_fill(dt_ctx *ctx, uint64_t nm, DevMem &nch, DevMem &base, uint64_t ni, DevMem &items, hipStream_t st) {
     DT_TRY(dev_alloc(ctx, items, ni * 8));
     if (nm) {
         k_medium_fill<<<grid_for(nm, kBlock), kBlock, 0, st>>>(nm, nch.as<uint64_t>(), base.as<uint64_t>(),
@@ -333,26 +415,17 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     k_classify<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), g->eoff.as<uint32_t>(), cap_l, cap_m, force,
                                         unit_ok, cls.as<uint8_t>(), bcnt.as<uint32_t>(), part.as<uint64_t>());
     DT_HIP(hipGetLastError());
-    std::vector<uint64_t> hp((size_t)grid * kPartWords);
-    std::vector<uint32_t> hc((size_t)grid * 4);
-    DT_HIP(hipMemcpyAsync(hp.data(), part.ptr, hp.size() * 8, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipMemcpyAsync(hc.data(), bcnt.ptr, hc.size() * 4, hipMemcpyDeviceToHost, st));
+    DevMem tot;
+    DT_TRY(dev_alloc(ctx, tot, 16 * 8));
+    k_cls_totals<<<1, kBlock, 0, st>>>(grid, bcnt.as<uint32_t>(), part.as<uint64_t>(), base.as<uint64_t>(),
+                                       tot.as<uint64_t>());
+    DT_HIP(hipGetLastError());
+    uint64_t *hs = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
+    DT_HIP(hipMemcpyAsync(hs, tot.ptr, 10 * 8, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    unsigned __int128 s3 = 0;
-    uint64_t w[kPartWords] = {0, 0, 0, 0, 0, 0};
-    for (unsigned b = 0; b < grid; ++b) {
-        s3 += ((unsigned __int128)hp[kPartWords * b + 1] << 64) | hp[kPartWords * b];
-        for (int x = 2; x < kPartWords; ++x) w[x] += hp[kPartWords * b + x];
-    }
-    // each block's first position in each class list
-    std::vector<uint64_t> hb((size_t)grid * 4);
-    uint64_t ncls[4] = {0, 0, 0, 0};
-    for (unsigned b = 0; b < grid; ++b)
-        for (int c = 0; c < 4; ++c) {
-            hb[4 * b + c] = ncls[c];
-            ncls[c] += hc[4 * b + c];
-        }
-    DT_HIP(hipMemcpyAsync(base.ptr, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st));
+    uint64_t ncls[4] = {hs[0], hs[1], hs[2], hs[3]};
+    const unsigned __int128 s3 = ((unsigned __int128)hs[5] << 64) | hs[4];
+    const uint64_t w[kPartWords] = {0, 0, hs[6], hs[7], hs[8], hs[9]};
     g->sum_sigma3 = s3;
     g->alg_bytes = w[2];
     g->alg_bytes_light = w[3];
@@ -395,8 +468,12 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     DT_TRY(dev_alloc(ctx, S.medium_w, nm * 12));
     DT_TRY(cell_order(ctx, S.n_light, lkey, lrec, S.light_w, lstart, st));
     DT_TRY(cell_order(ctx, nm, mkey, mrec, S.medium_w, mstart, st));
+    // read back through the pinned staging buffer: the light cell starts at word 0, the unit
+    // bucket starts from byte kStageUnit
+    constexpr size_t kStageUnit = 16384;
+    static_assert((kCells + 1) * 8 <= kStageUnit, "staging layout");
     S.light_cells.resize(kCells + 1);
-    DT_HIP(hipMemcpyAsync(S.light_cells.data(), lstart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipMemcpyAsync(ctx->pinned_stage, lstart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
     // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket); the
     // host keeps the bucket starts
     if (nu) {
@@ -409,17 +486,24 @@ int make_schedule(dt_graph *g, DevMem &tri) {
                                                                    ustart.as<uint32_t>());
         DT_HIP(hipGetLastError());
         S.unit_index.resize(nbk + 1);
-        DT_HIP(hipMemcpyAsync(S.unit_index.data(), ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, st));
+        if (kStageUnit + (nbk + 1) * 4 > kPinnedStage) return fail(DT_EDEVICE, "unit bucket index exceeds staging");
+        DT_HIP(hipMemcpyAsync(ctx->pinned_stage + kStageUnit, ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, st));
     }
     DT_HIP(hipStreamSynchronize(st));
+    memcpy(S.light_cells.data(), ctx->pinned_stage, (kCells + 1) * 8);
+    if (nu) memcpy(S.unit_index.data(), ctx->pinned_stage + kStageUnit, (nbk + 1) * 4);
     urec.reset();
     // medium work items of both copies (the same totals: the same triangles in another order)
     {
-        DevMem base;
-        uint64_t ni = 0, ni_w = 0;
-        DT_TRY(medium_items(ctx, nm, S.medium, g->eoff, S.mitems, &ni, base, st));
-        DT_TRY(medium_items(ctx, nm, S.medium_w, g->eoff, S.mitems_w, &ni_w, base, st));
+        DevMem nch0, base0, nch1, base;
+        uint64_t *ni2 = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
+        DT_TRY(medium_sizes(ctx, nm, S.medium, g->eoff, nch0, base0, &ni2[0], st));
+        DT_TRY(medium_sizes(ctx, nm, S.medium_w, g->eoff, nch1, base, &ni2[1], st));
+        DT_HIP(hipStreamSynchronize(st));
+        const uint64_t ni = ni2[0], ni_w = ni2[1];
         if (ni != ni_w) return fail(DT_EDEVICE, "medium work items of the two orders differ");
+        DT_TRY(medium_fill(ctx, nm, nch0, base0, ni, S.mitems, st));
+        DT_TRY(medium_fill(ctx, nm, nch1, base, ni_w, S.mitems_w, st));
         S.n_mitems = ni;
         DevMem istart;
         DT_TRY(dev_alloc(ctx, istart, (uint64_t)(kCells + 1) * 8));
@@ -427,8 +511,9 @@ int make_schedule(dt_graph *g, DevMem &tri) {
                                                                       istart.as<uint64_t>());
         DT_HIP(hipGetLastError());
         S.mitem_cells.resize(kCells + 1);
-        DT_HIP(hipMemcpyAsync(S.mitem_cells.data(), istart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(ctx->pinned_stage, istart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
+        memcpy(S.mitem_cells.data(), ctx->pinned_stage, (kCells + 1) * 8);
     }
     // heavy slots and chunks
     DevMem slots, nch, cbase;
@@ -445,12 +530,12 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     }
     DT_TRY(exclusive_scan_u64(ctx, slots.as<uint64_t>(), S.hslot.as<uint64_t>(), nh + 1, st));
     DT_TRY(exclusive_scan_u64(ctx, nch.as<uint64_t>(), cbase.as<uint64_t>(), nh + 1, st));
-    uint64_t tot[2] = {0, 0};
-    DT_HIP(hipMemcpyAsync(&tot[0], S.hslot.as<uint64_t>() + nh, 8, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipMemcpyAsync(&tot[1], cbase.as<uint64_t>() + nh, 8, hipMemcpyDeviceToHost, st));
+    uint64_t *htot = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
+    DT_HIP(hipMemcpyAsync(&htot[0], S.hslot.as<uint64_t>() + nh, 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipMemcpyAsync(&htot[1], cbase.as<uint64_t>() + nh, 8, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    S.n_slots = tot[0];
-    S.n_chunks = tot[1];
+    S.n_slots = htot[0];
+    S.n_chunks = htot[1];
     if (S.n_chunks > 0xffffffffull || nh > 0xffffffffull)
         return fail(DT_EOVERFLOW, "too many heavy work items (%llu)", (unsigned long long)S.n_chunks);
     DT_TRY(dev_alloc(ctx, S.chunks, S.n_chunks * 8));
