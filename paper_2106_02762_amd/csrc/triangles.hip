@@ -36,6 +36,8 @@ constexpr uint32_t kSplitU = 4096, kParts = 8;
 constexpr uint32_t kSingles = 16384;
 constexpr uint32_t kChunk = 16;
 constexpr uint32_t kOut = 192;    // triangles a wavefront buffers in LDS before appending them
+constexpr int kBatchBuild = 4;    // blocks of 64 flattened candidates a lane works on at once
+constexpr int kBatchFused = 1;    // (one in the one-shot pass: its counting holds the registers)
 
 __device__ __forceinline__ uint32_t find_u32(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
     uint32_t len = hi - lo;
@@ -86,7 +88,8 @@ struct FusedArgs {
 // atomic per kOut triangles.  Positions past `cap` are counted but not written.  In the one-shot
 // pass (FUSED) a full buffer is counted instead: each lane takes every 64th buffered triangle;
 // one with a single temporal edge per pair is tested as a unit record, a light one is counted
-// pairwise in the lane, and the others go to the rest list for the medium and heavy paths.
+// pairwise in the lane, and the others go to the rest list for the medium and heavy paths (one
+// atomic per wavefront and step); the wavefront's triangle count is added once, at the end.
 template <bool FUSED>
 struct TriSink {
     uint32_t *buf;      // LDS, 3 * kOut words
@@ -95,10 +98,11 @@ struct TriSink {
     uint64_t cap;
     unsigned long long *total;
     const FusedArgs *fa;
+    unsigned long long found = 0;   // triangles this wavefront counted (one-shot pass)
     int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long s3lo = 0, s3hi = 0;
-
-    __device__ __forceinline__ void count_one(uint32_t a, uint32_t b, uint32_t c) {
+    // counts one triangle; false when it belongs to the medium or heavy paths (the rest list)
+    __device__ __forceinline__ bool count_one(uint32_t a, uint32_t b, uint32_t c) {
         const FusedArgs &F = *fa;
         const uint32_t *eoff = F.eoff;
         const uint64_t s_uv = eoff[2 * a + 2] - eoff[2 * a], s_uw = eoff[2 * b + 2] - eoff[2 * b],
@@ -123,30 +127,58 @@ struct TriSink {
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc[j] += A.t[j];
         } else {
-            const unsigned long long r = atomicAdd(F.rest_n, 1ull);
-            if (r < F.rest_cap) {
-                F.rest[3 * r] = a;
-                F.rest[3 * r + 1] = b;
-                F.rest[3 * r + 2] = c;
-            }
+            return false;
         }
+        return true;
     }
 
     __device__ __forceinline__ void flush(unsigned lane) {
         if (n == 0) return;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
         if (FUSED) {
-            for (uint32_t x = lane; x < n; x += 64) count_one(buf[3 * x], buf[3 * x + 1], buf[3 * x + 2]);
+            found += n;
+            // each lane counts every 64th buffered triangle; the rest list takes one atomic per step
+            const FusedArgs &F = *fa;
+            for (uint32_t x0 = 0; x0 < n; x0 += 64) {
+                const uint32_t x = x0 + lane;
+                uint32_t a = 0, b = 0, c = 0;
+                bool rest = false;
+                if (x < n) {
+                    a = buf[3 * x];
+                    b = buf[3 * x + 1];
+                    c = buf[3 * x + 2];
+                    rest = !count_one(a, b, c);
+                }
+                const uint64_t m = __ballot(rest);
+                if (!m) continue;
+                unsigned long long r0 = 0;
+                if (lane == 0) r0 = atomicAdd(F.rest_n, (unsigned long long)__popcll(m));
+                r0 = __shfl(r0, 0, 64);
+                if (rest) {
+                    const unsigned long long r = r0 + (unsigned long long)__popcll(m & ((1ull << lane) - 1));
+                    if (r < F.rest_cap) {
+                        F.rest[3 * r] = a;
+                        F.rest[3 * r + 1] = b;
+                        F.rest[3 * r + 2] = c;
+                    }
+                }
+            }
         } else {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
             base = __shfl(base, 0, 64);
             for (uint32_t x = lane; x < 3 * n; x += 64)
                 if (base + x / 3 < cap) tri[3 * base + x] = buf[x];
         }
         __builtin_amdgcn_wave_barrier();
         n = 0;
+    }
+
+    // at the end: the buffer out, and in the one-shot pass the wavefront's count added
+    __device__ __forceinline__ void finish(unsigned lane) {
+        flush(lane);
+        if (FUSED && lane == 0 && found) atomicAdd(total, found);
     }
 
     // the lanes with hit set hold one triangle each; mask = the wave's ballot of hit
@@ -243,32 +275,92 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         if (in_lds) {
-            for (uint32_t b = part * 64; b < work; b += parts * 64) {
-                const uint32_t p = b + lane;
-                bool hit = false;
-                uint32_t i = 0, e_uw = 0, e_vw = 0;
-                if (p < work) {
-                    i = owner(pre_lds, du, p);
-                    const uint32_t j = p - pre_lds[i];
-                    const uint32_t vb = vb_lds[i];
-                    const uint32_t outv = dv_lds[i] != 0xffffu ? dv_lds[i] : dag_row[nbr_lds[i] + 1] - vb;
-                    if (outv <= du - i - 1) {
-                        // walk N+(v), search N+(u) after v in LDS
-                        const uint32_t w = dag_col[vb + j];
-                        const uint32_t pos = find_u32(nbr_lds, i + 1, du, w);
-                        hit = pos < du && nbr_lds[pos] == w;
-                        e_uw = r0 + pos;
-                        e_vw = vb + j;
-                    } else {
-                        // walk N+(u) after v, search N+(v) in global memory
-                        const uint32_t w = nbr_lds[i + 1 + j];
-                        const uint32_t pos = find_u32(dag_col, vb, vb + outv, w);
-                        hit = pos < vb + outv && dag_col[pos] == w;
-                        e_uw = r0 + i + 1 + j;
-                        e_vw = pos;
-                    }
+            // kBatch blocks of 64 candidates per step: their owners, then all their first loads,
+            // then their searches in lockstep, so that kBatch global loads per lane are in flight
+            // instead of one
+            constexpr int kBatch = FUSED ? kBatchFused : kBatchBuild;
+            for (uint32_t b = part * 64; b < work; b += parts * 64 * kBatch) {
+                uint32_t ci[kBatch], cj[kBatch], cvb[kBatch], cov[kBatch], w[kBatch], lo[kBatch], len[kBatch];
+                bool ok[kBatch], walk_v[kBatch];
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x) {
+                    const uint32_t p = b + (uint32_t)x * parts * 64 + lane;
+                    ok[x] = p < work;
+                    ci[x] = ok[x] ? owner(pre_lds, du, p) : 0u;
+                    cj[x] = p - pre_lds[ci[x]];
+                    cvb[x] = vb_lds[ci[x]];
+                    const uint32_t d16 = dv_lds[ci[x]];
+                    cov[x] = d16 != 0xffffu ? d16 : (ok[x] ? dag_row[nbr_lds[ci[x]] + 1] - cvb[x] : 0u);
+                    // walk N+(v) and search N+(u) after v in LDS, or walk N+(u) after v and search
+                    // N+(v) in global memory
+                    walk_v[x] = cov[x] <= du - ci[x] - 1;
                 }
-                out.put(hit, __ballot(hit), lane, r0 + i, e_uw, e_vw);
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x)
+                    w[x] = !ok[x] ? 0u : (walk_v[x] ? dag_col[cvb[x] + cj[x]] : nbr_lds[ci[x] + 1 + cj[x]]);
+                // searches in LDS (lower bound of w in nbr_lds[i + 1, du))
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x) {
+                    lo[x] = ci[x] + 1;
+                    len[x] = ok[x] && walk_v[x] ? du - ci[x] - 1 : 0u;
+                }
+                while (true) {
+                    bool more = false;
+#pragma unroll
+                    for (int x = 0; x < kBatch; ++x) {
+                        if (!len[x]) continue;
+                        const uint32_t half = len[x] >> 1;
+                        if (nbr_lds[lo[x] + half] < w[x]) {
+                            lo[x] += half + 1;
+                            len[x] -= half + 1;
+                        } else {
+                            len[x] = half;
+                        }
+                        more |= len[x] != 0;
+                    }
+                    if (!more) break;
+                }
+                uint32_t pos[kBatch];
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x) {
+                    pos[x] = lo[x];
+                    lo[x] = cvb[x];
+                    len[x] = ok[x] && !walk_v[x] ? cov[x] : 0u;
+                }
+                // searches in global memory (lower bound of w in N+(v)), loads of all kBatch together
+                while (true) {
+                    uint32_t val[kBatch];
+#pragma unroll
+                    for (int x = 0; x < kBatch; ++x) val[x] = len[x] ? dag_col[lo[x] + (len[x] >> 1)] : 0u;
+                    bool more = false;
+#pragma unroll
+                    for (int x = 0; x < kBatch; ++x) {
+                        if (!len[x]) continue;
+                        const uint32_t half = len[x] >> 1;
+                        if (val[x] < w[x]) {
+                            lo[x] += half + 1;
+                            len[x] -= half + 1;
+                        } else {
+                            len[x] = half;
+                        }
+                        more |= len[x] != 0;
+                    }
+                    if (!more) break;
+                }
+                uint32_t at[kBatch];
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x) {
+                    if (!ok[x]) at[x] = ~w[x];
+                    else if (walk_v[x]) at[x] = pos[x] < du ? nbr_lds[pos[x]] : ~w[x];
+                    else at[x] = lo[x] < cvb[x] + cov[x] ? dag_col[lo[x]] : ~w[x];
+                }
+#pragma unroll
+                for (int x = 0; x < kBatch; ++x) {
+                    const bool hit = ok[x] && at[x] == w[x];
+                    const uint32_t e_uw = walk_v[x] ? r0 + pos[x] : r0 + ci[x] + 1 + cj[x];
+                    const uint32_t e_vw = walk_v[x] ? cvb[x] + cj[x] : lo[x];
+                    out.put(hit, __ballot(hit), lane, r0 + ci[x], e_uw, e_vw);
+                }
             }
             // long walks into a long N+(v): copy N+(v) into LDS, then search it there
             for (uint32_t i = part; i + kStage < du; i += parts) {
@@ -314,7 +406,7 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
         __builtin_amdgcn_wave_barrier();
         }
     }
-    out.flush(lane);
+    out.finish(lane);
     if (lane == 0) atomicAdd(cand, wave_cand);
     if (FUSED) {
         // this wavefront's sums: its partial slot, and the 128-bit multiplicity sum with carry
@@ -361,7 +453,7 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint
                                               tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1, FusedArgs{});
         prof_end(ctx, kProfTriFill, st);
         DT_HIP(hipGetLastError());
-        uint64_t h[2] = {0, 0};
+        uint64_t *h = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
         DT_HIP(hipMemcpyAsync(h, c64, 16, hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
         *ntri_out = h[0];

@@ -3,7 +3,8 @@ as records with their ordering and orientation fixed at build time and counted b
 three times against the query.  Checked against the oracle (exact integers) on a graph where most
 of ~10^6 triangles are unit triangles, with windows narrow enough that the t1-ordered index skips
 most records, through single counts, the cells diagnostic and batches; and on a graph whose time
-span is too wide for the record format, where the path must stay off."""
+span is too wide for the record format, where the path must stay off.  The same graph's triangle
+list is checked against the oracle's."""
 import numpy as np
 import pytest
 
@@ -53,6 +54,18 @@ def test_unit_records_cover_most_triangles(scaled):
     assert parts == st["n_static_triangles"]
     assert st["n_unit_triangles"] > 0.8 * st["n_static_triangles"], st
     assert st["alg_bytes_unit"] == 16 * st["n_unit_triangles"]
+
+
+def test_triangle_list_matches_oracle(scaled):
+    """The build's triangle list on this graph (about a million triangles, written by thousands of
+    wavefronts in no particular order) holds exactly the oracle's triangles."""
+    g, b = scaled
+    st = dt.dt_graph_stats(b.h)
+    tri = dt.dt_graph_triangles(b.h)
+    assert tri.shape == (st["n_static_triangles"], 3)
+    tri = tri[np.lexsort(tri.T[::-1])]
+    otri = oracle.triangles(g.n, g.src, g.dst, g.t)
+    assert tri.shape == otri.shape and (tri == otri).all()
 
 
 def test_unit_windows_match_oracle(scaled):
