@@ -95,15 +95,6 @@ __device__ __forceinline__ uint32_t row_class(uint32_t len) {
     return len <= kLaneDeg ? 0u : (len <= kWaveDeg ? 1u : 2u);
 }
 
-__device__ __forceinline__ unsigned wave_max(unsigned x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned y = __shfl_xor(x, o, 64);
-        x = y > x ? y : x;
-    }
-    return x;
-}
-
 __device__ __forceinline__ unsigned wave_sum(unsigned x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

@@ -68,6 +68,23 @@ def test_multigraphs_every_split(ctx, caps):
             dt.dt_graph_free(h)
 
 
+def test_second_ordering_method(ctx):
+    """With the h-index ordering (order_method 1) the one-shot count, and a build and count after
+    it, still equal the oracle's (counts do not depend on the degeneracy ordering chosen)."""
+    g = synth.plain_full(n=60_000, ms=800_000)
+    h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
+    try:
+        dt.dt_graph_set_tuning(h, order_method=1)
+        q = (3600, 1800, 3600, dt.INT64_MIN, INF)
+        want = oracle.count(g.n, g.src, g.dst, g.t, *q)
+        assert (_oneshot(h, "scaled, h-index ordering", *q) == want).all()
+        say("build with the h-index ordering")
+        dt.dt_graph_build(h)
+        assert (dt.dt_count(h, *q) == want).all()
+    finally:
+        dt.dt_graph_free(h)
+
+
 def test_batch_graph_and_degenerate_inputs(ctx):
     g = synth.batch_graph(3)
     h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
