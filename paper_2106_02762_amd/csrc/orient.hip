@@ -86,13 +86,13 @@ __device__ __forceinline__ void dag_edge(uint64_t d, uint4 r, uint32_t *__restri
 
 // Sort every run by head rank (heads are distinct).  Wavefronts take chunks of kTailChunk tails
 // from a work counter; runs that fit together in 64 lanes are loaded in one piece and sorted at
-// once by a bitonic network on (run, head).  Longer runs go to a list for k_dag_sort_long.
+// once by a bitonic network on (run, head).  Longer runs are left to k_dag_sort_long.
 constexpr uint32_t kTailChunk = 64;
 
 __global__ void __launch_bounds__(kBlock)
 k_dag_sort(uint32_t n, const uint32_t *__restrict__ dag_row, const uint4 *__restrict__ runs,
            uint32_t *__restrict__ dag_col, uint32_t *__restrict__ dag_of, uint32_t *__restrict__ gsize,
-           unsigned *__restrict__ next_chunk, unsigned *__restrict__ n_long, uint32_t *__restrict__ longs) {
+           unsigned *__restrict__ next_chunk) {
     const unsigned lane = threadIdx.x & 63;
     for (;;) {
         uint32_t t0 = 0;
@@ -107,8 +107,7 @@ k_dag_sort(uint32_t n, const uint32_t *__restrict__ dag_row, const uint4 *__rest
             const uint32_t endl = r + lane < t1 ? dag_row[r + lane + 1] - b : 0xffffffffu;
             const uint64_t fits = __ballot(endl <= 64);
             const uint32_t cnt = fits == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~fits) - 1;
-            if (cnt == 0) {   // run r alone exceeds 64
-                if (lane == 0) longs[atomicAdd(n_long, 1u)] = r;
+            if (cnt == 0) {   // run r alone exceeds 64: listed by k_long_runs, sorted by k_dag_sort_long
                 r += 1;
                 continue;
             }
@@ -141,6 +140,20 @@ k_dag_sort(uint32_t n, const uint32_t *__restrict__ dag_row, const uint4 *__rest
             r += cnt;
         }
     }
+}
+
+// the tails whose runs are longer than 64 (one atomic per wavefront)
+__global__ void k_long_runs(uint32_t n, const uint32_t *__restrict__ dag_row, unsigned *__restrict__ n_long,
+                            uint32_t *__restrict__ longs) {
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned lane = threadIdx.x & 63;
+    const bool is_long = t < n && dag_row[t + 1] - dag_row[t] > 64;
+    const uint64_t m = __ballot(is_long);
+    if (!m) return;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(n_long, (unsigned)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (is_long) longs[base + (unsigned)__popcll(m & ((1ull << lane) - 1))] = t;
 }
 
 // Runs longer than 64: one workgroup per run, a bitonic sort of (head, index) keys in LDS (runs
@@ -275,14 +288,27 @@ int orient(dt_graph *g, bool overlap) {
             g->pstart.as<uint32_t>(), g->c1.as<uint32_t>(), g->dag_row.as<uint32_t>(), cursor.as<uint32_t>(),
             runs.as<uint4>());
         DT_HIP(hipGetLastError());
-        k_dag_sort<<<(unsigned)ctx->num_cus * 8, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), runs.as<uint4>(),
-            g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(), gsize.as<uint32_t>(), scal.as<unsigned>() + 8,
-            scal.as<unsigned>() + 16, longs.as<uint32_t>());
+        // runs of at most 64 on this stream, the longer ones beside them on side[1] (the two write
+        // disjoint DAG edges; every buffer they use lives until this function returns, after the join)
+        k_long_runs<<<grid_for(n, kBlock), kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), scal.as<unsigned>() + 16,
+                                                            longs.as<uint32_t>());
         DT_HIP(hipGetLastError());
-        k_dag_sort_long<<<(unsigned)ctx->num_cus * 4, kBlock, 0, st>>>(scal.as<unsigned>() + 16, longs.as<uint32_t>(),
+        hipStream_t ls = ctx->side[1] ? ctx->side[1] : st;
+        if (ls != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
+            DT_HIP(hipStreamWaitEvent(ls, ctx->ev_relay[0], 0));
+        }
+        k_dag_sort_long<<<(unsigned)ctx->num_cus * 4, kBlock, 0, ls>>>(scal.as<unsigned>() + 16, longs.as<uint32_t>(),
             g->dag_row.as<uint32_t>(), runs.as<uint4>(), g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(),
             gsize.as<uint32_t>());
         DT_HIP(hipGetLastError());
+        k_dag_sort<<<(unsigned)ctx->num_cus * 8, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), runs.as<uint4>(),
+            g->dag_col.as<uint32_t>(), dag_of.as<uint32_t>(), gsize.as<uint32_t>(), scal.as<unsigned>() + 8);
+        DT_HIP(hipGetLastError());
+        if (ls != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[1], ls));
+            DT_HIP(hipStreamWaitEvent(st, ctx->ev_relay[1], 0));
+        }
     }
     if (n) {
         unsigned grid = grid_for(n, kBlock);
