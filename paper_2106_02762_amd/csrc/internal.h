@@ -281,9 +281,11 @@ int sort_pairs_u64_u32(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
                        uint32_t *vout, size_t n, int end_bit, hipStream_t s);
 int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const uint64_t *vin,
                        uint64_t *vout, size_t n, int end_bit, hipStream_t s);
-// (16-bit key, 16-byte record) pairs
+// (16-bit key, 16-byte record) pairs; with `keep` the temporary storage is handed to the caller
+// instead of being released (and a foreign stream s is not waited for): for a sort left running on
+// a side stream, whose caller releases it after the join
 int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const uint4 *vin, uint4 *vout,
-                      size_t n, int end_bit, hipStream_t s);
+                      size_t n, int end_bit, hipStream_t s, DevMem *keep = nullptr);
 int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
 int exclusive_scan_u64(dt_ctx *ctx, const uint64_t *in, uint64_t *out, size_t n, hipStream_t s);
 

@@ -463,36 +463,48 @@ int make_schedule(dt_graph *g, DevMem &tri) {
         DT_HIP(hipGetLastError());
     }
     cls.reset();
+    // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket) on the
+    // first side stream, while this stream builds the other lists; the host keeps the bucket starts
+    // (read back through the pinned staging buffer from byte kStageUnit; the light cell starts and
+    // the other read-backs use the words before it)
+    constexpr size_t kStageUnit = 16384;
+    static_assert((kCells + 1) * 8 <= kStageUnit, "staging layout");
+    if (kStageUnit + (nbk + 1) * 4 > kPinnedStage) return fail(DT_EDEVICE, "unit bucket index exceeds staging");
+    DevMem usort_tmp;
+    const hipStream_t us = nu && ctx->side[0] ? ctx->side[0] : st;
+    // an early return must not release buffers the side stream still uses
+    struct Join {
+        hipStream_t s, main;
+        ~Join() {
+            if (s != main) (void)hipStreamSynchronize(s);
+        }
+    } join{us, st};
+    if (nu) {
+        DT_TRY(dev_alloc(ctx, ubkt2, nu * 2));
+        DT_TRY(dev_alloc(ctx, S.unit, nu * sizeof(uint4)));
+        DT_TRY(dev_alloc(ctx, ustart, (nbk + 1) * 4));
+        if (us != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
+            DT_HIP(hipStreamWaitEvent(us, ctx->ev_relay[0], 0));
+        }
+        DT_TRY(sort_pairs_u16_u4(ctx, ubkt.as<uint16_t>(), ubkt2.as<uint16_t>(), urec.as<uint4>(), S.unit.as<uint4>(),
+                                 nu, 16, us, us != st ? &usort_tmp : nullptr));
+        k_unit_starts<<<grid_for(nu + 1, kBlock), kBlock, 0, us>>>(nu, (uint32_t)nbk, ubkt2.as<uint16_t>(),
+                                                                   ustart.as<uint32_t>());
+        DT_HIP(hipGetLastError());
+        S.unit_index.resize(nbk + 1);
+        DT_HIP(hipMemcpyAsync(ctx->pinned_stage + kStageUnit, ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, us));
+        if (us != st) DT_HIP(hipEventRecord(ctx->ev_relay[1], us));
+    }
     // the windowed copies of the light and medium lists, in window-cell order
     DT_TRY(dev_alloc(ctx, S.light_w, S.n_light * 12));
     DT_TRY(dev_alloc(ctx, S.medium_w, nm * 12));
     DT_TRY(cell_order(ctx, S.n_light, lkey, lrec, S.light_w, lstart, st));
     DT_TRY(cell_order(ctx, nm, mkey, mrec, S.medium_w, mstart, st));
-    // read back through the pinned staging buffer: the light cell starts at word 0, the unit
-    // bucket starts from byte kStageUnit
-    constexpr size_t kStageUnit = 16384;
-    static_assert((kCells + 1) * 8 <= kStageUnit, "staging layout");
     S.light_cells.resize(kCells + 1);
     DT_HIP(hipMemcpyAsync(ctx->pinned_stage, lstart.ptr, (kCells + 1) * 8, hipMemcpyDeviceToHost, st));
-    // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket); the
-    // host keeps the bucket starts
-    if (nu) {
-        DT_TRY(dev_alloc(ctx, ubkt2, nu * 2));
-        DT_TRY(dev_alloc(ctx, S.unit, nu * sizeof(uint4)));
-        DT_TRY(sort_pairs_u16_u4(ctx, ubkt.as<uint16_t>(), ubkt2.as<uint16_t>(), urec.as<uint4>(), S.unit.as<uint4>(),
-                                 nu, 16, st));
-        DT_TRY(dev_alloc(ctx, ustart, (nbk + 1) * 4));
-        k_unit_starts<<<grid_for(nu + 1, kBlock), kBlock, 0, st>>>(nu, (uint32_t)nbk, ubkt2.as<uint16_t>(),
-                                                                   ustart.as<uint32_t>());
-        DT_HIP(hipGetLastError());
-        S.unit_index.resize(nbk + 1);
-        if (kStageUnit + (nbk + 1) * 4 > kPinnedStage) return fail(DT_EDEVICE, "unit bucket index exceeds staging");
-        DT_HIP(hipMemcpyAsync(ctx->pinned_stage + kStageUnit, ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, st));
-    }
     DT_HIP(hipStreamSynchronize(st));
     memcpy(S.light_cells.data(), ctx->pinned_stage, (kCells + 1) * 8);
-    if (nu) memcpy(S.unit_index.data(), ctx->pinned_stage + kStageUnit, (nbk + 1) * 4);
-    urec.reset();
     // medium work items of both copies (the same totals: the same triangles in another order)
     {
         DevMem nch0, base0, nch1, base;
@@ -544,7 +556,10 @@ int make_schedule(dt_graph *g, DevMem &tri) {
                                                                 chunk, S.chunks.as<uint32_t>());
         DT_HIP(hipGetLastError());
     }
+    // join the unit-record sort
+    if (nu && us != st) DT_HIP(hipStreamWaitEvent(st, ctx->ev_relay[1], 0));
     DT_HIP(hipStreamSynchronize(st));
+    if (nu) memcpy(S.unit_index.data(), ctx->pinned_stage + kStageUnit, (nbk + 1) * 4);
     return DT_OK;
 }
 

@@ -175,14 +175,15 @@ int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
 }
 
 int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const uint4 *vin, uint4 *vout,
-                      size_t n, int end_bit, hipStream_t s) {
+                      size_t n, int end_bit, hipStream_t s, DevMem *keep) {
     if (n == 0) return DT_OK;
     size_t bytes = 0;
     DT_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, n, 0u, (unsigned)end_bit, s));
     DevMem tmp;
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::radix_sort_pairs(tmp.ptr, bytes, kin, kout, vin, vout, n, 0u, (unsigned)end_bit, s));
-    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
+    if (keep) *keep = std::move(tmp);   // the caller releases it after joining stream s
+    else if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
     return DT_OK;
 }
 
