@@ -201,7 +201,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the count of one graph runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not built); run with --gpus 1",
+              "(sharding the triangles over several GPUs is not built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
