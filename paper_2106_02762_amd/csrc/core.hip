@@ -196,21 +196,11 @@ __device__ uint32_t grp_hindex(uint32_t b, uint32_t e, uint32_t hv, const uint32
         grp_sync<G>();
         for (uint32_t i = gl; i <= nb; i += G) hist[i] = 0;
         grp_sync<G>();
-        auto add = [&](uint32_t y) {
-            y = min(y, hv);
+        for (uint32_t j = b + gl; j < e; j += G) {
+            const uint32_t y = min(h[col[j]], hv);
             if (y > top) atomicAdd(&hist[nb], 1u);
             else if (y >= lo) atomicAdd(&hist[(y - lo) / B], 1u);
-        };
-        uint32_t j = b + gl;
-        for (; j + 3 * G < e; j += 4 * G) {   // four independent gathers in flight
-            const uint32_t x0 = col[j], x1 = col[j + G], x2 = col[j + 2 * G], x3 = col[j + 3 * G];
-            const uint32_t y0 = h[x0], y1 = h[x1], y2 = h[x2], y3 = h[x3];
-            add(y0);
-            add(y1);
-            add(y2);
-            add(y3);
         }
-        for (; j < e; j += G) add(h[col[j]]);
         grp_sync<G>();
         const uint32_t above = hist[nb];
         const unsigned c = grp_prefix_true<G>(hist, nb, above, lo, B, gl, s_red);
@@ -221,22 +211,29 @@ __device__ uint32_t grp_hindex(uint32_t b, uint32_t e, uint32_t hv, const uint32
     }
 }
 
-// number of row entries [b, e) whose bound is >= k, counted by a group (every thread gets the total)
-template <unsigned G>
-__device__ __forceinline__ uint32_t grp_count_ge(const uint32_t *__restrict__ col, const uint32_t *__restrict__ h,
-                                                 uint32_t b, uint32_t e, uint32_t k, unsigned gl, unsigned *s_red) {
-    uint32_t c = 0, j = b + gl;
-    for (; j + 7 * G < e; j += 8 * G) {   // eight independent gathers in flight
-        uint32_t x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = col[j + u * G];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) c += h[x[u]] >= k;
-    }
-    for (; j < e; j += G) c += h[col[j]] >= k;
-    return grp_sum<G>(c, s_red);
+// number of row entries [b, e) whose bound is >= k (one lane)
+__device__ __forceinline__ uint32_t lane_count_ge(const uint32_t *__restrict__ col, const uint32_t *__restrict__ h,
+                                                  uint32_t b, uint32_t e, uint32_t k) {
+    uint32_t c = 0;
+    for (uint32_t j = b; j < e; ++j) c += h[col[j]] >= k;
+    return c;
 }
 
+// h-index of a lane's vertex, capped at hv: the count c of bounds >= hv is a lower bound, and
+// binary search over [c, hv - 1] finds the largest k with at least k bounds >= k
+__device__ __forceinline__ uint32_t lane_hindex(uint32_t b, uint32_t e, uint32_t hv, const uint32_t *__restrict__ col,
+                                                const uint32_t *__restrict__ h) {
+    if (hv == 0) return 0;
+    const uint32_t c = lane_count_ge(col, h, b, e, hv);
+    if (c >= hv) return hv;
+    uint32_t lo = c, hi = hv - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (lane_count_ge(col, h, b, e, mid) >= mid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 struct Ctx {
     const uint32_t *__restrict__ row;
@@ -266,21 +263,20 @@ __device__ void grp_hindex_vertex(uint32_t v, const Ctx &C, uint32_t next, unsig
     const uint32_t b = C.row[v], e = C.row[v + 1];
     const uint32_t hv = C.h[v];   // written only by v's own processing
     if (hv == 0) return;
-    if (grp_count_ge<G>(C.col, C.h, b, e, hv, gl, s_red) >= hv) return;   // unchanged
     const uint32_t nh = grp_hindex<G, W>(b, e, hv, C.col, C.h, hist, gl, s_red);
     if (nh >= hv) return;
     if (gl == 0) __hip_atomic_store(&C.h[v], nh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t j = b + gl;
-    for (; j + 3 * G < e; j += 4 * G) {
-        const uint32_t w0 = C.col[j], w1 = C.col[j + G], w2 = C.col[j + 2 * G], w3 = C.col[j + 3 * G];
-        schedule(w0, nh, next, C);
-        schedule(w1, nh, next, C);
-        schedule(w2, nh, next, C);
-        schedule(w3, nh, next, C);
-    }
-    for (; j < e; j += G) schedule(C.col[j], nh, next, C);
+    for (uint32_t j = b + gl; j < e; j += G) schedule(C.col[j], nh, next, C);
 }
 
+__device__ void lane_hindex_vertex(uint32_t v, const Ctx &C, uint32_t next) {
+    const uint32_t b = C.row[v], e = C.row[v + 1];
+    const uint32_t hv = C.h[v];
+    const uint32_t nh = lane_hindex(b, e, hv, C.col, C.h);
+    if (nh >= hv) return;
+    __hip_atomic_store(&C.h[v], nh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t j = b; j < e; ++j) schedule(C.col[j], nh, next, C);
+}
 
 // degree stage: d(v) = neighbours of core >= core(v); d(v) <= core(v) puts v in removal round 0
 __device__ __forceinline__ void degree_done(uint32_t v, uint32_t dv, uint32_t hv, const Ctx &C, unsigned *s_kappa) {
@@ -297,10 +293,16 @@ template <unsigned G>
 __device__ void grp_degree_vertex(uint32_t v, const Ctx &C, unsigned gl, unsigned *s_red, unsigned *s_kappa) {
     const uint32_t b = C.row[v], e = C.row[v + 1];
     const uint32_t hv = C.h[v];
-    const unsigned c = grp_count_ge<G>(C.col, C.h, b, e, hv, gl, s_red);
+    unsigned c = 0;
+    for (uint32_t j = b + gl; j < e; j += G) c += C.h[C.col[j]] >= hv;
+    c = grp_sum<G>(c, s_red);
     if (gl == 0) degree_done(v, c, hv, C, s_kappa);
 }
 
+__device__ void lane_degree_vertex(uint32_t v, const Ctx &C, unsigned *s_kappa) {
+    const uint32_t hv = C.h[v];
+    degree_done(v, lane_count_ge(C.col, C.h, C.row[v], C.row[v + 1], hv), hv, C, s_kappa);
+}
 
 // removal stage, round r: v leaves its shell; a shell neighbour not yet removed whose d falls from
 // core + 1 to core is removed in round r + 1 (d only falls, once per removed neighbour, so exactly
@@ -316,173 +318,14 @@ template <unsigned G>
 __device__ void grp_remove_vertex(uint32_t v, const Ctx &C, uint32_t r, unsigned gl) {
     const uint32_t b = C.row[v], e = C.row[v + 1];
     const uint32_t cv = C.h[v];
-    uint32_t j = b + gl;
-    for (; j + 3 * G < e; j += 4 * G) {
-        const uint32_t w0 = C.col[j], w1 = C.col[j + G], w2 = C.col[j + 2 * G], w3 = C.col[j + 3 * G];
-        remove_edge(w0, cv, r, C);
-        remove_edge(w1, cv, r, C);
-        remove_edge(w2, cv, r, C);
-        remove_edge(w3, cv, r, C);
-    }
-    for (; j < e; j += G) remove_edge(C.col[j], cv, r, C);
+    for (uint32_t j = b + gl; j < e; j += G) remove_edge(C.col[j], cv, r, C);
 }
 
-
-// --- lane-kind vertices, 64 at a time per wavefront, their row entries spread over its lanes ----
-
-__device__ __forceinline__ unsigned wave_prefix_excl(unsigned x, unsigned lane, unsigned *total) {
-    unsigned incl = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned y = __shfl_up(incl, o, 64);
-        if (lane >= (unsigned)o) incl += y;
-    }
-    *total = __shfl(incl, 63, 64);
-    return incl - x;
+__device__ void lane_remove_vertex(uint32_t v, const Ctx &C, uint32_t r) {
+    const uint32_t b = C.row[v], e = C.row[v + 1];
+    const uint32_t cv = C.h[v];
+    for (uint32_t j = b; j < e; ++j) remove_edge(C.col[j], cv, r, C);
 }
-
-// words of a wavefront's LDS region: first entry of each lane's row in the spread order, row
-// start, value (bound or core), counter, and 32 bytes per lane for the values of its row
-constexpr uint32_t kLcStart = 0, kLcBase = 64, kLcVal = 128, kLcCnt = 192, kLcStage = 256;
-static_assert(kLcStage + 64 * kLaneDeg / 4 <= kWaveHist, "lane staging exceeds the wavefront's LDS");
-
-// the lane that owns spread entry k: the last lane whose first entry is <= k (a lane with an empty
-// row shares its start with the next one, so the last such lane has k inside its row)
-__device__ __forceinline__ uint32_t owner_of(const uint32_t *st, uint32_t k) {
-    uint32_t lo = 0;
-#pragma unroll
-    for (uint32_t s = 32; s > 0; s >>= 1)
-        if (st[lo + s] <= k) lo += s;
-    return lo;
-}
-
-// Calls f(owner, index in row, neighbour) for the T spread entries, four per lane in flight.
-template <class F>
-__device__ __forceinline__ void spread(uint32_t T, const uint32_t *reg, const uint32_t *__restrict__ col, F &&f) {
-    const unsigned lane = threadIdx.x & 63;
-    for (uint32_t k0 = 0; k0 < T; k0 += 256) {
-        uint32_t o[4], q[4], w[4];
-        bool ok[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t k = k0 + u * 64 + lane;
-            ok[u] = k < T;
-            o[u] = ok[u] ? owner_of(reg + kLcStart, k) : 0u;
-            q[u] = k - reg[kLcStart + o[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = ok[u] ? col[reg[kLcBase + o[u]] + q[u]] : 0u;
-        f(ok, o, q, w);
-    }
-}
-
-template <int S>
-__device__ void lane_chunk(const Ctx &C, bool act, uint32_t v, uint32_t arg, uint32_t *reg, unsigned *s_kappa) {
-    const unsigned lane = threadIdx.x & 63;
-    uint32_t b = 0, len = 0, val = 0;
-    if (act) {
-        b = C.row[v];
-        len = C.row[v + 1] - b;
-        val = C.h[v];
-    }
-    if (S == kHindex && val == 0) len = 0;   // a bound of 0 cannot fall
-    unsigned T;
-    const unsigned start = wave_prefix_excl(len, lane, &T);
-    if (S != kDegree && T == 0) return;
-    wave_sync();   // earlier users of the region are done
-    reg[kLcStart + lane] = start;
-    reg[kLcBase + lane] = b;
-    reg[kLcVal + lane] = val;
-    reg[kLcCnt + lane] = 0;
-    wave_sync();
-    if constexpr (S == kHindex) {
-        uint8_t *stg = reinterpret_cast<uint8_t *>(reg + kLcStage);
-        spread(T, reg, C.col, [&](const bool *ok, const uint32_t *o, const uint32_t *q, const uint32_t *w) {
-            uint32_t y[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y[u] = ok[u] ? C.h[w[u]] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ok[u]) stg[o[u] * kLaneDeg + q[u]] = (uint8_t)min(y[u], reg[kLcVal + o[u]]);
-        });
-        wave_sync();
-        // each lane: the h-index of its row's staged values (bounds capped at val <= 32)
-        uint32_t nh = val;
-        if (len) {
-            const uint8_t *my = stg + lane * kLaneDeg;
-            auto count_ge = [&](uint32_t k) {
-                uint32_t c = 0;
-                for (uint32_t i = 0; i < len; ++i) c += my[i] >= k;
-                return c;
-            };
-            const uint32_t c = count_ge(val);
-            if (c < val) {   // at least c values are >= c
-                uint32_t lo = c, hi = val - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (count_ge(mid) >= mid) lo = mid;
-                    else hi = mid - 1;
-                }
-                nh = lo;
-            }
-        }
-        const bool changed = len && nh < val;
-        if (changed) __hip_atomic_store(&C.h[v], nh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // schedule the neighbours of the lowered rows
-        unsigned T2;
-        const unsigned start2 = wave_prefix_excl(changed ? len : 0u, lane, &T2);
-        if (T2 == 0) return;
-        wave_sync();
-        reg[kLcStart + lane] = start2;
-        reg[kLcVal + lane] = nh;
-        wave_sync();
-        const uint32_t next = arg + 1;
-        spread(T2, reg, C.col, [&](const bool *ok, const uint32_t *o, const uint32_t *, const uint32_t *w) {
-            uint32_t hw[4], mk[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                hw[u] = ok[u] ? C.h[w[u]] : 0u;
-                mk[u] = ok[u] ? C.mark[w[u]] : next;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ok[u] && hw[u] > reg[kLcVal + o[u]] && mk[u] != next) {
-                    C.mark[w[u]] = next;
-                    *C.s_flag = 1;
-                }
-        });
-    } else if constexpr (S == kDegree) {
-        spread(T, reg, C.col, [&](const bool *ok, const uint32_t *o, const uint32_t *, const uint32_t *w) {
-            uint32_t y[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y[u] = ok[u] ? C.h[w[u]] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ok[u] && y[u] >= reg[kLcVal + o[u]]) atomicAdd(&reg[kLcCnt + o[u]], 1u);
-        });
-        wave_sync();
-        if (act) degree_done(v, reg[kLcCnt + lane], val, C, s_kappa);
-    } else {
-        const uint32_t r = arg;
-        spread(T, reg, C.col, [&](const bool *ok, const uint32_t *o, const uint32_t *, const uint32_t *w) {
-            uint32_t hw[4], rw[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                hw[u] = ok[u] ? C.h[w[u]] : 0u;
-                rw[u] = ok[u] ? C.rnd[w[u]] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t cv = reg[kLcVal + o[u]];
-                if (ok[u] && hw[u] == cv && rw[u] == kUnset && atomicSub(&C.d[w[u]], 1u) == cv + 1) {
-                    C.rnd[w[u]] = r + 1;
-                    *C.s_flag = 1;
-                }
-            }
-        });
-    }
-}
-
 
 // Whether v is processed in this phase: in the h-index stage when scheduled for it or already for
 // the next one (skipping those would let a vertex whose neighbours keep changing be put off phase
@@ -531,9 +374,12 @@ __device__ void run_phase(const Ctx &C, const uint32_t *__restrict__ all, const 
     }
     for (uint32_t c0 = gw * 64; c0 < cnt[0]; c0 += nw * 64) {
         const uint32_t i = c0 + lane;
-        const uint32_t v = i < cnt[0] ? all[base[0] + i] : 0u;
-        const bool act = i < cnt[0] && is_active<S>(v, arg, C);
-        if (__ballot(act)) lane_chunk<S>(C, act, v, arg, w_hist, s_kappa);
+        if (i >= cnt[0]) continue;
+        const uint32_t v = all[base[0] + i];
+        if (!is_active<S>(v, arg, C)) continue;
+        if constexpr (S == kHindex) lane_hindex_vertex(v, C, arg + 1);
+        else if constexpr (S == kDegree) lane_degree_vertex(v, C, s_kappa);
+        else lane_remove_vertex(v, C, arg);
     }
 }
 
