@@ -15,7 +15,7 @@
 // mostly adjacent (as do their edge lists in the temporal store); the list's order is otherwise
 // unspecified.  The list is sized at four triangles per static pair and the pass runs again at
 // the counted size when a graph has more.  A vertex whose N+(u) exceeds the LDS slice takes the
-// same steps on global memory.
+// same steps on global memory (degeneracy above the slice, as in the densest inputs of Table 1).
 #include <algorithm>
 
 #include "count_dev.h"
@@ -385,9 +385,10 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-        } else if (part == 0) {
-            // N+(u) larger than the LDS slice: the same candidates, v by v, on global memory
-            for (uint32_t i = 0; i + 1 < du; ++i) {
+        } else {
+            // N+(u) larger than the LDS slice: the same candidates, v by v, on global memory (the
+            // parts of a split vertex take every parts-th v)
+            for (uint32_t i = part; i + 1 < du; i += parts) {
                 const uint32_t v = nbr[i];
                 const uint32_t b0 = dag_row[v], dv = dag_row[v + 1] - b0;
                 for (uint32_t b = 0; b < dv; b += 64) {

@@ -91,6 +91,13 @@ def library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2106_02762_amd.build.build()")
+    # torch ships its own HIP runtime; loaded first, it is the one the library binds to as well, so a
+    # process that also uses torch's device memory holds a single runtime (with the system runtime
+    # loaded first, torch's own copy then finds no GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, U32, U64, I64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int
     PP = ctypes.POINTER(ctypes.c_void_p)

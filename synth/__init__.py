@@ -15,4 +15,5 @@ from .graphs import (  # noqa: F401
     batch_delta,
     served_stream,
     delta_triple_like_batch,
+    clique_graph,
 )

@@ -351,3 +351,34 @@ def served_stream(spans, duration_s: float = 60.0, rate: float = 2000.0,
         out.append({"arrival": float(arr[i]), "graph": g, "d13": d13, "d12": d12, "d23": d23,
                     "t_lo": ta, "t_hi": ta + width})
     return out
+
+
+def clique_graph(k: int, seed: int, multi_frac: float = 0.02, max_mult: int = 5, t_range: int = 10**5,
+                 noise_n: int = 0, noise_m: int = 0, all_mult: int = 0):
+    """A k-clique (degeneracy k - 1) of temporal edges, for the dense extremes of the paper's
+    inputs (large degeneracy, many triangles per static pair).  Each clique pair carries one
+    temporal edge, or 2..max_mult of them with probability multi_frac (all_mult > 0: exactly
+    all_mult on every pair); directions uniform; t ~ U{0..t_range-1}.  Optionally noise_m edges
+    on noise_n further nodes, each joined to a random clique node or to another noise node."""
+    rng = np.random.default_rng([SEED_BASE + 5, seed, k])
+    iu, ju = np.triu_indices(k, 1)
+    if all_mult:
+        mult = np.full(iu.shape[0], all_mult, dtype=np.int64)
+    else:
+        mult = np.ones(iu.shape[0], dtype=np.int64)
+        heavy = rng.random(iu.shape[0]) < multi_frac
+        mult[heavy] = rng.integers(2, max_mult + 1, int(heavy.sum()))
+    u = np.repeat(iu, mult).astype(np.int64)
+    v = np.repeat(ju, mult).astype(np.int64)
+    if noise_m:
+        a = k + rng.integers(0, noise_n, noise_m)
+        b = np.where(rng.random(noise_m) < 0.5, rng.integers(0, k, noise_m), k + rng.integers(0, noise_n, noise_m))
+        ok = a != b
+        u = np.concatenate([u, a[ok]])
+        v = np.concatenate([v, b[ok]])
+    flip = rng.random(u.shape[0]) < 0.5
+    src = np.where(flip, v, u).astype(np.uint32)
+    dst = np.where(flip, u, v).astype(np.uint32)
+    t = rng.integers(0, t_range, src.shape[0]).astype(np.int64)
+    perm = rng.permutation(src.shape[0])
+    return TemporalGraph(k + noise_n, src[perm], dst[perm], t[perm], name=f"clique{k}(seed={seed})")
