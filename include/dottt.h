@@ -159,6 +159,16 @@ int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]);
 /* The same, enqueued on `hip_stream` (a hipStream_t; NULL = the context's stream).  out8 is
  * device memory or pinned host memory that stays valid until the stream reaches the work. */
 int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream);
+/* dt_count_async without any allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same counts,
+ * enqueued on `hip_stream` (NULL = the context's stream) into out8 (device or pinned host memory,
+ * int64[8]), but the count's scratch -- per-block partial sums and the heavy path's prefix arrays --
+ * lives in one fixed 64 MiB device array per GPU, held until the process ends, instead of memory
+ * the context allocates.  A count that needs more scratch than that (a graph with many
+ * prefix-count triangles) returns DT_ENOMEM and enqueues nothing.  Every call on one GPU shares
+ * the array: calls whose work overlaps on the device (other streams, other threads, other
+ * contexts on the same GPU) race and must be ordered by the caller. */
+int dt_count_noalloc(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream);
 /* Diagnostic: the 48 per-(ordering, orientation) counts, out[(pi-1)*8 + (rho-1)], with u, v, w
  * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
 int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);

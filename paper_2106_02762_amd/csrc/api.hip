@@ -141,28 +141,31 @@ int dt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, dt_ctx **out) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_relay[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        if (c->ev_a) (void)hipEventDestroy(c->ev_a);
-        if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+    auto release = [](dt_ctx *x) {
+        x->out8.reset();
+        if (x->ev_a) (void)hipEventDestroy(x->ev_a);
+        if (x->ev_b) (void)hipEventDestroy(x->ev_b);
         for (int i = 0; i < 2; ++i) {
-            if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
-            if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
-            if (c->ev_relay[i]) (void)hipEventDestroy(c->ev_relay[i]);
+            if (x->side[i]) (void)hipStreamDestroy(x->side[i]);
+            if (x->ev_join[i]) (void)hipEventDestroy(x->ev_join[i]);
+            if (x->ev_relay[i]) (void)hipEventDestroy(x->ev_relay[i]);
         }
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        if (c->pinned_out) (void)hipHostFree(c->pinned_out);
-        if (c->pinned_stage) (void)hipHostFree(c->pinned_stage);
-        if (c->stream) (void)hipStreamDestroy(c->stream);
-        delete c;
+        if (x->ev_fork) (void)hipEventDestroy(x->ev_fork);
+        if (x->pinned_out) (void)hipHostFree(x->pinned_out);
+        if (x->pinned_stage) (void)hipHostFree(x->pinned_stage);
+        if (x->stream) (void)hipStreamDestroy(x->stream);
+        delete x;
+    };
+    if (e != hipSuccess) {
+        release(c);
         return fail(DT_EDEVICE, "context setup failed: %s", hipGetErrorString(e));
     }
     if (c->num_cus <= 0) c->num_cus = 256;
-    int rc = dev_alloc(c, c->out8, 64 * sizeof(int64_t), false);
+    // the no-allocation count's scratch address on this device (taken once per device)
+    int rc = noalloc_init(hip_device);
+    if (rc == DT_OK) rc = dev_alloc(c, c->out8, 64 * sizeof(int64_t), false);
     if (rc != DT_OK) {
-        (void)hipStreamDestroy(c->stream);
-        (void)hipHostFree(c->pinned_out);
-        (void)hipHostFree(c->pinned_stage);
-        delete c;
+        release(c);
         return rc;
     }
     *out = c;

@@ -629,33 +629,44 @@ int normalise_query(const dt_graph *g, const dt_query *qq, DQuery *out, bool *em
     return DT_OK;
 }
 
-// Enqueue one count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the 48
-// cells into cells_dev (zeroed here) instead.
-int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev, Scratch &sc, unsigned parts) {
-    dt_ctx *ctx = g->ctx;
-    Schedule &S = g->sched;
+void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p) {
+    const dt_ctx *ctx = g->ctx;
+    const Schedule &S = g->sched;
+    p.parts = parts;
     const bool do_light = parts & 1, do_medium = parts & 2, do_heavy = parts & 4;
     // the parts of the light and medium lists a windowed query can see
-    Ranges lr, mr;
-    cell_ranges(S.light_cells, S.cell_shift, q, lr);
-    cell_ranges(S.mitem_cells, S.cell_shift, q, mr);
-    const uint64_t nl = lr.pre[lr.n], nmi = mr.pre[mr.n];
-    const uint32_t *light = (q.windowed ? S.light_w : S.light).as<uint32_t>();
-    const uint32_t *medium = (q.windowed ? S.medium_w : S.medium).as<uint32_t>();
-    const uint32_t *mitems = (q.windowed ? S.mitems_w : S.mitems).as<uint32_t>();
+    cell_ranges(S.light_cells, S.cell_shift, q, p.lr);
+    cell_ranges(S.mitem_cells, S.cell_shift, q, p.mr);
+    const uint64_t nl = p.lr.pre[p.lr.n], nmi = p.mr.pre[p.mr.n];
+    p.light = (q.windowed ? S.light_w : S.light).as<uint32_t>();
+    p.medium = (q.windowed ? S.medium_w : S.medium).as<uint32_t>();
+    p.mitems = (q.windowed ? S.mitems_w : S.mitems).as<uint32_t>();
     const unsigned light_grid = (nl && do_light) ? (unsigned)std::min<uint64_t>(
         (nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
-    const unsigned lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
-    const unsigned hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    const unsigned mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * 8) : 0;
-    uint64_t ub = 0, ue = 0;
-    if (S.n_unit && (parts & 8)) unit_range(g, q, &ub, &ue);
-    const unsigned ug = ue > ub ? (unsigned)std::min<uint64_t>((ue - ub + kUnitPerBlock - 1) / kUnitPerBlock,
-                                                               (uint64_t)ctx->num_cus * 8) : 0;
-    const uint64_t n_part = (uint64_t)lg + hg + mg + ug;
-    DT_TRY(ensure(ctx, sc.partials, (n_part + 1) * 8 * sizeof(int64_t)));
-    int64_t *part = sc.partials.as<int64_t>();
+    p.lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
+    p.hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
+    p.mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * 8) : 0;
+    p.ub = p.ue = 0;
+    if (S.n_unit && (parts & 8)) unit_range(g, q, &p.ub, &p.ue);
+    p.ug = p.ue > p.ub ? (unsigned)std::min<uint64_t>((p.ue - p.ub + kUnitPerBlock - 1) / kUnitPerBlock,
+                                                      (uint64_t)ctx->num_cus * 8) : 0;
+    p.n_part = (uint64_t)p.lg + p.hg + p.mg + p.ug;
+    p.part_bytes = (p.n_part + 1) * 8 * sizeof(int64_t);
+    p.heavy_bytes = (S.n_heavy && do_heavy) ? S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256 : 0;
+}
+
+// Enqueue one planned count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the
+// 48 cells into cells_dev (zeroed here) instead.  The scratch must hold the plan's needs.
+int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
+                 int64_t *cells_dev, const ScratchView &sv) {
+    dt_ctx *ctx = g->ctx;
+    Schedule &S = g->sched;
+    if (sv.part_bytes < p.part_bytes || sv.heavy_bytes < p.heavy_bytes)
+        return fail(DT_EINVAL, "count scratch too small (%zu of %zu, %zu of %zu bytes)", sv.part_bytes, p.part_bytes,
+                    sv.heavy_bytes, p.heavy_bytes);
+    const unsigned lg = p.lg, hg = p.hg, mg = p.mg, ug = p.ug;
+    const uint64_t n_part = p.n_part;
+    int64_t *part = sv.part;
     if (cells) {
         k_zero<<<1, 64, 0, s>>>(48, cells_dev);
         DT_HIP(hipGetLastError());
@@ -679,10 +690,10 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     if (lg) {
         prof_begin(ctx, kProfLight, sl);
         if (cells)
-            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(lr, light,
+            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light,
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
         else
-            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(lr, light,
+            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light,
                 g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
         prof_end(ctx, kProfLight, sl);
         DT_HIP(hipGetLastError());
@@ -690,11 +701,11 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     if (mg) {
         prof_begin(ctx, kProfMedium, sm);
         if (cells)
-            k_medium<true, 256><<<mg, 256, 0, sm>>>(mr, medium, mitems,
+            k_medium<true, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems,
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
         else
-            k_medium<false, 256><<<mg, 256, 0, sm>>>(mr, medium, mitems,
+            k_medium<false, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems,
                 g->eoff.as<uint32_t>(),
                 g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
         prof_end(ctx, kProfMedium, sm);
@@ -705,15 +716,14 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         int64_t *up = part + 8 * ((uint64_t)lg + hg + mg);
         prof_begin(ctx, kProfUnit, s);
         if (cells)
-            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(ub, ue, S.unit.as<uint4>(), u, up, cells_dev);
+            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, cells_dev);
         else
-            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(ub, ue, S.unit.as<uint4>(), u, up, nullptr);
+            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, nullptr);
         prof_end(ctx, kProfUnit, s);
         DT_HIP(hipGetLastError());
     }
-    if (S.n_heavy && do_heavy) {
-        DT_TRY(ensure(ctx, sc.heavy_vals, S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256));
-        int64_t *P = sc.heavy_vals.as<int64_t>();
+    if (p.heavy_bytes) {
+        int64_t *P = reinterpret_cast<int64_t *>(sv.heavy);
         uint32_t *clip = reinterpret_cast<uint32_t *>(P + S.n_slots * kVals);
         k_heavy_clip<<<grid_for(S.n_heavy, 256), 256, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, clip);
@@ -760,6 +770,21 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
         DT_HIP(hipGetLastError());
     }
     return DT_OK;
+}
+
+// Plan one count, grow the scratch sc to its needs, and enqueue it on stream s.
+int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
+                  int64_t *cells_dev, Scratch &sc, unsigned parts) {
+    CountPlan p;
+    count_plan(g, q, parts, p);
+    DT_TRY(ensure(g->ctx, sc.partials, p.part_bytes));
+    if (p.heavy_bytes) DT_TRY(ensure(g->ctx, sc.heavy_vals, p.heavy_bytes));
+    ScratchView sv;
+    sv.part = sc.partials.as<int64_t>();
+    sv.part_bytes = sc.partials.bytes;
+    sv.heavy = sc.heavy_vals.as<uint8_t>();
+    sv.heavy_bytes = p.heavy_bytes ? sc.heavy_vals.bytes : 0;
+    return count_launch(g, q, p, out8_dev, s, cells, cells_dev, sv);
 }
 
 void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipStream_t s) {

@@ -250,11 +250,36 @@ void cell_ranges(const std::vector<uint64_t> &ix, int cell_shift, const DQuery &
 
 // counting
 int normalise_query(const dt_graph *g, const dt_query *q, DQuery *out, bool *empty);
-// Enqueue one count on stream s using scratch sc.  parts: bit 0 light, bit 1 medium, bit 2 heavy,
+// Device scratch of one count: per-block partial sums and the heavy path's prefix arrays.
+struct ScratchView {
+    int64_t *part = nullptr;
+    size_t part_bytes = 0;
+    uint8_t *heavy = nullptr;
+    size_t heavy_bytes = 0;
+};
+// Launch geometry of one count and the scratch it needs (count_plan, host only).
+struct CountPlan {
+    Ranges lr, mr;                               // light triangles and medium entries the query sees
+    const uint32_t *light = nullptr, *medium = nullptr, *mitems = nullptr;
+    unsigned lg = 0, hg = 0, mg = 0, ug = 0;     // grids of the light, heavy, medium and unit kernels
+    uint64_t ub = 0, ue = 0;                     // unit records [ub, ue)
+    uint64_t n_part = 0;                         // partial slots
+    size_t part_bytes = 0, heavy_bytes = 0;
+    unsigned parts = 15;
+};
+void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p);
+// Enqueue a planned count on stream s with scratch sv (which must hold the plan's needs).
+int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
+                 int64_t *cells_dev, const ScratchView &sv);
+// Enqueue one count on stream s using scratch sc (grown as needed).  parts: bit 0 light, bit 1 medium, bit 2 heavy,
 // bit 3 unit (all = 15).  Without cells the sum of the selected parts goes to out8_dev (int64[8]); with cells
 // the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
                   int64_t *cells_dev, Scratch &sc, unsigned parts = 15);
+// The no-allocation count's scratch: noalloc_init takes the current device's address of it (once
+// per device, from the context's setup); noalloc_capacity is its size in bytes.
+int noalloc_init(int device);
+size_t noalloc_capacity();
 // sum of n_part int64[8] partials into out8_dev, on stream s
 void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipStream_t s);
 // delta triples counted in one pass of a sweep

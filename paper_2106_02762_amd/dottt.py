@@ -30,7 +30,7 @@ INT64_MIN = -(1 << 63)
 ENTRY_POINTS = (
     "dt_strerror", "dt_last_error", "dt_ctx_create", "dt_ctx_destroy", "dt_ctx_memory",
     "dt_graph_load", "dt_graph_load_device", "dt_graph_build", "dt_graph_set_tuning",
-    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
+    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_noalloc", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
     "dt_graph_order", "dt_graph_triangles", "dt_graph_free", "dt_server_start",
     "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stop",
     "dt_ctx_set_profiling", "dt_ctx_last_profile",
@@ -114,6 +114,7 @@ def library():
         "dt_graph_stats": (I, [P, ctypes.POINTER(dt_stats)]),
         "dt_count": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_async": (I, [P, ctypes.POINTER(dt_query), P, P]),
+        "dt_count_noalloc": (I, [P, ctypes.POINTER(dt_query), P, P]),
         "dt_count_cells": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_oneshot": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_sweep": (I, [P, U64, P, P]),
@@ -243,6 +244,13 @@ def dt_count_async(g, query, out8_ptr, stream_ptr=None):
     _check(library().dt_count_async(g, ctypes.byref(query), ctypes.c_void_p(int(out8_ptr)),
                                     ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None),
            "dt_count_async")
+
+
+def dt_count_noalloc(g, query, out8_ptr, stream_ptr=None):
+    """dt_count_async with the scratch in the library's fixed per-device array (no allocation)."""
+    _check(library().dt_count_noalloc(g, ctypes.byref(query), ctypes.c_void_p(int(out8_ptr)),
+                                      ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None),
+           "dt_count_noalloc")
 
 
 def dt_count_cells(g, d13, d12, d23, t_lo=INT64_MIN, t_hi=DT_INF):
