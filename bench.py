@@ -106,6 +106,7 @@ def run_batched(dt, ctx, k, with_cpu):
            "speedup_vs_plain": round(plain_s / batch_s, 2),
            "graphs_per_s": round(k / batch_s, 1), "edges_per_s": round(m / batch_s, 1),
            "results_match_alone": ok,
+           "item_lengths_tuned": dict(zip(("light", "medium"), dt.dt_ctx_batch_tuning(ctx))),
            "oracle_checked": len(range(0, k, 32)) if with_cpu else 0, "results_match_oracle": oracle_ok}
     log("batched", res)
     return res, hs
@@ -324,18 +325,34 @@ def main():
                "matches_step": bool((o1 == out).all())}
     log("oneshot", oneshot)
     dt.dt_graph_build(h)
+    st0 = dt.dt_graph_stats(h)
 
-    # count alone on the resident build, per delta (the count does not depend on delta)
-    count_ms = {}
-    for dd in (600, 3600, 86400):
+    # count alone on the resident build, per delta up to infinity (Section 6: the time should not
+    # depend on the deltas), with the instrumented count's visits against Theorem 1's bound
+    count_ms, visits, count_kernels_by_delta = {}, {}, {}
+    sweep_ds = (600, 3600, 86400, 10**6, dt.DT_INF)
+    for dd in sweep_ds:
+        name = "inf" if dd == dt.DT_INF else str(dd)
         ts = []
         for _ in range(7 if dd != d else 21):
             torch.cuda.synchronize()
             a = time.perf_counter()
             dt.dt_count(h, dd, dd, dd)
             ts.append((time.perf_counter() - a) * 1e3)
-        count_ms[str(dd)] = round(statistics.median(ts[1:]), 4)
-    log("count ms", count_ms)
+        count_ms[name] = round(statistics.median(ts[1:]), 4)
+        pk = dt.dt_ctx_last_profile(ctx)
+        count_kernels_by_delta[name] = {k: round(float(pk[k]), 4) for k in
+                                        ("unit", "light", "medium", "heavy_prefix", "heavy_count") if pk[k] > 0}
+        got_v, v = dt.dt_count_visits(h, dd, dd, dd)
+        visits[name] = int(v)
+        if dd == dt.DT_INF:
+            inf_identity = int(got_v.sum()) == st0["sum_sigma3"]
+    bound = 2 * 48 * st0["degeneracy"] * g.m
+    cm = list(count_ms.values())
+    flat = {"count_ms": count_ms, "max_over_min": round(max(cm) / min(cm), 3),
+            "visits": visits, "visit_bound": bound, "visits_within_bound": max(visits.values()) <= bound,
+            "inf_sum_equals_sum_sigma3": inf_identity, "kernel_ms": count_kernels_by_delta}
+    log("count ms", flat)
 
     # a delta sweep (eight triples, the shape of the paper's parameter sweeps) in one pass against
     # eight separate counts
@@ -445,10 +462,15 @@ def main():
                    "parallelism": "single GPU"},
         "counts": out.tolist(),
         "count_ms": count_ms,
+        "delta_independence": flat,
         "count_edges_per_s": round(g.m / (count_ms[str(d)] / 1e3), 1),
         "sweep": sweep,
         "oneshot": oneshot,
         "kernel_ms": {k: round(v, 4) for k, v in mean.items()},
+        "autotuner": {"autotuned": st["autotuned"], "light_pair_cap": st["light_pair_cap_used"],
+                      "medium_cost_pct": st["medium_cost_pct_used"],
+                      "light_blocks_per_cu": st["light_blocks_per_cu"],
+                      "medium_blocks_per_cu": st["medium_blocks_per_cu"]},
         "build_ms": {"peel": round(st["ms_peel"], 3), "orient": round(st["ms_orient"], 3),
                      "triangles": round(st["ms_triangles"], 3),
                      "schedule": round(st["ms_schedule"], 3)},
@@ -457,6 +479,7 @@ def main():
                   "unit": st["n_unit_triangles"],
                   "light": st["n_light_triangles"], "medium": st["n_medium_triangles"],
                   "heavy": st["n_heavy_triangles"], "heavy_slots": st["heavy_slots"],
+                  "contested": st["n_contested_triangles"],
                   "tri_candidates": st["tri_candidates"],
                   "alg_bytes_count": st["alg_bytes"]},
         "roofline": roofline,

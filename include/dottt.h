@@ -75,7 +75,8 @@ typedef struct {
     uint32_t peel_rounds;          /* removal rounds of the parallel core peel                    */
     uint64_t sum_sigma3_lo, sum_sigma3_hi; /* sum over static triangles of the product of the
                                               three pair multiplicities, 128-bit                  */
-    uint64_t n_light_triangles, n_heavy_triangles; /* split chosen by the scheduler               */
+    uint64_t n_light_triangles, n_heavy_triangles; /* split chosen by the scheduler; a contested
+                                                      triangle is in both medium and heavy lists */
     uint64_t n_medium_triangles;
     uint64_t n_unit_triangles;     /* one temporal edge on each pair, stored as 16-byte records   */
     uint64_t alg_bytes;            /* algorithmic bytes of one whole-graph count: 16 per unit
@@ -89,6 +90,13 @@ typedef struct {
     uint64_t tri_candidates;       /* (v, w) candidates tested: sum over v of d-(v) d+(v)          */
     uint64_t heavy_slots;          /* prefix-array slots of the heavy path                        */
     double   ms_load, ms_peel, ms_orient, ms_triangles, ms_schedule; /* phase wall times          */
+    /* the count split and geometry the last build used */
+    uint64_t n_contested_triangles; /* split between the medium path and the prefix procedures
+                                       by each query's d13 (counted in n_medium and n_heavy)     */
+    uint32_t light_pair_cap_used, medium_cost_pct_used;
+    uint32_t light_blocks_per_cu, medium_blocks_per_cu;
+    uint32_t autotuned;            /* 1: the values above came from the autotuner                 */
+    uint32_t reserved0;
 } dt_stats;
 
 /* Tuning of the count scheduler.  A static triangle with one temporal edge on each pair (a unit
@@ -96,16 +104,22 @@ typedef struct {
  * testing its three times against the query (when the graph's time span is below 2^31).  Any other
  * triangle whose two source-incident pairs carry P = sigma_uv * sigma_uw temporal-edge pairs is
  * counted by one lane enumerating those pairs (the pairwise form of Lemma 1) when
- * P <= light_pair_cap and the {v,w} pair carries at most 64 edges, by one lane per edge of the
- * smaller source-incident pair that walks only the edges of the other pair within d13 of it (found
- * by binary search; a wavefront spreads those pairs over its lanes) when P <= medium_pair_cap,
- * and otherwise by the prefix-count procedures of Algorithms 1-3 split
- * into chunks of `heavy_chunk` source edges.  Zero fields keep the default; force_path 1-3 sends
- * every triangle, unit ones included, down one path. */
+ * P <= light_pair_cap and the {v,w} pair carries at most 64 edges.  The rest are split between two
+ * exact methods by a cost model with the query's d13 in it: the medium path (one lane per edge of
+ * the smaller source-incident pair, walking only the edges of the other pair within d13 of it,
+ * whose number grows with d13) and the prefix-count procedures of Algorithms 1-3 (Section 5, work
+ * (sigma_uv + sigma_uw) log sigma whatever the deltas).  At build time each such triangle gets the
+ * largest d13 (a power of two minus one) at which its close pairs stay within the prefix
+ * procedures' cost times medium_cost_pct / 100; a query takes it on the medium path up to that d13
+ * and on the prefix procedures beyond it, so no query does more than a constant times Theorem 1's
+ * work on it.  Zero fields keep the default (light_pair_cap and medium_cost_pct: the autotuner's
+ * choice for graphs of this size on this device, see dt_graph_build); force_path 1-3 sends every
+ * triangle, unit ones included, down one path. */
 typedef struct {
-    uint32_t light_pair_cap;       /* default 4                                                   */
+    uint32_t light_pair_cap;       /* 0 (default): the autotuner's choice, else 4                 */
     uint32_t heavy_chunk;          /* default 256 (the only compiled value)                       */
-    uint32_t medium_pair_cap;      /* default 2^27, at most 2^30                                  */
+    uint32_t medium_pair_cap;      /* default 2^27, at most 2^30: larger P always takes the
+                                      prefix procedures                                           */
     uint32_t force_path;           /* 0: split by the caps; 1: every triangle light;
                                       2: every triangle heavy; 3: every triangle medium
                                       (diagnostics and tests)                                     */
@@ -117,6 +131,12 @@ typedef struct {
                                       Both give the exact core numbers and an ordering with at
                                       most core(v) neighbours after each v; read by the next
                                       build or one-shot count                                    */
+    uint32_t medium_cost_pct;      /* weight of the prefix procedures' cost against the medium
+                                      path's, in percent (0: the autotuner's choice, else 100)    */
+    uint32_t autotune;             /* 0: tune on the first build of a graph of this size class
+                                      on this device (graphs of at least 2^20 static triangles;
+                                      smaller ones take the defaults); 1: never tune; 2: tune
+                                      again at the next build                                     */
 } dt_tuning;
 
 const char *dt_strerror(int code);
@@ -169,6 +189,13 @@ int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stre
  * the array: calls whose work overlaps on the device (other streams, other threads, other
  * contexts on the same GPU) race and must be ordered by the caller. */
 int dt_count_noalloc(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream);
+/* Diagnostic: dt_count with its kernels instrumented (slower).  *visits receives the work they
+ * did in the units of Theorem 1's bound (Section 5): one per unit record tested, per (uv edge,
+ * uw edge) pair evaluated on the light and medium paths, per outer edge of the medium path and per
+ * source edge in each of the two passes of the prefix procedures.  With at most one cost-model
+ * constant per triangle, visits stay within 2 * 48 * degeneracy * m', m' the temporal edges in the
+ * window, for every d13.  out: host int64[8], equal to dt_count's. */
+int dt_count_visits(dt_graph *g, const dt_query *q, int64_t out[8], uint64_t *visits);
 /* Diagnostic: the 48 per-(ordering, orientation) counts, out[(pi-1)*8 + (rho-1)], with u, v, w
  * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
 int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);
@@ -195,6 +222,12 @@ int dt_count_sweep(dt_graph *g, uint64_t k, const dt_query *queries, int64_t *ou
  * launch over a shared work table.  out: host int64[k][8]. */
 int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
                    int64_t (*out)[8]);
+
+/* The item lengths of the context's last batched launch (out[0] light triangles per item, out[1]
+ * medium entries per item), chosen by timing candidates on the first batch of each size class
+ * (number of queries and their work, binary orders) on this device and cached for the process;
+ * the server uses the same cache.  Host output uint32[2]. */
+int dt_ctx_batch_tuning(const dt_ctx *ctx, uint32_t out[2]);
 
 /* Diagnostics of the build products, for tests.  Host outputs.
  * dt_graph_order: core[v] (core number) and rank[v] (position of v in the ordering) for all n;

@@ -49,6 +49,29 @@ __global__ void k_tri_vertices(uint64_t nt, const uint32_t *__restrict__ tri, ui
     out[3 * i + 2] = z;
 }
 
+// The split and geometry of the next schedule: the user's fields where set, else the autotuner's
+// choice for g's size class (tuning it first when allowed and not cached: graphs of at least 2^20
+// static triangles, both split fields automatic, no forced path), else the defaults.
+int resolve_split(dt_graph *g, DevMem *tri) {
+    const dt_tuning &tu = g->tuning;
+    TunedCount t;
+    bool have = tu.autotune != 1 && tuned_lookup(g, &t);
+    const bool auto_split = tu.light_pair_cap == 0 && tu.medium_cost_pct == 0 && tu.force_path == 0;
+    g->tuned = 0;
+    if (tri && auto_split && tu.autotune != 1 && (tu.autotune == 2 || (!have && g->n_tri >= (1ull << 20)))) {
+        DT_TRY(autotune_count(g, *tri, &t));
+        have = true;
+        if (g->tuning.autotune == 2) g->tuning.autotune = 0;
+    }
+    if (!have || !auto_split) t = TunedCount();
+    g->light_cap_used = tu.light_pair_cap ? tu.light_pair_cap : t.light_cap;
+    g->cost_pct_used = tu.medium_cost_pct ? tu.medium_cost_pct : t.cost_pct;
+    g->geom.light_bpc = t.light_bpc;
+    g->geom.medium_bpc = t.medium_bpc;
+    g->tuned = have && auto_split ? 1 : 0;
+    return DT_OK;
+}
+
 int check_graph(const dt_graph *g, bool need_built) {
     if (!g) return fail(DT_EINVAL, "null graph");
     if (need_built && !g->built) return fail(DT_ENOTBUILT, "graph not built (call dt_graph_build)");
@@ -247,6 +270,7 @@ int dt_graph_build(dt_graph *g) {
     g->tri_candidates = cand;
     g->alg_bytes_tri = 4 * (g->m_s + cand) + 12 * ntri;
     double t3 = now_ms();
+    DT_TRY(resolve_split(g, &tri));
     DT_TRY(make_schedule(g, tri));
     double t4 = now_ms();
     g->ms_peel = t1 - t0;
@@ -263,6 +287,9 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     if (!tu) return fail(DT_EINVAL, "null tuning");
     dt_tuning nt = g->tuning;
     if (tu->light_pair_cap) nt.light_pair_cap = tu->light_pair_cap;
+    if (tu->medium_cost_pct) nt.medium_cost_pct = tu->medium_cost_pct;
+    if (tu->autotune > 2) return fail(DT_EINVAL, "autotune must be 0, 1 or 2");
+    nt.autotune = tu->autotune;
     if (tu->heavy_chunk) nt.heavy_chunk = tu->heavy_chunk;
     if (tu->medium_pair_cap) nt.medium_pair_cap = tu->medium_pair_cap;
     if (tu->force_path > 3) return fail(DT_EINVAL, "force_path must be 0, 1, 2 or 3");
@@ -282,6 +309,7 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     uint64_t ntri = 0, cand = 0;
     DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
     if (ntri != g->n_tri) return fail(DT_EDEVICE, "triangle enumeration changed between passes");
+    DT_TRY(resolve_split(g, g->tuning.autotune == 2 ? &tri : nullptr));
     return make_schedule(g, tri);
 }
 
@@ -322,6 +350,12 @@ int dt_graph_stats(const dt_graph *g, dt_stats *out) {
         out->ms_orient = g->ms_orient;
         out->ms_triangles = g->ms_tri;
         out->ms_schedule = g->ms_sched;
+        out->n_contested_triangles = g->sched.n_contested;
+        out->light_pair_cap_used = g->light_cap_used;
+        out->medium_cost_pct_used = g->cost_pct_used;
+        out->light_blocks_per_cu = g->geom.light_bpc;
+        out->medium_blocks_per_cu = g->geom.medium_bpc;
+        out->autotuned = (uint32_t)g->tuned;
     }
     return DT_OK;
 }
@@ -364,6 +398,11 @@ int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]) {
     if (empty) return DT_OK;
     dt_ctx *ctx = g->ctx;
     DeviceGuard dg(ctx->device);
+    // the split of the last build (or the user's, or the defaults)
+    if (g->tuning.light_pair_cap) g->light_cap_used = g->tuning.light_pair_cap;
+    if (!g->light_cap_used) g->light_cap_used = 4;
+    if (g->tuning.medium_cost_pct) g->cost_pct_used = g->tuning.medium_cost_pct;
+    if (!g->cost_pct_used) g->cost_pct_used = 100;
     // the cached products of an earlier build refer to the ordering about to be replaced
     g->built = false;
     g->sched = Schedule();
@@ -455,6 +494,31 @@ int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stre
     return DT_OK;
 }
 
+int dt_count_visits(dt_graph *g, const dt_query *q, int64_t out[8], uint64_t *visits) {
+    clear_error();
+    if (!out || !visits) return fail(DT_EINVAL, "null output");
+    DQuery dq;
+    bool empty = false;
+    DT_TRY(count_guarded(g, q, &dq, &empty));
+    *visits = 0;
+    if (empty || g->n_tri == 0) {
+        for (int i = 0; i < 8; ++i) out[i] = 0;
+        return DT_OK;
+    }
+    dt_ctx *ctx = g->ctx;
+    DeviceGuard dg(ctx->device);
+    // the counts in out8[0..8), the visits in out8[8]
+    int64_t *o = ctx->out8.as<int64_t>();
+    unsigned long long *v = reinterpret_cast<unsigned long long *>(o + 8);
+    DT_HIP(hipMemsetAsync(v, 0, 8, ctx->stream));
+    DT_TRY(count_enqueue(g, dq, o, ctx->stream, false, nullptr, ctx->scratch, 15, v));
+    DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    DT_HIP(hipStreamSynchronize(ctx->stream));
+    memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
+    *visits = (uint64_t)ctx->pinned_out[8];
+    return DT_OK;
+}
+
 int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]) {
     clear_error();
     if (!out) return fail(DT_EINVAL, "null output");
@@ -482,6 +546,14 @@ int dt_count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_qu
     if (k && (!graphs || !queries || !out)) return fail(DT_EINVAL, "null batch array");
     DeviceGuard dg(ctx->device);
     return count_batch(ctx, k, graphs, queries, out);
+}
+
+int dt_ctx_batch_tuning(const dt_ctx *ctx, uint32_t out[2]) {
+    clear_error();
+    if (!ctx || !out) return fail(DT_EINVAL, "null argument");
+    out[0] = ctx->batch_tune.light_chunk;
+    out[1] = ctx->batch_tune.medium_group;
+    return DT_OK;
 }
 
 int dt_ctx_set_profiling(dt_ctx *ctx, int enable) {

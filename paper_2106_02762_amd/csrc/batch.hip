@@ -9,11 +9,17 @@
 // whatever its composition.  Every item writes its own 8 partial sums (no atomics); a second
 // kernel adds each query's items.  The two kernels and the copy of the results to pinned host
 // memory are captured once in a HIP graph and replayed: only the item table, uploaded before the
-// replay, changes between batches.  The rare triangles beyond the medium path's reach (the
-// prefix-count path) are enqueued per query ahead of the replay and deliver their sums into a
-// reserved item slot.  The run length of light items is chosen by timing candidates on the first
-// batch of a context (autotuning); results never depend on it.
+// replay, changes between batches.  The triangles a query counts with the prefix procedures
+// (Algorithms 1-3: the contested ones below its level and those always counted that way) take
+// three more captured launches ahead of the main one, each over a table of its own: the clipped
+// bounds of their lists, then the two phases of the prefix pass per chunk of a list, into each
+// query's region of the runner's scratch; their count chunks are items of the main table.  The
+// run lengths of light and medium items are chosen by timing candidates on
+// the first batch of a size class on a device (autotuning, cached for the process and shared with
+// the server); results never depend on them.
+#include <array>
 #include <cstring>
+#include <map>
 #include <memory>
 
 #include "count_dev.h"
@@ -25,10 +31,10 @@ using namespace cdev;
 namespace {
 
 constexpr unsigned kBB = 256;
-constexpr uint32_t kMediumGroup = 1024;   // medium entries (one lane each) per table entry
 
 struct BQuery {
     const uint32_t *light, *medium, *mitems, *eoff;
+    const uint8_t *mlev;   // levels of the windowed medium copy (null: whole span)
     const uint64_t *key;
     const uint4 *unit;
     DQuery q;
@@ -36,20 +42,67 @@ struct BQuery {
 };
 
 struct BItem {
-    // kind 0: light triangles [b, e); 1: medium items [b, e); 2: heavy sums; 3: unit records [b, e)
+    // kind 0: light triangles [b, e); 1: medium items [b, e); 2: heavy count chunk b of heavy
+    // query e; 3: unit records [b, e)
     uint32_t q, kind, b, e;
 };
 
+// a piece of a heavy query's work before the main launch: clipped bounds of its heavy triangles
+// [b, e) (relative to its range), or prefix chunk b
+struct HItem {
+    uint32_t hq, b, e, pad;
+};
+
+__global__ void __launch_bounds__(kPrefixBlock)
+k_bheavy_clip(const HeavyArgs *__restrict__ hqs, const HItem *__restrict__ items, const uint32_t *__restrict__ n_p) {
+    const uint32_t n = *n_p;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const HItem I = items[it];
+        const uint32_t hl = I.b + threadIdx.x;
+        if (hl < I.e) heavy_clip_one(hqs[I.hq], hl);
+    }
+}
+
+// phase 0: the chunk-local prefixes and totals; phase 2: the carries added.  A prefix item's e is
+// the end of its query's prefix chunks.
+__global__ void __launch_bounds__(kPrefixBlock)
+k_bheavy_prefix(const HeavyArgs *__restrict__ hqs, const HItem *__restrict__ items, const uint32_t *__restrict__ n_p,
+                int phase) {
+    const uint32_t n = *n_p;
+    uint64_t vis = 0;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const HItem I = items[it];
+        const HeavyArgs A = hqs[I.hq];
+        if (phase == 0) heavy_prefix_local_chunk(A, I.b, vis);
+        else heavy_prefix_add_chunk(A, I.b);
+    }
+}
+
+// phase 1: the carries of every list (a thread per prefix item, the list's first chunk works)
+__global__ void k_bheavy_scan(const HeavyArgs *__restrict__ hqs, const HItem *__restrict__ items,
+                              const uint32_t *__restrict__ n_p) {
+    const uint32_t it = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= *n_p) return;
+    const HItem I = items[it];
+    heavy_prefix_scan_list(hqs[I.hq], I.b, I.e);
+}
+
 __global__ void __launch_bounds__(kBB)
 k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
-        const BQuery *__restrict__ qs, int64_t *__restrict__ part) {
+        const BQuery *__restrict__ qs, const HeavyArgs *__restrict__ hqs, int64_t *__restrict__ part) {
+    static_assert(kBB == 256, "a heavy count chunk is 256 source edges, one per thread");
     const uint32_t n_items = *n_items_p;
     const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const BItem I = items[it];
-        if (I.kind == 2) continue;
-        const BQuery Q = qs[I.q];
         Acc<false> acc;
+        if (I.kind == 2) {
+            heavy_count_chunk(hqs[I.e], I.b, acc);
+            block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
+            __syncthreads();
+            continue;
+        }
+        const BQuery Q = qs[I.q];
         if (I.kind == 3) {
             uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             unit_run<false, kBB>(Q.unit, I.b, I.e, Q.u, c, nullptr);
@@ -59,7 +112,7 @@ k_batch(const BItem *__restrict__ items, const uint32_t *__restrict__ n_items_p,
             for (uint64_t i = I.b + threadIdx.x; i < I.e; i += kBB) light_tri(Q.light, i, Q.eoff, Q.key, Q.q, acc);
         } else {
             for (uint64_t b = I.b + 64 * wave; b < I.e; b += kBB)
-                medium_lanes(Q.medium, Q.mitems, b + lane, b + lane < I.e, Q.eoff, Q.key, Q.q, acc, lane);
+                medium_lanes(Q.medium, Q.mitems, b + lane, b + lane < I.e, Q.eoff, Q.key, Q.q, acc, lane, Q.mlev);
         }
         block_store<kBB>(acc.t, part + 8 * (uint64_t)it);
         __syncthreads();
@@ -96,7 +149,6 @@ struct BatchRunner {
     dt_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
-    Scratch sc;
     // pinned host tables
     BItem *h_items = nullptr;
     BQuery *h_q = nullptr;
@@ -106,12 +158,26 @@ struct BatchRunner {
     // device tables
     DevMem d_items, d_q, d_qfirst, d_counts, d_part, d_out;
     uint64_t cap_items = 0, cap_q = 0;
+    // heavy work: per heavy query its arguments, the clip and prefix item tables, the scratch
+    HeavyArgs *h_hq = nullptr;
+    HItem *h_hitems = nullptr;
+    uint64_t cap_h_hq = 0, cap_h_hitems = 0;
+    DevMem d_hq, d_hclip, d_hpre, d_heavy;
+    uint64_t cap_hq = 0, cap_hclip = 0, cap_hpre = 0;
+    struct HeavyQ {
+        dt_graph *g;
+        uint32_t q;
+        HeavyRange hr;
+        uint64_t off;   // bytes into d_heavy
+    };
+    std::vector<HeavyQ> heavy;
+    uint64_t n_hclip = 0, n_hpre = 0, heavy_bytes = 0;
     // captured graph for the current capacities
     hipGraphExec_t gexec = nullptr;
     uint64_t g_items = 0, g_q = 0;
-    std::vector<std::pair<uint32_t, uint32_t>> heavy;   // (query, item slot)
     std::vector<std::pair<uint64_t, uint64_t>> uranges; // unit records of each query
     std::vector<Ranges> lranges, mranges;              // light and medium parts of each query
+    std::vector<const uint8_t *> mlevs;                 // level arrays of the windowed medium parts
     uint64_t n_items = 0, nq = 0;
 
     int init(dt_ctx *c) {
@@ -131,6 +197,8 @@ struct BatchRunner {
         if (h_qfirst) (void)hipHostFree(h_qfirst);
         if (h_counts) (void)hipHostFree(h_counts);
         if (h_out) (void)hipHostFree(h_out);
+        if (h_hq) (void)hipHostFree(h_hq);
+        if (h_hitems) (void)hipHostFree(h_hitems);
         if (done) (void)hipEventDestroy(done);
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
@@ -138,13 +206,17 @@ struct BatchRunner {
     }
 
     // Build the item table for k queries (empty[i]: the query's window holds no edge).
-    int plan(uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty, uint32_t light_chunk) {
+    int plan(uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty, const BatchTune &bt) {
         nq = k;
         heavy.clear();
+        n_hclip = n_hpre = heavy_bytes = 0;
+        const uint32_t light_chunk = bt.light_chunk, medium_group = bt.medium_group;
         const uint64_t unit_chunk = 4 * (uint64_t)light_chunk;
         uranges.resize(k);
         lranges.resize(k);
         mranges.resize(k);
+        mlevs.resize(k);
+        std::vector<char> has_heavy(k, 0);
         uint64_t total = 0;
         auto pieces = [](const Ranges &r, uint64_t len) {
             uint64_t c = 0;
@@ -156,24 +228,39 @@ struct BatchRunner {
             const Schedule &S = graphs[i]->sched;
             unit_range(graphs[i], qs[i], &uranges[i].first, &uranges[i].second);
             cell_ranges(S.light_cells, S.cell_shift, qs[i], lranges[i]);
-            cell_ranges(S.mitem_cells, S.cell_shift, qs[i], mranges[i]);
-            total += pieces(lranges[i], light_chunk) + pieces(mranges[i], kMediumGroup) + (S.n_heavy ? 1 : 0) +
+            medium_ranges(graphs[i], qs[i], mranges[i], &mlevs[i]);
+            HeavyRange hr;
+            heavy_range(graphs[i], qs[i], hr);
+            has_heavy[i] = hr.n > 0;
+            uint64_t nhc = 0;
+            if (hr.n) {
+                const Schedule &S = graphs[i]->sched;
+                nhc = S.n_chunks - hr.cb;
+                heavy.push_back(HeavyQ{graphs[i], (uint32_t)i, hr, heavy_bytes});
+                heavy_bytes += (hr.scratch_bytes + 255) & ~uint64_t(255);
+                n_hclip += (hr.n + kPrefixBlock - 1) / kPrefixBlock;
+                n_hpre += S.n_pchunks - hr.pb;
+            }
+            total += pieces(lranges[i], light_chunk) + pieces(mranges[i], medium_group) + nhc +
                      (uranges[i].second - uranges[i].first + unit_chunk - 1) / unit_chunk;
         }
+        if (n_hclip + n_hpre >= 0xffffffffull) return fail(DT_EOVERFLOW, "batch heavy table too large");
         if (total >= 0xffffffffull) return fail(DT_EOVERFLOW, "batch table too large");
         DT_TRY(host_grow(h_items, cap_h_items, total + 1));
         DT_TRY(host_grow(h_q, cap_h_q, k + 1));
         DT_TRY(host_grow(h_qfirst, cap_h_qfirst, k + 2));
         DT_TRY(host_grow(h_counts, cap_h_counts, 4));
-        uint64_t n = 0;
+        DT_TRY(host_grow(h_hq, cap_h_hq, heavy.size() + 1));
+        DT_TRY(host_grow(h_hitems, cap_h_hitems, n_hclip + n_hpre + 1));
+        uint64_t n = 0, hj = 0;
         for (uint64_t i = 0; i < k; ++i) {
             h_qfirst[i] = (uint32_t)n;
             dt_graph *g = graphs[i];
             const Schedule &S = g->sched;
             const bool w = qs[i].windowed;
             h_q[i] = BQuery{(w ? S.light_w : S.light).as<uint32_t>(), (w ? S.medium_w : S.medium).as<uint32_t>(),
-                            (w ? S.mitems_w : S.mitems).as<uint32_t>(),
-                            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), S.unit.as<uint4>(), qs[i],
+                            (w ? S.mitems_w : S.mitems).as<uint32_t>(), g->eoff.as<uint32_t>(),
+                            empty[i] ? nullptr : mlevs[i], g->key.as<uint64_t>(), S.unit.as<uint4>(), qs[i],
                             unit_query(qs[i])};
             if (empty[i]) continue;
             for (uint64_t b = uranges[i].first; b < uranges[i].second; b += unit_chunk)
@@ -188,21 +275,59 @@ struct BatchRunner {
                 }
             };
             add(lranges[i], 0, light_chunk);
-            add(mranges[i], 1, kMediumGroup);
-            if (S.n_heavy) {
-                heavy.emplace_back((uint32_t)i, (uint32_t)n);
-                h_items[n++] = BItem{(uint32_t)i, 2, 0, 0};
+            add(mranges[i], 1, medium_group);
+            if (has_heavy[i]) {
+                // its count chunks; the clip and prefix items go to their own tables
+                const HeavyQ &H = heavy[hj];
+                const Schedule &S = H.g->sched;
+                for (uint64_t ch = H.hr.cb; ch < S.n_chunks; ++ch)
+                    h_items[n++] = BItem{(uint32_t)i, 2, (uint32_t)ch, (uint32_t)hj};
+                ++hj;
             }
         }
         h_qfirst[k] = (uint32_t)n;
+        uint64_t nc = 0, np = 0;
+        for (uint64_t j = 0; j < heavy.size(); ++j) {
+            const HeavyQ &H = heavy[j];
+            for (uint64_t b = 0; b < H.hr.n; b += kPrefixBlock)
+                h_hitems[nc++] = HItem{(uint32_t)j, (uint32_t)b, (uint32_t)std::min<uint64_t>(b + kPrefixBlock, H.hr.n), 0};
+        }
+        for (uint64_t j = 0; j < heavy.size(); ++j) {
+            const HeavyQ &H = heavy[j];
+            for (uint64_t c = H.hr.pb; c < H.g->sched.n_pchunks; ++c)
+                h_hitems[n_hclip + np++] = HItem{(uint32_t)j, (uint32_t)c, (uint32_t)H.g->sched.n_pchunks, 0};
+        }
         h_counts[0] = (uint32_t)n;
         h_counts[1] = (uint32_t)k;
+        h_counts[2] = (uint32_t)n_hclip;
+        h_counts[3] = (uint32_t)n_hpre;
         n_items = n;
         return DT_OK;
     }
 
     int ensure_device() {
         bool regrow = false;
+        const bool grow = !d_items.ptr || cap_items < n_items + 1 || !d_q.ptr || cap_q < nq + 1 ||
+                          !d_hq.ptr || cap_hq < heavy.size() + 1 || !d_hclip.ptr || cap_hclip < n_hclip + 1 ||
+                          !d_hpre.ptr || cap_hpre < n_hpre + 1 || d_heavy.bytes < heavy_bytes;
+        // the buffers are replaced only when no earlier batch of this runner can still use them
+        if (grow) DT_HIP(hipStreamSynchronize(stream));
+        if (!d_hq.ptr || cap_hq < heavy.size() + 1) {
+            cap_hq = heavy.size() + heavy.size() / 2 + 16;
+            DT_TRY(dev_alloc(ctx, d_hq, cap_hq * sizeof(HeavyArgs), false));
+            regrow = true;
+        }
+        if (!d_hclip.ptr || cap_hclip < n_hclip + 1) {
+            cap_hclip = n_hclip + n_hclip / 2 + 64;
+            DT_TRY(dev_alloc(ctx, d_hclip, cap_hclip * sizeof(HItem), false));
+            regrow = true;
+        }
+        if (!d_hpre.ptr || cap_hpre < n_hpre + 1) {
+            cap_hpre = n_hpre + n_hpre / 2 + 64;
+            DT_TRY(dev_alloc(ctx, d_hpre, cap_hpre * sizeof(HItem), false));
+            regrow = true;
+        }
+        if (d_heavy.bytes < heavy_bytes) DT_TRY(dev_alloc(ctx, d_heavy, heavy_bytes + heavy_bytes / 4, false));
         if (!d_items.ptr || cap_items < n_items + 1) {
             cap_items = n_items + n_items / 2 + 64;
             DT_TRY(dev_alloc(ctx, d_items, cap_items * sizeof(BItem), false));
@@ -216,7 +341,10 @@ struct BatchRunner {
             DT_TRY(dev_alloc(ctx, d_out, cap_q * 8 * sizeof(int64_t), false));
             regrow = true;
         }
-        if (!d_counts.ptr) DT_TRY(dev_alloc(ctx, d_counts, 256, false));
+        if (!d_counts.ptr) {
+            DT_TRY(dev_alloc(ctx, d_counts, 256, false));
+            regrow = true;
+        }
         if (regrow || cap_h_out < 8 * cap_q) {
             DT_TRY(host_grow(h_out, cap_h_out, 8 * cap_q));
             if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -230,7 +358,12 @@ struct BatchRunner {
         const unsigned grid = (unsigned)ctx->num_cus * 8;
         hipGraph_t graph = nullptr;
         DT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        k_batch<<<grid, kBB, 0, stream>>>(d_items.as<BItem>(), d_counts.as<uint32_t>(), d_q.as<BQuery>(),
+        const uint32_t *cnt = d_counts.as<uint32_t>();
+        k_bheavy_clip<<<grid, kPrefixBlock, 0, stream>>>(d_hq.as<HeavyArgs>(), d_hclip.as<HItem>(), cnt + 2);
+        k_bheavy_prefix<<<grid, kPrefixBlock, 0, stream>>>(d_hq.as<HeavyArgs>(), d_hpre.as<HItem>(), cnt + 3, 0);
+        k_bheavy_scan<<<grid_for(cap_hpre, 256), 256, 0, stream>>>(d_hq.as<HeavyArgs>(), d_hpre.as<HItem>(), cnt + 3);
+        k_bheavy_prefix<<<grid, kPrefixBlock, 0, stream>>>(d_hq.as<HeavyArgs>(), d_hpre.as<HItem>(), cnt + 3, 2);
+        k_batch<<<grid, kBB, 0, stream>>>(d_items.as<BItem>(), cnt, d_q.as<BQuery>(), d_hq.as<HeavyArgs>(),
                                           d_part.as<int64_t>());
         k_batch_reduce<<<grid_for(cap_q, 256), 256, 0, stream>>>(d_counts.as<uint32_t>() + 1, d_qfirst.as<uint32_t>(),
                                                                  d_part.as<int64_t>(), d_out.as<int64_t>());
@@ -249,16 +382,26 @@ struct BatchRunner {
     }
 
     // Enqueue the planned batch on the runner's stream; results land in h_out when `done` fires.
-    int launch(dt_graph *const *graphs, const DQuery *qs) {
+    int launch(const DQuery *qs) {
         DT_TRY(ensure_device());
         DT_TRY(capture());
+        // the heavy queries' arguments, with their scratch regions
+        for (uint64_t j = 0; j < heavy.size(); ++j) {
+            const HeavyQ &H = heavy[j];
+            heavy_args(H.g, qs[H.q], H.hr, d_heavy.as<uint8_t>() + H.off, h_hq[j]);
+        }
         DT_HIP(hipMemcpyAsync(d_items.ptr, h_items, n_items * sizeof(BItem), hipMemcpyHostToDevice, stream));
         DT_HIP(hipMemcpyAsync(d_q.ptr, h_q, nq * sizeof(BQuery), hipMemcpyHostToDevice, stream));
         DT_HIP(hipMemcpyAsync(d_qfirst.ptr, h_qfirst, (nq + 1) * 4, hipMemcpyHostToDevice, stream));
-        DT_HIP(hipMemcpyAsync(d_counts.ptr, h_counts, 8, hipMemcpyHostToDevice, stream));
-        for (auto &hq : heavy)
-            DT_TRY(count_enqueue(graphs[hq.first], qs[hq.first], d_part.as<int64_t>() + 8 * (uint64_t)hq.second,
-                                 stream, false, nullptr, sc, 4));
+        DT_HIP(hipMemcpyAsync(d_counts.ptr, h_counts, 16, hipMemcpyHostToDevice, stream));
+        if (!heavy.empty()) {
+            DT_HIP(hipMemcpyAsync(d_hq.ptr, h_hq, heavy.size() * sizeof(HeavyArgs), hipMemcpyHostToDevice, stream));
+            if (n_hclip)
+                DT_HIP(hipMemcpyAsync(d_hclip.ptr, h_hitems, n_hclip * sizeof(HItem), hipMemcpyHostToDevice, stream));
+            if (n_hpre)
+                DT_HIP(hipMemcpyAsync(d_hpre.ptr, h_hitems + n_hclip, n_hpre * sizeof(HItem), hipMemcpyHostToDevice,
+                                      stream));
+        }
         DT_HIP(hipGraphLaunch(gexec, stream));
         DT_HIP(hipEventRecord(done, stream));
         return DT_OK;
@@ -279,9 +422,69 @@ int make_batch_runner(dt_ctx *ctx, BatchRunner **out) {
 }
 
 int batch_plan_and_launch(BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs, const bool *empty,
-                          uint32_t light_chunk) {
-    DT_TRY(r->plan(k, graphs, qs, empty, light_chunk));
-    return r->launch(graphs, qs);
+                          const BatchTune &bt) {
+    DT_TRY(r->plan(k, graphs, qs, empty, bt));
+    return r->launch(qs);
+}
+
+namespace {
+std::mutex g_bt_mu;
+std::map<std::array<int, 3>, BatchTune> g_bt_cache;
+
+// size class of a batch: device, binary orders of its queries and of its unit, light and medium work
+std::array<int, 3> batch_class(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const bool *empty) {
+    uint64_t work = 1;
+    for (uint64_t i = 0; i < k; ++i)
+        if (!empty[i]) work += graphs[i]->sched.n_unit + graphs[i]->sched.n_light + graphs[i]->sched.n_mitems;
+    auto lg = [](uint64_t x) {
+        int b = 0;
+        while (x > 1) {
+            x >>= 1;
+            ++b;
+        }
+        return b;
+    };
+    return {ctx->device, lg(k), lg(work)};
+}
+}  // namespace
+
+int batch_tuned(dt_ctx *ctx, BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs,
+                const bool *empty, BatchTune *out) {
+    const auto key = batch_class(ctx, k, graphs, empty);
+    {
+        std::lock_guard<std::mutex> lk(g_bt_mu);
+        auto it = g_bt_cache.find(key);
+        if (it != g_bt_cache.end()) {
+            *out = it->second;
+            return DT_OK;
+        }
+    }
+    // time each candidate on this batch (one warm launch, then one timed) and keep the fastest
+    const uint32_t lcs[3] = {2048, 8192, 32768}, mgs[3] = {512, 1024, 4096};
+    float best = 1e30f;
+    BatchTune bt;
+    for (uint32_t lc : lcs)
+        for (uint32_t mgp : mgs) {
+            const BatchTune c{lc, mgp};
+            DT_TRY(r->plan(k, graphs, qs, empty, c));
+            DT_TRY(r->launch(qs));
+            DT_HIP(hipEventRecord(r->t0, r->stream));
+            DT_TRY(r->launch(qs));
+            DT_HIP(hipEventRecord(r->t1, r->stream));
+            DT_HIP(hipEventSynchronize(r->t1));
+            float ms = 0;
+            DT_HIP(hipEventElapsedTime(&ms, r->t0, r->t1));
+            if (ms < best) {
+                best = ms;
+                bt = c;
+            }
+        }
+    {
+        std::lock_guard<std::mutex> lk(g_bt_mu);
+        g_bt_cache[key] = bt;
+    }
+    *out = bt;
+    return DT_OK;
 }
 
 int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]) {
@@ -316,30 +519,10 @@ int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query
     BatchRunner *r = ctx->batch;
     // the context's own stream and the runner's stream must not overlap on the graphs' scratch
     DT_HIP(hipStreamSynchronize(ctx->stream));
-    if (!ctx->batch_light_chunk) {
-        // autotune: time each candidate run length on this batch and keep the fastest
-        const uint32_t cands[3] = {2048, 8192, 32768};
-        float best = 1e30f;
-        uint32_t best_c = cands[1];
-        for (uint32_t c : cands) {
-            DT_TRY(r->plan(k, graphs, qs.data(), empty.get(), c));
-            DT_TRY(r->ensure_device());
-            DT_TRY(r->capture());
-            DT_TRY(r->launch(graphs, qs.data()));   // warm (uploads, graph instantiation)
-            DT_HIP(hipEventRecord(r->t0, r->stream));
-            DT_TRY(r->launch(graphs, qs.data()));
-            DT_HIP(hipEventRecord(r->t1, r->stream));
-            DT_HIP(hipEventSynchronize(r->t1));
-            float ms = 0;
-            DT_HIP(hipEventElapsedTime(&ms, r->t0, r->t1));
-            if (ms < best) {
-                best = ms;
-                best_c = c;
-            }
-        }
-        ctx->batch_light_chunk = best_c;
-    }
-    DT_TRY(batch_plan_and_launch(r, k, graphs, qs.data(), empty.get(), ctx->batch_light_chunk));
+    BatchTune bt;
+    DT_TRY(batch_tuned(ctx, r, k, graphs, qs.data(), empty.get(), &bt));
+    ctx->batch_tune = bt;
+    DT_TRY(batch_plan_and_launch(r, k, graphs, qs.data(), empty.get(), bt));
     return batch_wait(r, k, empty.get(), out);
 }
 

@@ -44,7 +44,7 @@ template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
         const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
-        int64_t *__restrict__ cells) {
+        int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
     Acc<CELLS> acc;
     acc.cells = cells;
     const uint64_t n_tri = R.pre[R.n];
@@ -56,26 +56,32 @@ k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__
     uint32_t r = 0;
     for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
         light_tri(tri, range_at(R, r, i), eoff, key, q, acc);
+    add_visits(visits, acc.visits);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
-// medium path: wave w takes the 64 entries from 64 w on, then those from 64 (w + W) on, ...
+// medium path: wave w takes the 64 entries from 64 w on, then those from 64 (w + W) on, ...;
+// with lev (windowed copies) entries of triangles below the query's level are skipped
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
-         const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, DQuery q,
-         int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
+         const uint8_t *__restrict__ lev, const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
+         DQuery q, int64_t *__restrict__ partial, int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
     Acc<CELLS> acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
     const uint64_t n_ent = R.pre[R.n];
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
     uint32_t r = 0;
+    uint64_t vis = 0;
     for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
         const uint64_t j = b + lane;
         const bool active = j < n_ent;
-        medium_lanes(med, ent, active ? range_at(R, r, j) : 0, active, eoff, key, q, acc, lane);
+        // one visit per outer edge, plus the wavefront's close pairs (counted by lane 0)
+        const uint32_t pairs = medium_lanes(med, ent, active ? range_at(R, r, j) : 0, active, eoff, key, q, acc, lane, lev);
+        vis += (active ? 1u : 0u) + (lane == 0 ? pairs : 0u);
     }
+    add_visits(visits, vis);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -83,13 +89,14 @@ k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict_
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_unit(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, UQuery u, int64_t *__restrict__ partial,
-       int64_t *__restrict__ cells) {
+       int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
     const uint64_t n = end - beg;
     const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t b = beg + (uint64_t)blockIdx.x * per;
     const uint64_t e = b + per < end ? b + per : end;
     uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (b < e) unit_run<CELLS, BLOCK>(rec, b, e, u, c, cells);
+    if (visits && threadIdx.x == 0 && e > b) atomicAdd(visits, (unsigned long long)(e - b));
     if (!CELLS) {
         int64_t t[8];
 #pragma unroll
@@ -99,270 +106,43 @@ k_unit(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, UQuery u, int6
 }
 
 // ---------------------------------------------------------------------------------------------
-// heavy path
+// heavy path (the per-item bodies are in count_dev.h, shared with the batched kernel)
 // ---------------------------------------------------------------------------------------------
-// window-clipped bounds of the six lists of every heavy triangle
-__global__ void k_heavy_clip(uint64_t n_heavy, const uint32_t *__restrict__ tri,
-                             const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
-                             DQuery q, uint32_t *__restrict__ clip) {
-    uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n_heavy) return;
-    Lists L;
-    load_lists(eoff, tri[3 * h], tri[3 * h + 1], tri[3 * h + 2], key, q, L);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        clip[12 * h + 2 * i] = L.lo[i];
-        clip[12 * h + 2 * i + 1] = L.hi[i];
-    }
+// window-clipped bounds of the six lists of every heavy triangle of the query
+__global__ void k_heavy_clip(HeavyArgs A, uint64_t n_q) {
+    const uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < n_q) heavy_clip_one(A, h);
 }
 
-// full (unclipped) start of the six lists, from the DAG edge offsets
-__device__ __forceinline__ void full_lists(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ t3,
-                                           uint32_t (&beg)[7]) {
-    // beg[i], beg[i+1] delimit list i for i = 0..3 (uv+, uv-, uw+, uw-)
-    beg[0] = eoff[2 * t3[0]];
-    beg[1] = eoff[2 * t3[0] + 1];
-    beg[2] = eoff[2 * t3[0] + 2];
-    beg[3] = eoff[2 * t3[1]];
-    beg[4] = eoff[2 * t3[1] + 1];
-    beg[5] = eoff[2 * t3[1] + 2];
-    beg[6] = 0;
-}
-
-// Prefix values per source edge (the cumulative edge counts of Algorithms 1-3), for
-// list X of heavy triangle h, against the two vw lists (c = 0, 1):
-//   E_c = #{z in vw_c : t_z <= t + d13}                  (Algorithm 1, prefix over S1)
-//   A_c = #{z in vw_c : key_z < key}                     (Algorithm 2, prefix over S3)
-//   B_c = #{z in vw_c : t_z < t - d23}                   (Algorithm 2, prefix over S3)
-//   C_c = #{z in vw_c : t_z < t - d13}                   (Algorithm 3, prefix over S3)
-// stored as exclusive prefix sums P_v[r] over the clipped list, r = 0..len.
-constexpr unsigned kPrefixBlock = 256;
-constexpr int kVals = 8;   // E0, E1, A0, A1, B0, B1, C0, C1
-
-template <class T> __device__ __forceinline__ T wave_incl_scan(T v, unsigned lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T y = __shfl_up(v, o, 64);
-        if (lane >= (unsigned)o) v += y;
-    }
-    return v;
-}
-
+// phase 1 of the prefix pass over prefix chunks [A.pb, pe)
 __global__ void __launch_bounds__(kPrefixBlock)
-k_heavy_prefix(uint64_t n_heavy, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
-               const uint64_t *__restrict__ key, const uint32_t *__restrict__ clip,
-               const uint64_t *__restrict__ hslot, uint64_t n_slots, DQuery q,
-               int64_t *__restrict__ P) {
-    const uint64_t h = blockIdx.x / 4;
-    const int X = blockIdx.x % 4;
-    if (h >= n_heavy) return;
-    const uint32_t *t3 = tri + 3 * h;
-    uint32_t beg[7];
-    full_lists(eoff, t3, beg);
-    // slots of the four source lists follow each other, sized by the unclipped lengths
-    const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
-    uint64_t base = hslot[h];
-    for (int Y = 0; Y < X; ++Y) base += len_full[Y] + 1;
-    const uint32_t lo = clip[12 * h + 2 * X], hi = clip[12 * h + 2 * X + 1];
-    const uint32_t z0 = clip[12 * h + 8], z0e = clip[12 * h + 9];
-    const uint32_t z1 = clip[12 * h + 10], z1e = clip[12 * h + 11];
-    const uint32_t len = hi - lo;
-    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
-    __shared__ int64_t s_tot[kPrefixBlock / 64][kVals];
-    int64_t carry[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t c0 = 0; c0 < len; c0 += kPrefixBlock) {
-        const uint32_t r = c0 + threadIdx.x;
-        int64_t v[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (r < len) {
-            const uint64_t k = key[lo + r];
-            const int64_t t = (int64_t)(k >> q.shift);
-            v[0] = lower(key, z0, z0e, before_time(t + q.d13 + 1, q)) - z0;
-            v[1] = lower(key, z1, z1e, before_time(t + q.d13 + 1, q)) - z1;
-            v[2] = lower(key, z0, z0e, k) - z0;
-            v[3] = lower(key, z1, z1e, k) - z1;
-            v[4] = lower(key, z0, z0e, before_time(t - q.d23, q)) - z0;
-            v[5] = lower(key, z1, z1e, before_time(t - q.d23, q)) - z1;
-            v[6] = lower(key, z0, z0e, before_time(t - q.d13, q)) - z0;
-            v[7] = lower(key, z1, z1e, before_time(t - q.d13, q)) - z1;
-        }
-        int64_t incl[kVals];
-#pragma unroll
-        for (int i = 0; i < kVals; ++i) incl[i] = wave_incl_scan((long long)v[i], lane);
-        if (lane == 63) {
-#pragma unroll
-            for (int i = 0; i < kVals; ++i) s_tot[wave][i] = incl[i];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kVals; ++i) {
-            int64_t before = carry[i];
-            int64_t total = 0;
-            for (unsigned w = 0; w < kPrefixBlock / 64; ++w) {
-                if (w < wave) before += s_tot[w][i];
-                total += s_tot[w][i];
-            }
-            if (r < len) P[(uint64_t)i * n_slots + base + r] = before + incl[i] - v[i];
-            carry[i] += total;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kVals; ++i) P[(uint64_t)i * n_slots + base + len] = carry[i];
-    }
+k_heavy_prefix_local(HeavyArgs A, uint64_t pe, unsigned long long *__restrict__ visits) {
+    uint64_t vis = 0;
+    for (uint64_t c = A.pb + blockIdx.x; c < pe; c += gridDim.x) heavy_prefix_local_chunk(A, c, vis);
+    add_visits(visits, vis);
 }
 
-// One source edge e (key k, time t) on list X of heavy triangle h, as e2 of Algorithm 1, e1 of
-// Algorithm 2 and e2 of Algorithm 3, against both directions of the other source pair (b) and of
-// {v,w} (c).
-struct HeavyCtx {
-    const uint64_t *key;
-    const int64_t *P;
-    uint64_t n_slots;
-    uint64_t slot[4];          // first slot of the prefix arrays of lists 0..3
-    uint32_t lo[6], hi[6];     // clipped bounds
-};
-
-template <bool CELLS, int X, int B, int C>
-__device__ __forceinline__ void heavy_cell(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
-                                           Acc<CELLS> &acc, const uint32_t (&o)[8]) {
-    // element's pair: uv for X = 0, 1 and uw for X = 2, 3; direction a = X & 1
-    constexpr bool kUv = X < 2;
-    constexpr int a = X & 1;
-    constexpr int OL = kUv ? 2 + B : B;            // other source list
-    constexpr int DUV = kUv ? a : B, DUW = kUv ? B : a;
-    const uint32_t zb = H.lo[4 + C], ze = H.hi[4 + C];
-    const uint32_t olo = H.lo[OL];
-    // searches into the vw list of direction C
-    const uint64_t *key = H.key;
-    const int64_t r_lt = (int64_t)(lower(key, zb, ze, k) - zb);                          // key < k
-    const int64_t r_d23 = (int64_t)(lower(key, zb, ze, before_time(t + q.d23 + 1, q)) - zb); // t <= t + d23
-    const int64_t r_d12 = (int64_t)(lower(key, zb, ze, before_time(t + q.d12 + 1, q)) - zb); // t <= t + d12
-    const int64_t r_m12 = (int64_t)(lower(key, zb, ze, before_time(t - q.d12, q)) - zb);     // t < t - d12
-    const int64_t *P = H.P;
-    const uint64_t ns = H.n_slots;
-    const uint64_t sb = H.slot[OL] - olo;   // P index of absolute position p in list OL: sb + p
-    const int64_t *PE = P + (uint64_t)(0 + C) * ns + sb;
-    const int64_t *PA = P + (uint64_t)(2 + C) * ns + sb;
-    const int64_t *PB = P + (uint64_t)(4 + C) * ns + sb;
-    const int64_t *PC = P + (uint64_t)(6 + C) * ns + sb;
-    // o[]: searches into the other list (absolute indices), shared by the C = 0, 1 calls
-    const uint32_t o_m12 = o[0], o_lt = o[1], o_mid = o[2], o_p12 = o[3], o_p23 = o[4],
-                   o_p13 = o[5], o_p1312 = o[6];
-    // Algorithm 1 (e = e2 on S2; S1 = other list, S3 = vw_C): pi1 when e is on uw, pi2 on uv
-    if (o_lt > o_m12) {
-        uint32_t lo1 = o_m12, hi1 = o_lt;
-        uint32_t mid = o_mid < lo1 ? lo1 : (o_mid > hi1 ? hi1 : o_mid);
-        int64_t c = (PE[mid] - PE[lo1]) - (int64_t)(mid - lo1) * r_lt +
-                    (int64_t)(hi1 - mid) * (r_d23 - r_lt);
-        if (kUv) acc.template add<Cell<2, DUV, DUW, C>>(c);
-        else acc.template add<Cell<1, DUV, DUW, C>>(c);
-    }
-    // Algorithm 2 (e = e1 on S1; S2 = vw_C, S3 = other list): pi3 when e is on uv, pi4 on uw
-    {
-        const bool d12_first = q.d12 <= q.d23;
-        uint32_t f = o_lt;
-        uint32_t x1 = d12_first ? o_p12 : o_p23;
-        uint32_t x2 = d12_first ? o_p23 : o_p12;
-        x1 = x1 < f ? f : x1;
-        x2 = x2 < x1 ? x1 : x2;
-        uint32_t x3 = o_p13 < x2 ? x2 : o_p13;
-        int64_t c = (PA[x1] - PA[f]) - (int64_t)(x1 - f) * r_lt;
-        if (d12_first) c += (int64_t)(x2 - x1) * (r_d12 - r_lt);
-        else c += (PA[x2] - PA[x1]) - (PB[x2] - PB[x1]);
-        c += (int64_t)(x3 - x2) * r_d12 - (PB[x3] - PB[x2]);
-        if (kUv) acc.template add<Cell<3, DUV, DUW, C>>(c);
-        else acc.template add<Cell<4, DUV, DUW, C>>(c);
-    }
-    // Algorithm 3 (e = e2 on S2; S3 = other list, S1 = vw_C): pi5 when e is on uv, pi6 on uw
-    {
-        uint32_t f = o_lt;
-        uint32_t s = o_p1312 < f ? f : o_p1312;
-        uint32_t e = o_p23 < s ? s : o_p23;
-        int64_t c = (int64_t)(s - f) * (r_lt - r_m12) + (int64_t)(e - s) * r_lt - (PC[e] - PC[s]);
-        if (kUv) acc.template add<Cell<5, DUV, DUW, C>>(c);
-        else acc.template add<Cell<6, DUV, DUW, C>>(c);
-    }
+// phase 2: the carries between the chunks of each list (a thread per chunk, the list's first works)
+__global__ void k_heavy_prefix_scan(HeavyArgs A, uint64_t pe) {
+    const uint64_t c = A.pb + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < pe) heavy_prefix_scan_list(A, c, pe);
 }
 
-template <bool CELLS, int X, int B>
-__device__ __forceinline__ void heavy_other(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
-                                            Acc<CELLS> &acc) {
-    constexpr int OL = X < 2 ? 2 + B : B;
-    const uint32_t ob = H.lo[OL], oe = H.hi[OL];
-    const uint64_t *key = H.key;
-    uint32_t o[8];
-    o[0] = lower(key, ob, oe, before_time(t - q.d12, q));              // t < t - d12
-    o[1] = lower(key, ob, oe, k);                                     // key < k
-    o[2] = lower(key, ob, oe, before_time(t - q.d13 + q.d23 + 1, q)); // t <= t - d13 + d23
-    o[3] = lower(key, ob, oe, before_time(t + q.d12 + 1, q));         // t <= t + d12
-    o[4] = lower(key, ob, oe, before_time(t + q.d23 + 1, q));         // t <= t + d23
-    o[5] = lower(key, ob, oe, before_time(t + q.d13 + 1, q));         // t <= t + d13
-    o[6] = lower(key, ob, oe, before_time(t + q.d13 - q.d12 + 1, q)); // t <= t + d13 - d12
-    o[7] = 0;
-    heavy_cell<CELLS, X, B, 0>(H, q, k, t, acc, o);
-    heavy_cell<CELLS, X, B, 1>(H, q, k, t, acc, o);
+// phase 3: every chunk adds its carry
+__global__ void __launch_bounds__(kPrefixBlock)
+k_heavy_prefix_add(HeavyArgs A, uint64_t pe) {
+    for (uint64_t c = A.pb + blockIdx.x; c < pe; c += gridDim.x) heavy_prefix_add_chunk(A, c);
 }
 
-template <bool CELLS, int X>
-__device__ __forceinline__ void heavy_elem(const HeavyCtx &H, const DQuery &q, uint32_t p,
-                                           Acc<CELLS> &acc) {
-    const uint64_t k = H.key[p];
-    const int64_t t = (int64_t)(k >> q.shift);
-    heavy_other<CELLS, X, 0>(H, q, k, t, acc);
-    heavy_other<CELLS, X, 1>(H, q, k, t, acc);
-}
-
+// the count pass: chunks [cb, ce) of 256 source edges (of the four lists in a row) each
 template <bool CELLS, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_heavy_count(uint64_t n_chunks, const uint32_t *__restrict__ chunks, const uint32_t *__restrict__ tri,
-              const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
-              const uint32_t *__restrict__ clip, const uint64_t *__restrict__ hslot,
-              uint64_t n_slots, const int64_t *__restrict__ P, DQuery q,
-              int64_t *__restrict__ partial, int64_t *__restrict__ cells) {
+k_heavy_count(HeavyArgs A, uint64_t cb, uint64_t ce, int64_t *__restrict__ partial, int64_t *__restrict__ cells,
+              unsigned long long *__restrict__ visits) {
     Acc<CELLS> acc;
     acc.cells = cells;
-    for (uint64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const uint32_t h = chunks[2 * ch], first = chunks[2 * ch + 1];
-        const uint32_t *t3 = tri + 3 * (uint64_t)h;
-        uint32_t beg[7];
-        full_lists(eoff, t3, beg);
-        const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
-        const uint32_t start_full[4] = {beg[0], beg[1], beg[3], beg[4]};
-        HeavyCtx H;
-        H.key = key;
-        H.P = P;
-        H.n_slots = n_slots;
-        uint64_t s = hslot[h];
-#pragma unroll
-        for (int Y = 0; Y < 4; ++Y) {
-            H.slot[Y] = s;
-            s += len_full[Y] + 1;
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            H.lo[i] = clip[12 * (uint64_t)h + 2 * i];
-            H.hi[i] = clip[12 * (uint64_t)h + 2 * i + 1];
-        }
-        uint32_t ei = first + threadIdx.x;
-        const uint32_t total = len_full[0] + len_full[1] + len_full[2] + len_full[3];
-        if (ei < total) {
-            int X = 0;
-            while (ei >= len_full[X]) {
-                ei -= len_full[X];
-                ++X;
-            }
-            const uint32_t p = start_full[X] + ei;
-            if (p >= H.lo[X] && p < H.hi[X]) {
-                switch (X) {
-                    case 0: heavy_elem<CELLS, 0>(H, q, p, acc); break;
-                    case 1: heavy_elem<CELLS, 1>(H, q, p, acc); break;
-                    case 2: heavy_elem<CELLS, 2>(H, q, p, acc); break;
-                    default: heavy_elem<CELLS, 3>(H, q, p, acc); break;
-                }
-            }
-        }
-    }
+    for (uint64_t ch = cb + blockIdx.x; ch < ce; ch += gridDim.x) heavy_count_chunk(A, ch, acc);
+    add_visits(visits, acc.visits);
     if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
 }
 
@@ -390,6 +170,7 @@ struct SweepQ {
     UQuery u[kSweepMax];
     uint32_t k;
     int64_t d13max;   // largest d13 of the k triples
+    uint32_t qlev;    // its level: the pass's medium / heavy split
 };
 
 // adds a sweep's contributions to one triple's eight LDS counters (of this wavefront)
@@ -539,7 +320,7 @@ k_light_sweep(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__rest
 template <unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_medium_sweep(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
-               const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, SweepQ Q,
+               const uint8_t *__restrict__ lev, const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key, SweepQ Q,
                int64_t *__restrict__ part, uint64_t slot0) {
     __shared__ unsigned long long s_sw[BLOCK / 64][kSweepMax * 8];
     for (unsigned x = threadIdx.x; x < (BLOCK / 64) * kSweepMax * 8; x += BLOCK) (&s_sw[0][0])[x] = 0;
@@ -548,8 +329,9 @@ k_medium_sweep(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__res
     const unsigned lane = threadIdx.x & 63;
     const uint64_t n_ent = R.pre[R.n];
     const uint64_t W = (uint64_t)gridDim.x * (BLOCK / 64);
-    DQuery qr = Q.q[0];   // the window, and the widest closeness
+    DQuery qr = Q.q[0];   // the window, the widest closeness and the pass's medium / heavy split
     qr.d13 = Q.d13max;
+    qr.qlev = Q.qlev;
     uint32_t r = 0;
     for (uint64_t b = ((uint64_t)blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) * 64; b < n_ent; b += W * 64) {
         const uint64_t x = b + lane;
@@ -561,7 +343,7 @@ k_medium_sweep(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__res
                                   medium_pair_any(combo, key, L, Q.q[j], k_uv, k_uw, a);
                               }
                           },
-                          lane);
+                          lane, lev);
     }
     sweep_flush<BLOCK>(s_sw, Q.k, part, slot0 + blockIdx.x);
 }
@@ -606,6 +388,7 @@ int normalise_query(const dt_graph *g, const dt_query *qq, DQuery *out, bool *em
     q.d13 = d13;
     q.d12 = d12;
     q.d23 = d23;
+    q.qlev = query_level(d13);
     q.span = span;
     q.shift = g->shift;
     *empty = (g->m == 0);
@@ -629,36 +412,92 @@ int normalise_query(const dt_graph *g, const dt_query *qq, DQuery *out, bool *em
     return DT_OK;
 }
 
+void medium_ranges(const dt_graph *g, const DQuery &q, Ranges &r, const uint8_t **lev) {
+    const Schedule &S = g->sched;
+    if (q.windowed) {
+        cell_ranges(S.mitem_cells, S.cell_shift, q, r);
+        *lev = S.mlev_w.as<uint8_t>();
+        return;
+    }
+    // whole span: the entries of the always-medium triangles and of the contested ones at or above
+    // the query's level, a prefix of the list
+    const uint64_t e = S.med_item_at[q.qlev < kLevels ? q.qlev : kLevels];
+    r.n = e ? 1 : 0;
+    r.pre[0] = 0;
+    if (e) {
+        r.b[0] = 0;
+        r.pre[1] = e;
+    }
+    *lev = nullptr;
+}
+
+void heavy_range(const dt_graph *g, const DQuery &q, HeavyRange &h) {
+    const Schedule &S = g->sched;
+    const uint32_t l = q.qlev < kLevels ? q.qlev : kLevels;
+    h.hb = S.heavy_tri_at[l];
+    h.cb = S.heavy_chunk_at[l];
+    h.pb = S.heavy_pchunk_at[l];
+    h.slot_base = S.heavy_slot_at[l];
+    h.n = S.n_heavy - h.hb;
+    h.scratch_bytes = h.n ? (S.n_slots - h.slot_base) * kVals * sizeof(int64_t) + 12 * 4 * h.n +
+                                (S.n_pchunks - h.pb) * kVals * sizeof(int64_t) + 512
+                          : 0;
+}
+
+void heavy_args(const dt_graph *g, const DQuery &q, const HeavyRange &hr, uint8_t *scratch, HeavyArgs &A) {
+    const Schedule &S = g->sched;
+    const uint64_t ns = S.n_slots - hr.slot_base, npc = S.n_pchunks - hr.pb;
+    A.heavy = S.heavy.as<uint32_t>();
+    A.pchunks = S.pchunks.as<uint32_t>();
+    A.chunks = S.chunks.as<uint32_t>();
+    A.eoff = g->eoff.as<uint32_t>();
+    A.key = g->key.as<uint64_t>();
+    A.hslot = S.hslot.as<uint64_t>();
+    A.hb = hr.hb;
+    A.pb = hr.pb;
+    A.slot_base = hr.slot_base;
+    A.ns = ns;
+    A.P = reinterpret_cast<int64_t *>(scratch);
+    A.T = A.P + ns * kVals;
+    A.clip = reinterpret_cast<uint32_t *>(A.T + npc * kVals);
+    A.q = q;
+}
+
 void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p) {
     const dt_ctx *ctx = g->ctx;
     const Schedule &S = g->sched;
     p.parts = parts;
     const bool do_light = parts & 1, do_medium = parts & 2, do_heavy = parts & 4;
-    // the parts of the light and medium lists a windowed query can see
+    // the parts of the light and medium lists the query sees (window cells; the medium / heavy
+    // split of its level)
     cell_ranges(S.light_cells, S.cell_shift, q, p.lr);
-    cell_ranges(S.mitem_cells, S.cell_shift, q, p.mr);
+    medium_ranges(g, q, p.mr, &p.mlev);
     const uint64_t nl = p.lr.pre[p.lr.n], nmi = p.mr.pre[p.mr.n];
     p.light = (q.windowed ? S.light_w : S.light).as<uint32_t>();
     p.medium = (q.windowed ? S.medium_w : S.medium).as<uint32_t>();
     p.mitems = (q.windowed ? S.mitems_w : S.mitems).as<uint32_t>();
+    const CountGeom &G = g->geom;
     const unsigned light_grid = (nl && do_light) ? (unsigned)std::min<uint64_t>(
-        (nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * 16) : 0;
+        (nl + kLightBlock - 1) / kLightBlock, (uint64_t)ctx->num_cus * G.light_bpc) : 0;
     p.lg = light_grid ? ((light_grid + 7) / 8) * 8 : 0;
-    p.hg = (S.n_chunks && do_heavy) ? (unsigned)std::min<uint64_t>(S.n_chunks, (uint64_t)ctx->num_cus * 16) : 0;
-    p.mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * 8) : 0;
+    heavy_range(g, q, p.hr);
+    if (!do_heavy) p.hr.n = 0;
+    p.hg = p.hr.n ? (unsigned)std::min<uint64_t>(S.n_chunks - p.hr.cb, (uint64_t)ctx->num_cus * 16) : 0;
+    p.mg = (nmi && do_medium) ? (unsigned)std::min<uint64_t>((nmi + 255) / 256, (uint64_t)ctx->num_cus * G.medium_bpc) : 0;
     p.ub = p.ue = 0;
     if (S.n_unit && (parts & 8)) unit_range(g, q, &p.ub, &p.ue);
     p.ug = p.ue > p.ub ? (unsigned)std::min<uint64_t>((p.ue - p.ub + kUnitPerBlock - 1) / kUnitPerBlock,
                                                       (uint64_t)ctx->num_cus * 8) : 0;
     p.n_part = (uint64_t)p.lg + p.hg + p.mg + p.ug;
     p.part_bytes = (p.n_part + 1) * 8 * sizeof(int64_t);
-    p.heavy_bytes = (S.n_heavy && do_heavy) ? S.n_slots * kVals * sizeof(int64_t) + 12 * 4 * S.n_heavy + 256 : 0;
+    p.heavy_bytes = p.hr.n ? p.hr.scratch_bytes : 0;
 }
 
 // Enqueue one planned count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the
-// 48 cells into cells_dev (zeroed here) instead.  The scratch must hold the plan's needs.
+// 48 cells into cells_dev (zeroed here) instead.  The scratch must hold the plan's needs.  With
+// visits, the kernels add the pairs and list elements they iterate over to *visits.
 int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
-                 int64_t *cells_dev, const ScratchView &sv) {
+                 int64_t *cells_dev, const ScratchView &sv, unsigned long long *visits) {
     dt_ctx *ctx = g->ctx;
     Schedule &S = g->sched;
     if (sv.part_bytes < p.part_bytes || sv.heavy_bytes < p.heavy_bytes)
@@ -671,14 +510,15 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
         k_zero<<<1, 64, 0, s>>>(48, cells_dev);
         DT_HIP(hipGetLastError());
     }
-    // The light and medium kernels are independent of the unit and heavy ones (each writes its own
-    // partial slots): when more than one path has work, they run on the context's side streams,
-    // forked from s here and joined back before the reduction, so their latency-bound tails overlap.
+    // The paths are independent (each writes its own partial slots): when more than one has work,
+    // the light and then the heavy kernels run on the context's first side stream and the medium
+    // kernel on the second, forked from s here and joined back before the reduction, beside the
+    // unit kernel on s, so that their latency-bound tails overlap.
     hipStream_t sl = s, sm = s;
-    const bool fork = ctx->side[0] && ((lg ? 1 : 0) + (mg ? 1 : 0) + ((ug || hg) ? 1 : 0)) >= 2;
+    const bool fork = ctx->side[0] && ((lg || hg ? 1 : 0) + (mg ? 1 : 0) + (ug ? 1 : 0)) >= 2;
     if (fork) {
         DT_HIP(hipEventRecord(ctx->ev_fork, s));
-        if (lg) {
+        if (lg || hg) {
             DT_HIP(hipStreamWaitEvent(ctx->side[0], ctx->ev_fork, 0));
             sl = ctx->side[0];
         }
@@ -687,27 +527,26 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
             sm = ctx->side[1];
         }
     }
+    const uint32_t *eoff = g->eoff.as<uint32_t>();
+    const uint64_t *key = g->key.as<uint64_t>();
     if (lg) {
         prof_begin(ctx, kProfLight, sl);
         if (cells)
-            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light,
-                g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, cells_dev);
+            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light, eoff, key, q, part, cells_dev, visits);
         else
-            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light,
-                g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, part, nullptr);
+            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light, eoff, key, q, part, nullptr, visits);
         prof_end(ctx, kProfLight, sl);
         DT_HIP(hipGetLastError());
     }
     if (mg) {
+        int64_t *mp = part + 8 * ((uint64_t)lg + hg);
         prof_begin(ctx, kProfMedium, sm);
         if (cells)
-            k_medium<true, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems,
-                g->eoff.as<uint32_t>(),
-                g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), cells_dev);
+            k_medium<true, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems, p.mlev, eoff, key, q, mp, cells_dev,
+                                                    visits);
         else
-            k_medium<false, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems,
-                g->eoff.as<uint32_t>(),
-                g->key.as<uint64_t>(), q, part + 8 * ((uint64_t)lg + hg), nullptr);
+            k_medium<false, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems, p.mlev, eoff, key, q, mp, nullptr,
+                                                     visits);
         prof_end(ctx, kProfMedium, sm);
         DT_HIP(hipGetLastError());
     }
@@ -716,45 +555,41 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
         int64_t *up = part + 8 * ((uint64_t)lg + hg + mg);
         prof_begin(ctx, kProfUnit, s);
         if (cells)
-            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, cells_dev);
+            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, cells_dev, visits);
         else
-            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, nullptr);
+            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, nullptr, visits);
         prof_end(ctx, kProfUnit, s);
         DT_HIP(hipGetLastError());
     }
-    if (p.heavy_bytes) {
-        int64_t *P = reinterpret_cast<int64_t *>(sv.heavy);
-        uint32_t *clip = reinterpret_cast<uint32_t *>(P + S.n_slots * kVals);
-        k_heavy_clip<<<grid_for(S.n_heavy, 256), 256, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
-            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), q, clip);
+    if (p.hr.n) {
+        const HeavyRange &hr = p.hr;
+        const uint64_t npc = S.n_pchunks - hr.pb;
+        HeavyArgs A;
+        heavy_args(g, q, hr, sv.heavy, A);
+        k_heavy_clip<<<grid_for(hr.n, 256), 256, 0, sl>>>(A, hr.n);
         DT_HIP(hipGetLastError());
-        prof_begin(ctx, kProfHeavyPrefix, s);
-        k_heavy_prefix<<<(unsigned)(4 * S.n_heavy), kPrefixBlock, 0, s>>>(S.n_heavy, S.heavy.as<uint32_t>(),
-            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip, S.hslot.as<uint64_t>(), S.n_slots, q, P);
-        prof_end(ctx, kProfHeavyPrefix, s);
+        const unsigned pgrid = (unsigned)std::min<uint64_t>(npc, (uint64_t)ctx->num_cus * 16);
+        prof_begin(ctx, kProfHeavyPrefix, sl);
+        k_heavy_prefix_local<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks, visits);
+        DT_HIP(hipGetLastError());
+        k_heavy_prefix_scan<<<grid_for(npc, 256), 256, 0, sl>>>(A, S.n_pchunks);
+        DT_HIP(hipGetLastError());
+        k_heavy_prefix_add<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks);
+        prof_end(ctx, kProfHeavyPrefix, sl);
         DT_HIP(hipGetLastError());
         const unsigned cb = g->tuning.heavy_chunk;
-        prof_begin(ctx, kProfHeavyCount, s);
-        if (cells) {
-            if (cb == 256)
-                k_heavy_count<true, 256><<<hg, 256, 0, s>>>(S.n_chunks, S.chunks.as<uint32_t>(),
-                    S.heavy.as<uint32_t>(), g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip,
-                    S.hslot.as<uint64_t>(), S.n_slots, P, q, part + 8 * (uint64_t)lg, cells_dev);
-            else
-                return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
-        } else {
-            if (cb == 256)
-                k_heavy_count<false, 256><<<hg, 256, 0, s>>>(S.n_chunks, S.chunks.as<uint32_t>(),
-                    S.heavy.as<uint32_t>(), g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), clip,
-                    S.hslot.as<uint64_t>(), S.n_slots, P, q, part + 8 * (uint64_t)lg, nullptr);
-            else
-                return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
-        }
-        prof_end(ctx, kProfHeavyCount, s);
+        if (cb != 256) return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
+        int64_t *hp = part + 8 * (uint64_t)lg;
+        prof_begin(ctx, kProfHeavyCount, sl);
+        if (cells)
+            k_heavy_count<true, 256><<<hg, 256, 0, sl>>>(A, hr.cb, S.n_chunks, hp, cells_dev, visits);
+        else
+            k_heavy_count<false, 256><<<hg, 256, 0, sl>>>(A, hr.cb, S.n_chunks, hp, nullptr, visits);
+        prof_end(ctx, kProfHeavyCount, sl);
         DT_HIP(hipGetLastError());
     }
     if (fork) {
-        if (lg) {
+        if (lg || hg) {
             DT_HIP(hipEventRecord(ctx->ev_join[0], sl));
             DT_HIP(hipStreamWaitEvent(s, ctx->ev_join[0], 0));
         }
@@ -774,7 +609,7 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
 
 // Plan one count, grow the scratch sc to its needs, and enqueue it on stream s.
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev, Scratch &sc, unsigned parts) {
+                  int64_t *cells_dev, Scratch &sc, unsigned parts, unsigned long long *visits) {
     CountPlan p;
     count_plan(g, q, parts, p);
     DT_TRY(ensure(g->ctx, sc.partials, p.part_bytes));
@@ -784,7 +619,7 @@ int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s
     sv.part_bytes = sc.partials.bytes;
     sv.heavy = sc.heavy_vals.as<uint8_t>();
     sv.heavy_bytes = p.heavy_bytes ? sc.heavy_vals.bytes : 0;
-    return count_launch(g, q, p, out8_dev, s, cells, cells_dev, sv);
+    return count_launch(g, q, p, out8_dev, s, cells, cells_dev, sv, visits);
 }
 
 void count_reduce(uint64_t n_part, const int64_t *part, int64_t *out8_dev, hipStream_t s) {
@@ -809,13 +644,27 @@ int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_
         Q.d13max = qs[j].d13 > Q.d13max ? qs[j].d13 : Q.d13max;
     }
     const DQuery &q0 = qs[0];   // the window (and so every range) is the same for all k
+    // one medium / heavy split for the whole pass: the level of the largest d13 (the medium pass
+    // finds close pairs at that distance for every triple)
+    uint32_t qlm = 0;
+    for (uint32_t j = 0; j < k; ++j) qlm = qs[j].qlev > qlm ? qs[j].qlev : qlm;
     // heavy triangles: one count per query, written to out_dev
-    const bool heavy = S.n_chunks > 0;
+    DQuery qh = q0;
+    qh.qlev = qlm;
+    HeavyRange hr;
+    heavy_range(g, qh, hr);
+    const bool heavy = hr.n > 0;
     if (heavy)
-        for (uint32_t j = 0; j < k; ++j) DT_TRY(count_enqueue(g, qs[j], out_dev + 8 * j, s, false, nullptr, sc, 4));
+        for (uint32_t j = 0; j < k; ++j) {
+            DQuery qq = qs[j];
+            qq.qlev = qlm;
+            DT_TRY(count_enqueue(g, qq, out_dev + 8 * j, s, false, nullptr, sc, 4));
+        }
+    Q.qlev = qlm;
     Ranges lr, mr;
+    const uint8_t *mlev = nullptr;
     cell_ranges(S.light_cells, S.cell_shift, q0, lr);
-    cell_ranges(S.mitem_cells, S.cell_shift, q0, mr);
+    medium_ranges(g, qh, mr, &mlev);
     const uint64_t nl = lr.pre[lr.n], nmi = mr.pre[mr.n];
     const uint32_t *light = (q0.windowed ? S.light_w : S.light).as<uint32_t>();
     const uint32_t *medium = (q0.windowed ? S.medium_w : S.medium).as<uint32_t>();
@@ -859,7 +708,7 @@ int count_sweep_enqueue(dt_graph *g, const DQuery *qs, uint32_t k, int64_t *out_
     }
     if (mg) {
         prof_begin(ctx, kProfMedium, sm);
-        k_medium_sweep<256><<<mg, 256, 0, sm>>>(mr, medium, mitems, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
+        k_medium_sweep<256><<<mg, 256, 0, sm>>>(mr, medium, mitems, mlev, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
                                                 Q, part, (uint64_t)ug + lgx);
         prof_end(ctx, kProfMedium, sm);
         DT_HIP(hipGetLastError());

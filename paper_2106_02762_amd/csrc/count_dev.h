@@ -40,9 +40,12 @@ template <int PI, int DUV, int DUW, int DVW> struct Cell {
 
 // accumulators: per-lane type counts, or (diagnostic) global atomics per cell
 template <bool CELLS> struct Acc;
+// `visits` counts the (uv edge, uw edge) pairs or list elements a lane iterated over (the work
+// measure of Theorem 1's bound; reported by the instrumented count).
 template <> struct Acc<false> {
     int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t *cells = nullptr;
+    uint64_t visits = 0;
     template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
         t[CA::type] += first ? v : 0;
         t[CB::type] += first ? 0 : v;
@@ -52,6 +55,7 @@ template <> struct Acc<false> {
 template <> struct Acc<true> {
     int64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t *cells = nullptr;
+    uint64_t visits = 0;
     template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
         if (v) atomicAdd((unsigned long long *)(cells + (first ? CA::cell : CB::cell)),
                          (unsigned long long)v);
@@ -71,9 +75,12 @@ __device__ __forceinline__ uint64_t range_at(const Ranges &R, uint32_t &r, uint6
 // ---------------------------------------------------------------------------------------------
 // searches on key-sorted lists
 // ---------------------------------------------------------------------------------------------
-// first index in [lo, hi) whose key is >= K (hi if none)
+// first index in [lo, hi) whose key is >= K (hi if none); the bounds 0 and ~0 (times before or
+// after the whole span, common at long deltas) need no search
 __device__ __forceinline__ uint32_t lower(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi,
                                           uint64_t K) {
+    if (K == 0) return lo;
+    if (K == ~0ull) return hi;
     uint32_t len = hi - lo;
     while (len > 0) {
         uint32_t half = len >> 1;
@@ -154,6 +161,7 @@ template <int A, int B, class ACC>
 __device__ __forceinline__ void light_pairs(const uint64_t *__restrict__ key, const Lists &L,
                                             const DQuery &q, ACC &acc) {
     const uint32_t xb = L.lo[A], xe = L.hi[A], yb = L.lo[2 + B], ye = L.hi[2 + B];
+    acc.visits += (uint64_t)(xe - xb) * (ye - yb);
     for (uint32_t ix = xb; ix < xe; ++ix) {
         const uint64_t kx = key[ix];
         for (uint32_t iy = yb; iy < ye; ++iy) {
@@ -228,13 +236,17 @@ __device__ __forceinline__ void lower2(const uint64_t *__restrict__ key, uint32_
 // with many close partners does not stall the others.  Every lane of the wavefront must call this.
 // Each pair goes to eval(direction combination 2 d_uv + d_uw, its {v,w} lists, uv key, uw key);
 // q gives the window and the d13 of the closeness test.
+// With lev (the windowed copies), an entry whose triangle's level is below q.qlev is skipped: that
+// triangle is counted by the prefix procedures for this query.  Returns the pairs this wavefront
+// evaluated (its share of the visits).
 template <class EVAL>
-__device__ __forceinline__ void medium_lanes_eval(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
-                                                  uint64_t e, bool active, const uint32_t *__restrict__ eoff,
-                                                  const uint64_t *__restrict__ key, const DQuery &q, EVAL &&eval,
-                                                  unsigned lane) {
+__device__ __forceinline__ uint32_t medium_lanes_eval(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+                                                      uint64_t e, bool active, const uint32_t *__restrict__ eoff,
+                                                      const uint64_t *__restrict__ key, const DQuery &q, EVAL &&eval,
+                                                      unsigned lane, const uint8_t *__restrict__ lev = nullptr) {
     uint64_t kx = 0;
     uint32_t lo0 = 0, c0 = 0, lo1 = 0, c1 = 0, zb0 = 0, ze0 = 0, zb1 = 0, ze1 = 0, flags = 0;
+    if (active && lev && lev[ent[2 * e]] < q.qlev) active = false;
     if (active) {
         const uint32_t t = ent[2 * e], j = ent[2 * e + 1];
         const uint32_t e_uv = med[3 * (uint64_t)t], e_uw = med[3 * (uint64_t)t + 1], e_vw = med[3 * (uint64_t)t + 2];
@@ -278,7 +290,7 @@ __device__ __forceinline__ void medium_lanes_eval(const uint32_t *__restrict__ m
     }
     const uint32_t excl = incl - c;
     const uint32_t total = __shfl(incl, 63, 64);
-    if (total == 0) return;
+    if (total == 0) return 0;
     const uint32_t kx_lo = (uint32_t)kx, kx_hi = (uint32_t)(kx >> 32);
     for (uint32_t base = 0; base < total; base += 64) {
         const uint32_t jp = base + lane;
@@ -305,6 +317,7 @@ __device__ __forceinline__ void medium_lanes_eval(const uint32_t *__restrict__ m
         const uint32_t d_uv = outer_uv ? x_dir : y_dir, d_uw = outer_uv ? y_dir : x_dir;
         eval(d_uv * 2 + d_uw, L, k_uv, k_uw);
     }
+    return total;
 }
 
 // one (uv, uw) pair of given direction combination for query q
@@ -319,17 +332,17 @@ __device__ __forceinline__ void medium_pair_any(int combo, const uint64_t *__res
     }
 }
 
-// the medium path for one query into accumulator acc
+// the medium path for one query into accumulator acc; returns the pairs the wavefront evaluated
 template <class ACC>
-__device__ __forceinline__ void medium_lanes(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
-                                             uint64_t e, bool active, const uint32_t *__restrict__ eoff,
-                                             const uint64_t *__restrict__ key, const DQuery &q, ACC &acc,
-                                             unsigned lane) {
-    medium_lanes_eval(med, ent, e, active, eoff, key, q,
-                      [&](int combo, const Lists &L, uint64_t k_uv, uint64_t k_uw) {
-                          medium_pair_any(combo, key, L, q, k_uv, k_uw, acc);
-                      },
-                      lane);
+__device__ __forceinline__ uint32_t medium_lanes(const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
+                                                 uint64_t e, bool active, const uint32_t *__restrict__ eoff,
+                                                 const uint64_t *__restrict__ key, const DQuery &q, ACC &acc,
+                                                 unsigned lane, const uint8_t *__restrict__ lev = nullptr) {
+    return medium_lanes_eval(med, ent, e, active, eoff, key, q,
+                             [&](int combo, const Lists &L, uint64_t k_uv, uint64_t k_uw) {
+                                 medium_pair_any(combo, key, L, q, k_uv, k_uw, acc);
+                             },
+                             lane, lev);
 }
 
 // light triangles: P <= light_pair_cap and at most kLightVw edges on {v,w}
@@ -448,6 +461,332 @@ __device__ __forceinline__ void block_store(const int64_t (&t)[8], int64_t *__re
     }
 }
 
+// add a lane's visits to *visits (when instrumented); every lane of the wavefront must call this
+__device__ __forceinline__ void add_visits(unsigned long long *visits, uint64_t v) {
+    if (!visits) return;
+    const unsigned long long s = wave_sum((unsigned long long)v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(visits, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// heavy path: the prefix-count procedures of Algorithms 1-3
+// ---------------------------------------------------------------------------------------------
+// A query counts the heavy triangles [hb, n_heavy) (those below its level come first in the list
+// order: the suffix is the query's share).  Its scratch indices are relative to that suffix:
+// clip[12 (h - hb) + .], prefix slots from hslot[h] - slot_base, chunk totals from the first
+// prefix chunk pb.
+struct HeavyArgs {
+    const uint32_t *heavy, *pchunks, *chunks, *eoff;
+    const uint64_t *key, *hslot;
+    uint64_t hb, pb, slot_base, ns;   // ns: prefix slots of the suffix (the stride of P's arrays)
+    int64_t *P, *T;                   // prefix arrays [kVals][ns]; chunk totals [chunk - pb][kVals]
+    uint32_t *clip;                   // clipped bounds of the six lists, 12 words per triangle
+    DQuery q;
+};
+
+// window-clipped bounds of the six lists of heavy triangle hb + hl
+__device__ __forceinline__ void heavy_clip_one(const HeavyArgs &A, uint64_t hl) {
+    const uint32_t *t3 = A.heavy + 3 * (A.hb + hl);
+    Lists L;
+    load_lists(A.eoff, t3[0], t3[1], t3[2], A.key, A.q, L);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        A.clip[12 * hl + 2 * i] = L.lo[i];
+        A.clip[12 * hl + 2 * i + 1] = L.hi[i];
+    }
+}
+
+// full (unclipped) start of the six lists, from the DAG edge offsets
+__device__ __forceinline__ void full_lists(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ t3,
+                                           uint32_t (&beg)[7]) {
+    // beg[i], beg[i+1] delimit list i for i = 0..3 (uv+, uv-, uw+, uw-)
+    beg[0] = eoff[2 * t3[0]];
+    beg[1] = eoff[2 * t3[0] + 1];
+    beg[2] = eoff[2 * t3[0] + 2];
+    beg[3] = eoff[2 * t3[1]];
+    beg[4] = eoff[2 * t3[1] + 1];
+    beg[5] = eoff[2 * t3[1] + 2];
+    beg[6] = 0;
+}
+
+// Prefix values per source edge (the cumulative edge counts of Algorithms 1-3), for
+// list X of heavy triangle h, against the two vw lists (c = 0, 1):
+//   E_c = #{z in vw_c : t_z <= t + d13}                  (Algorithm 1, prefix over S1)
+//   A_c = #{z in vw_c : key_z < key}                     (Algorithm 2, prefix over S3)
+//   B_c = #{z in vw_c : t_z < t - d23}                   (Algorithm 2, prefix over S3)
+//   C_c = #{z in vw_c : t_z < t - d13}                   (Algorithm 3, prefix over S3)
+// stored as exclusive prefix sums P_v[r] over the whole list X, r = 0..len(X), where an edge outside
+// the window contributes 0 (so P at a clipped position is the clipped list's prefix).
+constexpr unsigned kPrefixBlock = 256;
+constexpr int kVals = 8;   // E0, E1, A0, A1, B0, B1, C0, C1
+
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v, unsigned lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(v, o, 64);
+        if (lane >= (unsigned)o) v += y;
+    }
+    return v;
+}
+
+// A prefix chunk: up to kPrefixBlock consecutive edges of one list X of one heavy triangle,
+// pchunks[2 c] = h, pchunks[2 c + 1] = first | X (first, the chunk's offset in the list, is a
+// multiple of kPrefixBlock).  Decodes the chunk: its list's full start and length and its slot.
+struct PChunk {
+    uint32_t h, X, first, fs, len;
+    uint64_t slot;   // relative to slot_base
+};
+__device__ __forceinline__ PChunk pchunk_at(const uint32_t *__restrict__ pchunks, uint64_t c,
+                                            const uint32_t *__restrict__ heavy, const uint32_t *__restrict__ eoff,
+                                            const uint64_t *__restrict__ hslot, uint64_t slot_base) {
+    PChunk k;
+    k.h = pchunks[2 * c];
+    const uint32_t w = pchunks[2 * c + 1];
+    k.X = w & 3u;
+    k.first = w & ~(kPrefixBlock - 1);
+    uint32_t beg[7];
+    full_lists(eoff, heavy + 3 * (uint64_t)k.h, beg);
+    const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
+    const uint32_t start_full[4] = {beg[0], beg[1], beg[3], beg[4]};
+    k.fs = start_full[k.X];
+    k.len = len_full[k.X];
+    uint64_t slot = hslot[k.h] - slot_base;
+    for (uint32_t Y = 0; Y < k.X; ++Y) slot += len_full[Y] + 1;
+    k.slot = slot;
+    return k;
+}
+
+// Phase 1 of the prefix pass, one chunk c by the whole workgroup (kPrefixBlock threads): its edges'
+// eight values and their exclusive prefix within the chunk (into P) and the chunk's totals (into
+// T).  vis counts the edges inside the window.
+__device__ __forceinline__ void heavy_prefix_local_chunk(const HeavyArgs &A, uint64_t c, uint64_t &vis) {
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    __shared__ int64_t s_tot[kPrefixBlock / 64][kVals];
+    const DQuery &q = A.q;
+    const uint64_t *key = A.key;
+    const PChunk k = pchunk_at(A.pchunks, c, A.heavy, A.eoff, A.hslot, A.slot_base);
+    const uint64_t hl = k.h - A.hb;
+    const uint32_t lo = A.clip[12 * hl + 2 * k.X], hi = A.clip[12 * hl + 2 * k.X + 1];
+    const uint32_t z0 = A.clip[12 * hl + 8], z0e = A.clip[12 * hl + 9];
+    const uint32_t z1 = A.clip[12 * hl + 10], z1e = A.clip[12 * hl + 11];
+    const uint32_t r = k.first + threadIdx.x;
+    const uint32_t p = k.fs + r;
+    int64_t v[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r < k.len && p >= lo && p < hi) {
+        const uint64_t kk = key[p];
+        const int64_t t = (int64_t)(kk >> q.shift);
+        v[0] = lower(key, z0, z0e, before_time(t + q.d13 + 1, q)) - z0;
+        v[1] = lower(key, z1, z1e, before_time(t + q.d13 + 1, q)) - z1;
+        v[2] = lower(key, z0, z0e, kk) - z0;
+        v[3] = lower(key, z1, z1e, kk) - z1;
+        v[4] = lower(key, z0, z0e, before_time(t - q.d23, q)) - z0;
+        v[5] = lower(key, z1, z1e, before_time(t - q.d23, q)) - z1;
+        v[6] = lower(key, z0, z0e, before_time(t - q.d13, q)) - z0;
+        v[7] = lower(key, z1, z1e, before_time(t - q.d13, q)) - z1;
+        ++vis;
+    }
+    int64_t incl[kVals];
+#pragma unroll
+    for (int i = 0; i < kVals; ++i) incl[i] = wave_incl_scan((long long)v[i], lane);
+    if (lane == 63) {
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) s_tot[wave][i] = incl[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kVals; ++i) {
+        int64_t before = 0, total = 0;
+        for (unsigned w = 0; w < kPrefixBlock / 64; ++w) {
+            if (w < wave) before += s_tot[w][i];
+            total += s_tot[w][i];
+        }
+        if (r < k.len) A.P[(uint64_t)i * A.ns + k.slot + r] = before + incl[i] - v[i];
+        if (threadIdx.x == 0) A.T[(c - A.pb) * kVals + i] = total;
+    }
+    __syncthreads();
+}
+
+// Phase 2, one thread per prefix chunk c: a chunk that starts a list walks that list's chunks and
+// replaces their totals in T by the exclusive prefix of the totals (each chunk's carry), and writes
+// the list's totals at position len of its prefix arrays.
+__device__ __forceinline__ void heavy_prefix_scan_list(const HeavyArgs &A, uint64_t c, uint64_t pe) {
+    const PChunk k = pchunk_at(A.pchunks, c, A.heavy, A.eoff, A.hslot, A.slot_base);
+    if (k.first != 0) return;
+    const uint64_t nc = k.len ? (k.len + kPrefixBlock - 1) / kPrefixBlock : 1;
+    if (c + nc > pe) return;   // cannot happen: a list's chunks are consecutive
+    int64_t run[kVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint64_t j = c; j < c + nc; ++j) {
+        int64_t *t = A.T + (j - A.pb) * kVals;
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) {
+            const int64_t x = t[i];
+            t[i] = run[i];
+            run[i] += x;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kVals; ++i) A.P[(uint64_t)i * A.ns + k.slot + k.len] = run[i];
+}
+
+// Phase 3, one chunk c by the whole workgroup: adds its carry to its edges' prefix values.
+__device__ __forceinline__ void heavy_prefix_add_chunk(const HeavyArgs &A, uint64_t c) {
+    const PChunk k = pchunk_at(A.pchunks, c, A.heavy, A.eoff, A.hslot, A.slot_base);
+    const uint32_t r = k.first + threadIdx.x;
+    if (r < k.len && k.first > 0) {
+        const int64_t *t = A.T + (c - A.pb) * kVals;
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) A.P[(uint64_t)i * A.ns + k.slot + r] += t[i];
+    }
+}
+
+// One source edge e (key k, time t) on list X of heavy triangle h, as e2 of Algorithm 1, e1 of
+// Algorithm 2 and e2 of Algorithm 3, against both directions of the other source pair (b) and of
+// {v,w} (c).
+struct HeavyCtx {
+    const uint64_t *key;
+    const int64_t *P;
+    uint64_t n_slots;
+    uint64_t slot[4];          // first slot of the prefix arrays of lists 0..3
+    uint32_t fs[4];            // full start of lists 0..3 (P is indexed from there)
+    uint32_t lo[6], hi[6];     // clipped bounds
+};
+
+template <bool CELLS, int X, int B, int C>
+__device__ __forceinline__ void heavy_cell(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
+                                           Acc<CELLS> &acc, const uint32_t (&o)[8]) {
+    // element's pair: uv for X = 0, 1 and uw for X = 2, 3; direction a = X & 1
+    constexpr bool kUv = X < 2;
+    constexpr int a = X & 1;
+    constexpr int OL = kUv ? 2 + B : B;            // other source list
+    constexpr int DUV = kUv ? a : B, DUW = kUv ? B : a;
+    const uint32_t zb = H.lo[4 + C], ze = H.hi[4 + C];
+    // searches into the vw list of direction C
+    const uint64_t *key = H.key;
+    const int64_t r_lt = (int64_t)(lower(key, zb, ze, k) - zb);                          // key < k
+    const int64_t r_d23 = (int64_t)(lower(key, zb, ze, before_time(t + q.d23 + 1, q)) - zb); // t <= t + d23
+    const int64_t r_d12 = (int64_t)(lower(key, zb, ze, before_time(t + q.d12 + 1, q)) - zb); // t <= t + d12
+    const int64_t r_m12 = (int64_t)(lower(key, zb, ze, before_time(t - q.d12, q)) - zb);     // t < t - d12
+    const int64_t *P = H.P;
+    const uint64_t ns = H.n_slots;
+    const uint64_t sb = H.slot[OL] - H.fs[OL];   // P index of absolute position p in list OL: sb + p
+    const int64_t *PE = P + (uint64_t)(0 + C) * ns + sb;
+    const int64_t *PA = P + (uint64_t)(2 + C) * ns + sb;
+    const int64_t *PB = P + (uint64_t)(4 + C) * ns + sb;
+    const int64_t *PC = P + (uint64_t)(6 + C) * ns + sb;
+    // o[]: searches into the other list (absolute indices), shared by the C = 0, 1 calls
+    const uint32_t o_m12 = o[0], o_lt = o[1], o_mid = o[2], o_p12 = o[3], o_p23 = o[4],
+                   o_p13 = o[5], o_p1312 = o[6];
+    // Algorithm 1 (e = e2 on S2; S1 = other list, S3 = vw_C): pi1 when e is on uw, pi2 on uv
+    if (o_lt > o_m12) {
+        uint32_t lo1 = o_m12, hi1 = o_lt;
+        uint32_t mid = o_mid < lo1 ? lo1 : (o_mid > hi1 ? hi1 : o_mid);
+        int64_t c = (PE[mid] - PE[lo1]) - (int64_t)(mid - lo1) * r_lt +
+                    (int64_t)(hi1 - mid) * (r_d23 - r_lt);
+        if (kUv) acc.template add<Cell<2, DUV, DUW, C>>(c);
+        else acc.template add<Cell<1, DUV, DUW, C>>(c);
+    }
+    // Algorithm 2 (e = e1 on S1; S2 = vw_C, S3 = other list): pi3 when e is on uv, pi4 on uw
+    {
+        const bool d12_first = q.d12 <= q.d23;
+        uint32_t f = o_lt;
+        uint32_t x1 = d12_first ? o_p12 : o_p23;
+        uint32_t x2 = d12_first ? o_p23 : o_p12;
+        x1 = x1 < f ? f : x1;
+        x2 = x2 < x1 ? x1 : x2;
+        uint32_t x3 = o_p13 < x2 ? x2 : o_p13;
+        int64_t c = (PA[x1] - PA[f]) - (int64_t)(x1 - f) * r_lt;
+        if (d12_first) c += (int64_t)(x2 - x1) * (r_d12 - r_lt);
+        else c += (PA[x2] - PA[x1]) - (PB[x2] - PB[x1]);
+        c += (int64_t)(x3 - x2) * r_d12 - (PB[x3] - PB[x2]);
+        if (kUv) acc.template add<Cell<3, DUV, DUW, C>>(c);
+        else acc.template add<Cell<4, DUV, DUW, C>>(c);
+    }
+    // Algorithm 3 (e = e2 on S2; S3 = other list, S1 = vw_C): pi5 when e is on uv, pi6 on uw
+    {
+        uint32_t f = o_lt;
+        uint32_t s = o_p1312 < f ? f : o_p1312;
+        uint32_t e = o_p23 < s ? s : o_p23;
+        int64_t c = (int64_t)(s - f) * (r_lt - r_m12) + (int64_t)(e - s) * r_lt - (PC[e] - PC[s]);
+        if (kUv) acc.template add<Cell<5, DUV, DUW, C>>(c);
+        else acc.template add<Cell<6, DUV, DUW, C>>(c);
+    }
+}
+
+template <bool CELLS, int X, int B>
+__device__ __forceinline__ void heavy_other(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
+                                            Acc<CELLS> &acc) {
+    constexpr int OL = X < 2 ? 2 + B : B;
+    const uint32_t ob = H.lo[OL], oe = H.hi[OL];
+    const uint64_t *key = H.key;
+    uint32_t o[8];
+    o[0] = lower(key, ob, oe, before_time(t - q.d12, q));              // t < t - d12
+    o[1] = lower(key, ob, oe, k);                                     // key < k
+    o[2] = lower(key, ob, oe, before_time(t - q.d13 + q.d23 + 1, q)); // t <= t - d13 + d23
+    o[3] = lower(key, ob, oe, before_time(t + q.d12 + 1, q));         // t <= t + d12
+    o[4] = lower(key, ob, oe, before_time(t + q.d23 + 1, q));         // t <= t + d23
+    o[5] = lower(key, ob, oe, before_time(t + q.d13 + 1, q));         // t <= t + d13
+    o[6] = lower(key, ob, oe, before_time(t + q.d13 - q.d12 + 1, q)); // t <= t + d13 - d12
+    o[7] = 0;
+    heavy_cell<CELLS, X, B, 0>(H, q, k, t, acc, o);
+    heavy_cell<CELLS, X, B, 1>(H, q, k, t, acc, o);
+}
+
+template <bool CELLS, int X>
+__device__ __forceinline__ void heavy_elem(const HeavyCtx &H, const DQuery &q, uint32_t p,
+                                           Acc<CELLS> &acc) {
+    const uint64_t k = H.key[p];
+    const int64_t t = (int64_t)(k >> q.shift);
+    heavy_other<CELLS, X, 0>(H, q, k, t, acc);
+    heavy_other<CELLS, X, 1>(H, q, k, t, acc);
+}
+
+// The count pass for one chunk ch (256 source edges of the four lists in a row), one edge per
+// thread of a 256-thread workgroup, into acc.
+template <bool CELLS>
+__device__ __forceinline__ void heavy_count_chunk(const HeavyArgs &A, uint64_t ch, Acc<CELLS> &acc) {
+    const uint32_t h = A.chunks[2 * ch], first = A.chunks[2 * ch + 1];
+    const uint64_t hl = h - A.hb;
+    const uint32_t *t3 = A.heavy + 3 * (uint64_t)h;
+    uint32_t beg[7];
+    full_lists(A.eoff, t3, beg);
+    const uint32_t len_full[4] = {beg[1] - beg[0], beg[2] - beg[1], beg[4] - beg[3], beg[5] - beg[4]};
+    const uint32_t start_full[4] = {beg[0], beg[1], beg[3], beg[4]};
+    HeavyCtx H;
+    H.key = A.key;
+    H.P = A.P;
+    H.n_slots = A.ns;
+    uint64_t s = A.hslot[h] - A.slot_base;
+#pragma unroll
+    for (int Y = 0; Y < 4; ++Y) {
+        H.slot[Y] = s;
+        H.fs[Y] = start_full[Y];
+        s += len_full[Y] + 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        H.lo[i] = A.clip[12 * hl + 2 * i];
+        H.hi[i] = A.clip[12 * hl + 2 * i + 1];
+    }
+    uint32_t ei = first + threadIdx.x;
+    const uint32_t total = len_full[0] + len_full[1] + len_full[2] + len_full[3];
+    if (ei < total) {
+        int X = 0;
+        while (ei >= len_full[X]) {
+            ei -= len_full[X];
+            ++X;
+        }
+        const uint32_t p = start_full[X] + ei;
+        if (p >= H.lo[X] && p < H.hi[X]) {
+            ++acc.visits;
+            switch (X) {
+                case 0: heavy_elem<CELLS, 0>(H, A.q, p, acc); break;
+                case 1: heavy_elem<CELLS, 1>(H, A.q, p, acc); break;
+                case 2: heavy_elem<CELLS, 2>(H, A.q, p, acc); break;
+                default: heavy_elem<CELLS, 3>(H, A.q, p, acc); break;
+            }
+        }
+    }
+}
 
 }  // namespace cdev
 }  // namespace dt

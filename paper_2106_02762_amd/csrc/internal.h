@@ -72,6 +72,11 @@ struct Scratch {
     DevMem partials, heavy_vals, sweep_partials;
 };
 struct BatchRunner;
+// item lengths of the batched launch: light triangles and medium entries per table item (unit
+// records: four times the light length)
+struct BatchTune {
+    uint32_t light_chunk = 8192, medium_group = 1024;
+};
 }  // namespace dt
 
 struct dt_ctx {
@@ -84,7 +89,7 @@ struct dt_ctx {
     dt::Scratch scratch;
     dt::DevMem out8;
     dt::BatchRunner *batch = nullptr;        // dt_count_batch's runner (created on first use)
-    uint32_t batch_light_chunk = 0;          // autotuned on first use (0 = not yet)
+    dt::BatchTune batch_tune;                // item lengths of the last batch (autotuned per size class)
     int64_t *pinned_out = nullptr;       // 64 int64 of pinned host memory for results
     uint8_t *pinned_stage = nullptr;     // kPinnedStage bytes of pinned host memory for a build's read-backs
     hipEvent_t ev_a = nullptr, ev_b = nullptr;   // order foreign streams around the scratch
@@ -130,7 +135,23 @@ struct DQuery {
     int64_t span;            // t_max - t_min (relative times lie in [0, span])
     int shift;               // key = (t - t_min) << shift | input index
     int windowed;            // 0: klo = 0, khi = ~0
+    uint32_t qlev;           // level of d13 (query_level): contested triangles of a lower level take
+                             // the prefix procedures, the others the pairwise medium path
 };
+
+// Levels of the medium / heavy split.  A contested triangle's level l (1..31) says that its close
+// pairs within D(l) = 2^(l-1) - 1 of each other fit its pair budget (the medium path's cost stays
+// below the prefix procedures'); level 0: never, kLevelAlways: every query.  A query takes a
+// contested triangle on the medium path iff its level is at least query_level(d13), the smallest
+// l with D(l) >= d13 (32 when none).
+constexpr uint32_t kLevels = 32;
+constexpr uint8_t kLevelAlways = 255;
+__host__ __device__ inline int64_t level_delta(uint32_t l) { return l == 0 ? -1 : (int64_t(1) << (l - 1)) - 1; }
+__host__ __device__ inline uint32_t query_level(int64_t d13) {
+    uint32_t l = 1;
+    while (l < kLevels && level_delta(l) < d13) ++l;
+    return l;
+}
 
 // Unit triangles: static triangles with exactly one temporal edge on each of their three pairs
 // (the common case in sparse interaction data).  Their ordering pi (Figure 3) and orientation rho
@@ -161,8 +182,13 @@ struct Ranges {
 // ------------------------------------------------------------------------------------------------
 // build products of one graph (all device arrays unless noted)
 // ------------------------------------------------------------------------------------------------
+// The medium list holds the always-medium triangles first, then the contested ones by descending
+// level; the heavy list the contested ones in that same order, then the always-heavy ones.  So a
+// whole-span query at level l walks a prefix of the medium list and a suffix of the heavy list,
+// whose bounds the host keeps per level.
 struct Schedule {
     uint64_t n_light = 0, n_medium = 0, n_heavy = 0, n_unit = 0;
+    uint64_t n_always_medium = 0, n_contested = 0, n_always_heavy = 0;
     DevMem unit;                        // uint4[n_unit] unit-triangle records
     int unit_shift = 0;                 // t1 bucket of a record: t1 >> unit_shift
     std::vector<uint32_t> unit_index;   // host: first record of each t1 bucket, then n_unit
@@ -181,7 +207,19 @@ struct Schedule {
     uint64_t n_slots = 0;
     DevMem chunks;      // uint32[2 * n_chunks]: (heavy triangle, first element) per work item
     uint64_t n_chunks = 0;
-    DevMem lists;       // uint32[4 * n_heavy]: heavy triangle, list id pairs for the prefix pass
+    DevMem pchunks;     // uint32[2 * n_pchunks]: (heavy triangle, first | list) per prefix chunk
+    uint64_t n_pchunks = 0;
+    DevMem mlev_w;      // uint8[n_medium]: level of each triangle of medium_w
+    // per query level l = 1..kLevels (entry 0 unused): first medium entry not walked by a whole-span
+    // query; first heavy triangle, count chunk, prefix chunk and prefix slot it counts
+    uint64_t med_item_at[kLevels + 1] = {}, heavy_tri_at[kLevels + 1] = {}, heavy_chunk_at[kLevels + 1] = {},
+             heavy_pchunk_at[kLevels + 1] = {}, heavy_slot_at[kLevels + 1] = {};
+};
+
+// Per-graph count geometry (blocks per compute unit of the light and medium kernels), chosen by the
+// autotuner or the defaults.
+struct CountGeom {
+    uint32_t light_bpc = 16, medium_bpc = 8;
 };
 
 }  // namespace dt
@@ -219,11 +257,25 @@ struct dt_graph {
     uint64_t alg_bytes_unit = 0;
     uint64_t tri_candidates = 0;
     dt::Schedule sched;
-    dt_tuning tuning{4, 256, 1u << 27, 0, 0, 0};
+    dt::CountGeom geom;
+    // the user's tuning (zero fields: automatic) and the values the last build used
+    dt_tuning tuning{0, 256, 1u << 27, 0, 0, 0, 0, 0};
+    uint32_t light_cap_used = 0, cost_pct_used = 0;
+    int tuned = 0;              // 1: the build's split and geometry came from the autotuner
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
 };
 
 namespace dt {
+
+// the autotuner's choices for one size class of graphs on one device (tune.hip)
+struct TunedCount {
+    uint32_t light_cap = 4, cost_pct = 100, light_bpc = 16, medium_bpc = 8;
+};
+bool tuned_lookup(const dt_graph *g, TunedCount *t);
+// times candidate splits and geometries of g's count (building a schedule from tri for each),
+// caches the best for g's size class and leaves g's split and geometry set to it (the schedule
+// must be built again)
+int autotune_count(dt_graph *g, DevMem &tri, TunedCount *out);
 
 // build phases (each returns a DT_* code)
 int load_graph(dt_graph *g, const uint32_t *src_dev, const uint32_t *dst_dev, const int64_t *t_dev);
@@ -257,9 +309,26 @@ struct ScratchView {
     uint8_t *heavy = nullptr;
     size_t heavy_bytes = 0;
 };
+// The heavy triangles a query counts: [hb, hb + n) of the heavy list, their count chunks from cb,
+// prefix chunks from pb and prefix slots from slot_base; scratch_bytes of prefix arrays, chunk
+// totals and clipped bounds.
+struct HeavyRange {
+    uint64_t hb = 0, n = 0, cb = 0, pb = 0, slot_base = 0;
+    size_t scratch_bytes = 0;
+};
+void heavy_range(const dt_graph *g, const DQuery &q, HeavyRange &h);
+namespace cdev { struct HeavyArgs; }
+using cdev::HeavyArgs;
+// the arguments of a query's heavy kernels over the range hr, with its scratch at `scratch`
+void heavy_args(const dt_graph *g, const DQuery &q, const HeavyRange &hr, uint8_t *scratch, HeavyArgs &A);
+// The medium entries a query walks (whole span: a prefix by its level; windowed: the window cells,
+// with *lev the per-triangle levels to check).
+void medium_ranges(const dt_graph *g, const DQuery &q, Ranges &r, const uint8_t **lev);
 // Launch geometry of one count and the scratch it needs (count_plan, host only).
 struct CountPlan {
     Ranges lr, mr;                               // light triangles and medium entries the query sees
+    const uint8_t *mlev = nullptr;               // levels of the windowed medium copy (or null)
+    HeavyRange hr;
     const uint32_t *light = nullptr, *medium = nullptr, *mitems = nullptr;
     unsigned lg = 0, hg = 0, mg = 0, ug = 0;     // grids of the light, heavy, medium and unit kernels
     uint64_t ub = 0, ue = 0;                     // unit records [ub, ue)
@@ -270,12 +339,12 @@ struct CountPlan {
 void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p);
 // Enqueue a planned count on stream s with scratch sv (which must hold the plan's needs).
 int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
-                 int64_t *cells_dev, const ScratchView &sv);
+                 int64_t *cells_dev, const ScratchView &sv, unsigned long long *visits = nullptr);
 // Enqueue one count on stream s using scratch sc (grown as needed).  parts: bit 0 light, bit 1 medium, bit 2 heavy,
 // bit 3 unit (all = 15).  Without cells the sum of the selected parts goes to out8_dev (int64[8]); with cells
 // the 48 cells are accumulated into cells_dev (zeroed here).
 int count_enqueue(dt_graph *g, const DQuery &q, int64_t *out8_dev, hipStream_t s, bool cells,
-                  int64_t *cells_dev, Scratch &sc, unsigned parts = 15);
+                  int64_t *cells_dev, Scratch &sc, unsigned parts = 15, unsigned long long *visits = nullptr);
 // The no-allocation count's scratch: noalloc_init takes the current device's address of it (once
 // per device, from the context's setup); noalloc_capacity is its size in bytes.
 int noalloc_init(int device);
@@ -291,7 +360,11 @@ void destroy_batch_runner(BatchRunner *r);
 int make_batch_runner(dt_ctx *ctx, BatchRunner **out);
 // plan the item table of k queries and enqueue it on the runner's stream (asynchronous)
 int batch_plan_and_launch(BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs,
-                          const bool *empty, uint32_t light_chunk);
+                          const bool *empty, const BatchTune &bt);
+// the item lengths for this batch's size class on this device: cached, or timed on this batch with
+// runner r (whose stream must be idle) and cached
+int batch_tuned(dt_ctx *ctx, BatchRunner *r, uint64_t k, dt_graph *const *graphs, const DQuery *qs,
+                const bool *empty, BatchTune *out);
 int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]);
 bool batch_ready(BatchRunner *r);
 int batch_sync(BatchRunner *r);

@@ -20,11 +20,12 @@ uint64_t graph_device_bytes(const dt_graph *g) {
                           &g->pstart, &g->c1, &g->core, &g->rank, &g->order, &g->dag_row, &g->dag_col,
                           &g->eoff, &g->key, &g->sched.light, &g->sched.medium, &g->sched.mitems,
                           &g->sched.light_w, &g->sched.medium_w, &g->sched.mitems_w, &g->sched.heavy,
-                          &g->sched.hslot, &g->sched.chunks, &g->sched.unit};
+                          &g->sched.hslot, &g->sched.chunks, &g->sched.pchunks, &g->sched.mlev_w,
+                          &g->sched.unit};
     uint64_t b = 0;
     for (const DevMem *m : ms) b += m->bytes;
     // scratch of the heavy path, taken per query in flight
-    b += g->sched.n_slots * 8 * sizeof(int64_t);
+    b += g->sched.n_slots * 8 * sizeof(int64_t) + g->sched.n_pchunks * 8 * sizeof(int64_t) + 48 * g->sched.n_heavy;
     return b;
 }
 
@@ -146,8 +147,11 @@ void worker_main(dt_server *s) {
                 for (size_t i = 0; i < k; ++i) sl.empty[i] = s->tickets[sl.tickets[i]].empty;
                 sl.busy = true;
                 lk.unlock();
-                int rc = batch_plan_and_launch(sl.runner, k, sl.graphs.data(), sl.qs.data(), sl.empty.get(),
-                                               s->ctx->batch_light_chunk ? s->ctx->batch_light_chunk : 8192);
+                // item lengths for this batch's size class: cached, or tuned now on this batch
+                BatchTune bt;
+                int rc = batch_tuned(s->ctx, sl.runner, k, sl.graphs.data(), sl.qs.data(), sl.empty.get(), &bt);
+                if (rc == DT_OK)
+                    rc = batch_plan_and_launch(sl.runner, k, sl.graphs.data(), sl.qs.data(), sl.empty.get(), bt);
                 lk.lock();
                 if (rc != DT_OK) {
                     for (uint64_t id : sl.tickets) {

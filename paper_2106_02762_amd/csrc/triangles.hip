@@ -483,7 +483,7 @@ int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, u
     fa.q = q;
     fa.u = cdev::unit_query(q);
     fa.unit_ok = g->span <= kUnitMaxSpan ? 1u : 0u;
-    fa.cap_l = g->tuning.light_pair_cap;
+    fa.cap_l = g->light_cap_used ? g->light_cap_used : 4;
     fa.shift = g->shift;
     fa.part = part.as<int64_t>();
     // the rest list: sized at an eighth of the static pairs, the pass runs again when it overflows

@@ -30,10 +30,10 @@ INT64_MIN = -(1 << 63)
 ENTRY_POINTS = (
     "dt_strerror", "dt_last_error", "dt_ctx_create", "dt_ctx_destroy", "dt_ctx_memory",
     "dt_graph_load", "dt_graph_load_device", "dt_graph_build", "dt_graph_set_tuning",
-    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_noalloc", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
+    "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_noalloc", "dt_count_visits", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
     "dt_graph_order", "dt_graph_triangles", "dt_graph_free", "dt_server_start",
     "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stop",
-    "dt_ctx_set_profiling", "dt_ctx_last_profile",
+    "dt_ctx_set_profiling", "dt_ctx_last_profile", "dt_ctx_batch_tuning",
 )
 PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
                  "heavy_count", "reduce", "medium", "unit", "peel_adj", "peel_tail", "core")
@@ -67,13 +67,18 @@ class dt_stats(ctypes.Structure):
         ("ms_load", ctypes.c_double), ("ms_peel", ctypes.c_double),
         ("ms_orient", ctypes.c_double), ("ms_triangles", ctypes.c_double),
         ("ms_schedule", ctypes.c_double),
+        ("n_contested_triangles", ctypes.c_uint64),
+        ("light_pair_cap_used", ctypes.c_uint32), ("medium_cost_pct_used", ctypes.c_uint32),
+        ("light_blocks_per_cu", ctypes.c_uint32), ("medium_blocks_per_cu", ctypes.c_uint32),
+        ("autotuned", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
     ]
 
 
 class dt_tuning(ctypes.Structure):
     _fields_ = [("light_pair_cap", ctypes.c_uint32), ("heavy_chunk", ctypes.c_uint32),
                 ("medium_pair_cap", ctypes.c_uint32), ("force_path", ctypes.c_uint32),
-                ("peel_tail", ctypes.c_uint32), ("order_method", ctypes.c_uint32)]
+                ("peel_tail", ctypes.c_uint32), ("order_method", ctypes.c_uint32),
+                ("medium_cost_pct", ctypes.c_uint32), ("autotune", ctypes.c_uint32)]
 
 
 class dt_server_cfg(ctypes.Structure):
@@ -115,6 +120,7 @@ def library():
         "dt_count": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_async": (I, [P, ctypes.POINTER(dt_query), P, P]),
         "dt_count_noalloc": (I, [P, ctypes.POINTER(dt_query), P, P]),
+        "dt_count_visits": (I, [P, ctypes.POINTER(dt_query), P, ctypes.POINTER(U64)]),
         "dt_count_cells": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_oneshot": (I, [P, ctypes.POINTER(dt_query), P]),
         "dt_count_sweep": (I, [P, U64, P, P]),
@@ -129,6 +135,7 @@ def library():
         "dt_server_stop": (I, [P]),
         "dt_ctx_set_profiling": (I, [P, I]),
         "dt_ctx_last_profile": (I, [P, P]),
+        "dt_ctx_batch_tuning": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -215,12 +222,14 @@ def dt_graph_build(g):
 
 
 def dt_graph_set_tuning(g, light_pair_cap=0, heavy_chunk=0, medium_pair_cap=0, force_path=0,
-                        peel_tail=0, order_method=0):
-    """force_path: 0 unit records and the caps, 1 all light, 2 all heavy, 3 all medium.
+                        peel_tail=0, order_method=0, medium_cost_pct=0, autotune=0):
+    """force_path: 0 unit records and the split, 1 all light, 2 all heavy, 3 all medium.
     peel_tail: vertices the level peel leaves to one workgroup (next build; 0 keeps the setting).
-    order_method: 0 the level-by-level peel, 1 h-index core numbers and shell rounds."""
+    order_method: 0 the level-by-level peel, 1 h-index core numbers and shell rounds.
+    medium_cost_pct: weight of the prefix procedures' cost in the medium / heavy split (percent).
+    autotune: 0 tune per size class when not cached, 1 never, 2 tune again now."""
     tu = dt_tuning(int(light_pair_cap), int(heavy_chunk), int(medium_pair_cap), int(force_path),
-                   int(peel_tail), int(order_method))
+                   int(peel_tail), int(order_method), int(medium_cost_pct), int(autotune))
     _check(library().dt_graph_set_tuning(g, ctypes.byref(tu)), "dt_graph_set_tuning")
 
 
@@ -244,6 +253,15 @@ def dt_count_async(g, query, out8_ptr, stream_ptr=None):
     _check(library().dt_count_async(g, ctypes.byref(query), ctypes.c_void_p(int(out8_ptr)),
                                     ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None),
            "dt_count_async")
+
+
+def dt_count_visits(g, d13, d12, d23, t_lo=INT64_MIN, t_hi=DT_INF):
+    """The count with instrumented kernels: (int64[8] counts, visits)."""
+    q = make_query(d13, d12, d23, t_lo, t_hi)
+    out = np.zeros(8, dtype=np.int64)
+    v = ctypes.c_uint64()
+    _check(library().dt_count_visits(g, ctypes.byref(q), out.ctypes.data, ctypes.byref(v)), "dt_count_visits")
+    return out, v.value
 
 
 def dt_count_noalloc(g, query, out8_ptr, stream_ptr=None):
@@ -304,6 +322,13 @@ def dt_graph_triangles(g):
 
 def dt_graph_free(g):
     _check(library().dt_graph_free(g), "dt_graph_free")
+
+
+def dt_ctx_batch_tuning(ctx):
+    """(light triangles, medium entries) per item of the context's last batched launch."""
+    out = np.zeros(2, dtype=np.uint32)
+    _check(library().dt_ctx_batch_tuning(ctx, out.ctypes.data), "dt_ctx_batch_tuning")
+    return int(out[0]), int(out[1])
 
 
 def dt_ctx_set_profiling(ctx, enable=True):

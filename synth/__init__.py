@@ -16,4 +16,6 @@ from .graphs import (  # noqa: F401
     served_stream,
     delta_triple_like_batch,
     clique_graph,
+    contested_graph,
+    long_lists_graph,
 )

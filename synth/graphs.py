@@ -382,3 +382,58 @@ def clique_graph(k: int, seed: int, multi_frac: float = 0.02, max_mult: int = 5,
     t = rng.integers(0, t_range, src.shape[0]).astype(np.int64)
     perm = rng.permutation(src.shape[0])
     return TemporalGraph(k + noise_n, src[perm], dst[perm], t[perm], name=f"clique{k}(seed={seed})")
+
+
+def contested_graph(seed: int, n_tri: int = 60, n: int = 400, span: int = 10**6, noise_m: int = 3000):
+    """Triangles whose pairs carry many temporal edges in bursts, so that the number of edge pairs
+    within d13 of each other grows from almost none to all of them across the deltas of a sweep:
+    the shape where the medium path and the prefix procedures trade places.  Each of n_tri random
+    triangles gets, per pair, a multiplicity from {1, 2, 7, 40, 150, 600} and its edges in the
+    triangle's 1-4 sessions (uniform starts over the span shared by its three pairs, Exp(30) gaps);
+    plus noise_m single edges between random nodes.  Directions uniform; the input is sorted by
+    time with random tie order."""
+    rng = np.random.default_rng([SEED_BASE + 6, seed])
+    mults = np.array([1, 2, 7, 40, 150, 600])
+    src, dst, ts = [], [], []
+    for _ in range(n_tri):
+        a, b, c = rng.choice(n, 3, replace=False)
+        sess = int(rng.integers(1, 5))
+        starts = rng.integers(0, span, sess)
+        for (x, y) in ((a, b), (a, c), (b, c)):
+            k = int(rng.choice(mults))
+            which = rng.integers(0, sess, k)
+            t = starts[which] + np.floor(rng.exponential(30.0, k)).astype(np.int64)
+            flip = rng.random(k) < 0.5
+            src.append(np.where(flip, y, x))
+            dst.append(np.where(flip, x, y))
+            ts.append(np.minimum(t, span))
+    a = rng.integers(0, n, noise_m)
+    b = rng.integers(0, n, noise_m)
+    ok = a != b
+    src.append(a[ok])
+    dst.append(b[ok])
+    ts.append(rng.integers(0, span, int(ok.sum())))
+    src = np.concatenate(src).astype(np.uint32)
+    dst = np.concatenate(dst).astype(np.uint32)
+    t = np.concatenate(ts).astype(np.int64)
+    src, dst, t = _time_sorted(rng, src, dst, t)
+    return TemporalGraph(n, src, dst, t, name=f"contested(seed={seed})")
+
+
+def long_lists_graph(seed: int, sizes=(5000, 3000, 700), t_range: int = 40000):
+    """One triangle {0, 1, 2} whose pairs carry sizes[0], sizes[1], sizes[2] temporal edges (many
+    prefix chunks per list, many equal timestamps), plus a pendant triangle {2, 3, 4} with 1, 2
+    and 3 edges; t uniform over {0..t_range-1}, directions uniform."""
+    rng = np.random.default_rng([SEED_BASE + 7, seed])
+    pairs = [(0, 1), (0, 2), (1, 2), (2, 3), (3, 4), (2, 4)]
+    ks = list(sizes) + [1, 2, 3]
+    src, dst = [], []
+    for (x, y), k in zip(pairs, ks):
+        flip = rng.random(k) < 0.5
+        src.append(np.where(flip, y, x))
+        dst.append(np.where(flip, x, y))
+    src = np.concatenate(src).astype(np.uint32)
+    dst = np.concatenate(dst).astype(np.uint32)
+    t = rng.integers(0, t_range, src.shape[0]).astype(np.int64)
+    perm = rng.permutation(src.shape[0])
+    return TemporalGraph(5, src[perm], dst[perm], t[perm], name=f"long_lists(seed={seed})")
