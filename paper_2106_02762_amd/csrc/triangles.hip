@@ -6,8 +6,13 @@
 // shorter and binary-searching the longer (hub vertices late in the ordering have long N+(v)
 // runs reached from many u).  The candidates of all v are spread over the 64 lanes through a
 // prefix sum of those walk lengths; a hit yields the DAG edge ids of {u, w} and {v, w} directly.
-// When the walk over N+(u) is long (kStage entries or more) the longer run N+(v) is first copied
-// into LDS, so those searches (most of them on power-law graphs) never touch global memory.
+// Searches into N+(v) (when it is the longer run) take a rank-window bitmap of N+(v) instead, when
+// v has one: before the pass, every vertex whose N+(v) has at least kBmMin heads within a window
+// of kBmWin ranks gets its heads as bits over that window, each 32-bit word stored with the number
+// of heads before it, so a membership test and the head's position in N+(v) are one 8-byte load
+// (a hub's bitmap is read by all its in-neighbours and stays in cache).  Without a bitmap, a long
+// walk over N+(u) (kStage entries or more) copies N+(v) into LDS and searches it there, a short
+// one searches N+(v) in global memory.
 //
 // Waves take source vertices from the highest rank down, so the heaviest (the dense core, last in
 // the ordering) start first.  One pass writes the list: each wavefront buffers its triangles in
@@ -38,6 +43,95 @@ constexpr uint32_t kChunk = 16;
 constexpr uint32_t kOut = 192;    // triangles a wavefront buffers in LDS before appending them
 constexpr int kBatchBuild = 4;    // blocks of 64 flattened candidates a lane works on at once
 constexpr int kBatchFused = 1;    // (one in the one-shot pass: its counting holds the registers)
+constexpr uint32_t kBmMin = 16;      // heads of N+(v) at least for a bitmap
+constexpr uint32_t kBmWin = 16384;   // ranks a bitmap spans at most (512 words)
+constexpr uint32_t kBmWords = kBmWin / 32;
+constexpr uint64_t kBmBudgetSlots = 1ull << 27;   // bitmap words of one graph at most (1 GiB)
+
+// Bitmap of N+(v): info = (first head, words, slot base low, slot base high); words = 0: none.
+// Slot x holds (heads before word x) << 32 | word x.  Returns whether w is a head of v and its
+// position in N+(v).
+__device__ __forceinline__ bool bm_find(const uint4 info, const uint64_t *__restrict__ slots, uint32_t w,
+                                        uint32_t &pos) {
+    const uint32_t off = w - info.x;   // wraps when w precedes the window
+    if (off >= info.y * 32u) return false;
+    const uint64_t slot = slots[((uint64_t)info.w << 32 | info.z) + (off >> 5)];
+    const uint32_t word = (uint32_t)slot, bit = off & 31u;
+    pos = (uint32_t)(slot >> 32) + (uint32_t)__popc(word & ((1u << bit) - 1u));
+    return (word >> bit) & 1u;
+}
+
+// words of the bitmap of every vertex (0: none)
+__global__ void k_bm_sizes(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
+                           uint64_t *__restrict__ words) {
+    const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t vb = dag_row[v], outv = dag_row[v + 1] - vb;
+    uint64_t nw = 0;
+    if (outv >= kBmMin) {
+        const uint32_t win = dag_col[vb + outv - 1] - dag_col[vb] + 1;
+        if (win <= kBmWin) nw = (win + 31) / 32;
+    }
+    words[v] = nw;
+}
+
+// the info of every vertex (slot bases from the exclusive scan of the words; none when off)
+__global__ void k_bm_info(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
+                          const uint64_t *__restrict__ words, const uint64_t *__restrict__ base, int on,
+                          uint4 *__restrict__ info) {
+    const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t nw = on ? (uint32_t)words[v] : 0u;
+    const uint64_t b = base[v];
+    info[v] = make_uint4(nw ? dag_col[dag_row[v]] : 0u, nw, (uint32_t)b, (uint32_t)(b >> 32));
+}
+
+// the slots of every bitmap: one wavefront per vertex builds its words in LDS, then their prefix
+// popcounts (lane l owns words [8 l, 8 l + 8))
+__global__ void __launch_bounds__(256)
+k_bm_fill(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
+          const uint4 *__restrict__ info, uint64_t *__restrict__ slots) {
+    __shared__ uint32_t s_bm[4][kBmWords];
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    uint32_t *bm = s_bm[wave];
+    const uint32_t nw_all = gridDim.x * 4;
+    for (uint32_t v = blockIdx.x * 4 + wave; v < n; v += nw_all) {
+        const uint4 in = info[v];
+        if (in.y == 0) continue;
+        const uint32_t vb = dag_row[v], outv = dag_row[v + 1] - vb;
+        for (uint32_t x = lane; x < kBmWords; x += 64) bm[x] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t j = lane; j < outv; j += 64) {
+            const uint32_t off = dag_col[vb + j] - in.x;
+            atomicOr(&bm[off >> 5], 1u << (off & 31));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        constexpr uint32_t kPer = kBmWords / 64;
+        uint32_t c[kPer], sum = 0;
+#pragma unroll
+        for (uint32_t x = 0; x < kPer; ++x) {
+            c[x] = (uint32_t)__popc(bm[kPer * lane + x]);
+            sum += c[x];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= (unsigned)o) incl += y;
+        }
+        uint32_t run = incl - sum;
+        const uint64_t base = (uint64_t)in.w << 32 | in.z;
+#pragma unroll
+        for (uint32_t x = 0; x < kPer; ++x) {
+            const uint32_t wx = kPer * lane + x;
+            if (wx < in.y) slots[base + wx] = (uint64_t)run << 32 | bm[wx];
+            run += c[x];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
 
 __device__ __forceinline__ uint32_t find_u32(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
     uint32_t len = hi - lo;
@@ -201,7 +295,8 @@ template <bool FUSED>
 __global__ void __launch_bounds__(kBlock, 4)   // four wavefronts per SIMD (the LDS allows four blocks per CU)
 k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
       uint32_t *__restrict__ tri, uint64_t cap, unsigned long long *__restrict__ total,
-      unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa) {
+      unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa,
+      const uint4 *__restrict__ binfo, const uint64_t *__restrict__ bslots) {
     // per wavefront: N+(u), the run starts and (16-bit) lengths of each N+(v), and one slice that
     // holds the prefix of walk lengths during the flattened walks and then a staged N+(v) copy
     __shared__ uint32_t s_nbr[kWaves][kCap];
@@ -320,12 +415,24 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                     }
                     if (!more) break;
                 }
-                uint32_t pos[kBatch];
+                uint32_t pos[kBatch], bpos[kBatch];
+                bool bhit[kBatch], bmap[kBatch];
 #pragma unroll
                 for (int x = 0; x < kBatch; ++x) {
                     pos[x] = lo[x];
                     lo[x] = cvb[x];
-                    len[x] = ok[x] && !walk_v[x] ? cov[x] : 0u;
+                    // N+(v) with a bitmap: one lookup instead of the search
+                    bmap[x] = false;
+                    bhit[x] = false;
+                    bpos[x] = 0;
+                    if (ok[x] && !walk_v[x]) {
+                        const uint4 bi = binfo[nbr_lds[ci[x]]];
+                        if (bi.y) {
+                            bmap[x] = true;
+                            bhit[x] = bm_find(bi, bslots, w[x], bpos[x]);
+                        }
+                    }
+                    len[x] = ok[x] && !walk_v[x] && !bmap[x] ? cov[x] : 0u;
                 }
                 // searches in global memory (lower bound of w in N+(v)), loads of all kBatch together
                 while (true) {
@@ -352,13 +459,14 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 for (int x = 0; x < kBatch; ++x) {
                     if (!ok[x]) at[x] = ~w[x];
                     else if (walk_v[x]) at[x] = pos[x] < du ? nbr_lds[pos[x]] : ~w[x];
+                    else if (bmap[x]) at[x] = bhit[x] ? w[x] : ~w[x];
                     else at[x] = lo[x] < cvb[x] + cov[x] ? dag_col[lo[x]] : ~w[x];
                 }
 #pragma unroll
                 for (int x = 0; x < kBatch; ++x) {
                     const bool hit = ok[x] && at[x] == w[x];
                     const uint32_t e_uw = walk_v[x] ? r0 + pos[x] : r0 + ci[x] + 1 + cj[x];
-                    const uint32_t e_vw = walk_v[x] ? cvb[x] + cj[x] : lo[x];
+                    const uint32_t e_vw = walk_v[x] ? cvb[x] + cj[x] : (bmap[x] ? cvb[x] + bpos[x] : lo[x]);
                     out.put(hit, __ballot(hit), lane, r0 + ci[x], e_uw, e_vw);
                 }
             }
@@ -368,6 +476,18 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                 if (!(outv > after && after >= kStage && outv <= kCap)) continue;
                 const uint32_t vb = vb_lds[i];
                 wave_cand += after;
+                const uint4 bi = binfo[nbr_lds[i]];
+                if (bi.y) {
+                    // N+(v) has a bitmap: one lookup per head of N+(u) after v
+                    for (uint32_t b = 0; b < after; b += 64) {
+                        const uint32_t j = b + lane;
+                        bool hit = false;
+                        uint32_t pos = 0;
+                        if (j < after) hit = bm_find(bi, bslots, nbr_lds[i + 1 + j], pos);
+                        out.put(hit, __ballot(hit), lane, r0 + i, r0 + i + 1 + j, vb + pos);
+                    }
+                    continue;
+                }
                 __builtin_amdgcn_wave_barrier();
                 for (uint32_t j = lane; j < outv; j += 64) vn_lds[j] = dag_col[vb + j];
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -431,6 +551,38 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     }
 }
 
+// The rank-window bitmaps of the oriented graph (info per vertex, slots); none when they would
+// pass kBmBudgetSlots words.
+int build_bitmaps(const dt_graph *g, DevMem &info, DevMem &slots) {
+    dt_ctx *ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    DevMem words, base;
+    DT_TRY(dev_alloc(ctx, info, (uint64_t)n * sizeof(uint4) + 16));
+    DT_TRY(dev_alloc(ctx, words, ((uint64_t)n + 1) * 8));
+    DT_TRY(dev_alloc(ctx, base, ((uint64_t)n + 1) * 8));
+    DT_HIP(hipMemsetAsync(words.ptr, 0, ((uint64_t)n + 1) * 8, st));
+    k_bm_sizes<<<grid_for(n, 256), 256, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
+                                                 words.as<uint64_t>());
+    DT_HIP(hipGetLastError());
+    DT_TRY(exclusive_scan_u64(ctx, words.as<uint64_t>(), base.as<uint64_t>(), (uint64_t)n + 1, st));
+    uint64_t *h = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
+    DT_HIP(hipMemcpyAsync(h, base.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    const uint64_t total = h[0];
+    const int on = total > 0 && total <= kBmBudgetSlots;
+    k_bm_info<<<grid_for(n, 256), 256, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
+                                                words.as<uint64_t>(), base.as<uint64_t>(), on, info.as<uint4>());
+    DT_HIP(hipGetLastError());
+    DT_TRY(dev_alloc(ctx, slots, (on ? total : 0) * 8 + 8));
+    if (on) {
+        k_bm_fill<<<(unsigned)ctx->num_cus * 8, 256, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
+                                                              info.as<uint4>(), slots.as<uint64_t>());
+        DT_HIP(hipGetLastError());
+    }
+    return DT_OK;
+}
+
 }  // namespace
 
 int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint64_t *cand_out) {
@@ -440,8 +592,9 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint
     *ntri_out = 0;
     *cand_out = 0;
     if (n == 0) return DT_OK;
-    DevMem ctr;
+    DevMem ctr, binfo, bslots;
     DT_TRY(dev_alloc(ctx, ctr, 256));
+    DT_TRY(build_bitmaps(g, binfo, bslots));
     // room for 4 triangles per static pair; a graph with more runs the pass again at its size
     uint64_t cap = std::max<uint64_t>(4ull * g->m_s, 1ull << 16);
     const unsigned grid = (unsigned)ctx->num_cus * 8;
@@ -451,7 +604,8 @@ int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint
         unsigned long long *c64 = reinterpret_cast<unsigned long long *>(ctr.as<uint8_t>() + 8);
         prof_begin(ctx, kProfTriFill, st);
         k_tri<false><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
-                                              tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1, FusedArgs{});
+                                              tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1, FusedArgs{},
+                                              binfo.as<uint4>(), bslots.as<uint64_t>());
         prof_end(ctx, kProfTriFill, st);
         DT_HIP(hipGetLastError());
         uint64_t *h = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
@@ -474,9 +628,10 @@ int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, u
     *n_rest = *ntri_out = *cand_out = 0;
     const unsigned grid = (unsigned)ctx->num_cus * 8;
     const uint64_t n_part = (uint64_t)grid * kWaves;
-    DevMem ctr, part;
+    DevMem ctr, part, binfo, bslots;
     DT_TRY(dev_alloc(ctx, ctr, 256));
     DT_TRY(dev_alloc(ctx, part, n_part * 8 * sizeof(int64_t)));
+    if (n) DT_TRY(build_bitmaps(g, binfo, bslots));
     FusedArgs fa{};
     fa.eoff = g->eoff.as<uint32_t>();
     fa.key = g->key.as<uint64_t>();
@@ -500,7 +655,8 @@ int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, u
         prof_begin(ctx, kProfTriFill, st);
         if (n)
             k_tri<true><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), nullptr, 0,
-                                                 c64, ctr.as<unsigned>(), c64 + 1, fa);
+                                                 c64, ctr.as<unsigned>(), c64 + 1, fa, binfo.as<uint4>(),
+                                                 bslots.as<uint64_t>());
         else
             DT_HIP(hipMemsetAsync(part.ptr, 0, n_part * 8 * sizeof(int64_t), st));
         prof_end(ctx, kProfTriFill, st);

@@ -2,9 +2,8 @@
 // rule's pair cap and the weight of the cost model that splits the other triangles between the
 // medium path and the prefix procedures (each candidate is a schedule built and timed), then the
 // light and medium kernels' blocks per compute unit.  The objective is the geometric mean of the
-// whole-span count times at four d13 from ten minutes to eleven days (the paper's sweeps of
-// Section 6 span that range), so that the split serves short and long deltas alike; at longer
-// deltas the cost model alone bounds the work (within cost_pct / 100 of the prefix procedures').  Choices are cached per (device, size class) for the process and reused by
+// whole-span count times at five d13 from ten minutes to infinity (the paper's sweeps of Section 6
+// reach eleven days), so that the split serves short and long deltas alike.  Choices are cached per (device, size class) for the process and reused by
 // every later build of a graph in that class, by the batched path and by the server (which count
 // with the schedules those builds made).  Results never depend on any of these choices.
 #include <array>
@@ -39,7 +38,7 @@ std::array<int, 4> size_class(const dt_graph *g) {
 // logarithms (the geometric mean's order), so that each delta weighs alike
 int time_counts(dt_graph *g, float *ms_out) {
     dt_ctx *ctx = g->ctx;
-    const int64_t ds[4] = {600, 3600, 86400, 1000000};
+    const int64_t ds[5] = {600, 3600, 86400, 1000000, INT64_MAX};
     hipEvent_t a = nullptr, b = nullptr;
     DT_HIP(hipEventCreate(&a));
     DT_HIP(hipEventCreate(&b));
