@@ -252,7 +252,17 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (calibrates HBM counters)")
+    ap.add_argument("--maps-at-exit", action="store_true",
+                    help="write /proc/self/maps to stderr when the interpreter exits (to attribute a "
+                         "fault in exit-time teardown to a library)")
     args = ap.parse_args()
+    if args.maps_at_exit:
+        import atexit
+
+        def _maps():
+            sys.stderr.write(open("/proc/self/maps").read())
+            sys.stderr.flush()
+        atexit.register(_maps)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the count of one graph runs on a single MI355X "
@@ -495,6 +505,9 @@ def main():
     }
     dt.dt_graph_free(h)
     dt.dt_ctx_destroy(ctx)
+    # nothing of ours or torch's left on the device before the interpreter's teardown
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(line), flush=True)
 
 

@@ -1,5 +1,5 @@
-// Degeneracy ordering by a parallel k-core peel (Section 3: "removing a vertex with minimum degree
-// repeatedly"; the degeneracy is the largest core number).
+// Degeneracy ordering by a parallel k-core peel (Section 3, the degeneracy ordering: vertices taken
+// in order of smallest remaining degree; the degeneracy is the largest core number).
 //
 // Level k removes every remaining vertex whose remaining degree is <= k: the vertices found by a
 // scan of the remaining ones, then those whose degree falls to k while their neighbours are

@@ -1,6 +1,6 @@
 """GPU parity of the degeneracy ordering of Section 3, by both methods.  The second one (h-index core
-numbers, then every shell peeled at once) on every graph; the default level-by-level peel in its
-regimes:
+numbers, then every shell peeled at once) on the graph of shapes and one power-law graph; the
+default level-by-level peel in its regimes:
 the whole peel on the cooperative grid (peel_tail = 1), the whole peel in one workgroup (graphs of
 at most 16384 vertices), the grid handing its last vertices to one workgroup, and (on a 600K-vertex
 graph) the full-width grid for the first levels before the narrow one.  A graph of shapes covers
@@ -131,7 +131,10 @@ def test_peel_regimes_match_oracle(ctx, name):
     _, ocore = oracle.stats(g.n, g.src, g.dst, g.t, core=True)
     pairs = _static_pairs(g)
     want = oracle.count(g.n, g.src, g.dst, g.t, *q)
-    for method, pt in [(1, 0)] + [(0, pt) for pt in tails]:
+    # the second method (h-index core numbers, slower than the level peel on every graph measured)
+    # on the graph of shapes that covers its row kinds and on one power-law graph only
+    methods = [(1, 0)] if name in ("shapes", "scaled") else []
+    for method, pt in methods + [(0, pt) for pt in tails]:
         got = _check(ctx, g, method, pt, ocore, pairs, q)
         assert (got == want).all(), (name, method, pt, got, want)
 
