@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (calibrates HBM counters)")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the step and the count at the headline delta (for profiled runs)")
     ap.add_argument("--maps-at-exit", action="store_true",
                     help="write /proc/self/maps to stderr when the interpreter exits (to attribute a "
                          "fault in exit-time teardown to a library)")
@@ -319,6 +321,26 @@ def main():
     st = dt.dt_graph_stats(h)
     value = g.m / (ms_step / 1e3)
     log(f"step {ms_step:.2f} ms -> {value:.3e} edges/s")
+
+    if args.quick:
+        st = dt.dt_graph_stats(h)
+        ts = []
+        for _ in range(11):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            dt.dt_count(h, d, d, d)
+            ts.append((time.perf_counter() - a) * 1e3)
+        pk = dt.dt_ctx_last_profile(ctx)
+        print(json.dumps({"quick": True, "ms_per_step": round(ms_step, 3), "value": round(value, 1),
+                          "count_ms": round(statistics.median(ts[1:]), 4),
+                          "kernel_ms_step": {k: round(float(np.mean([p[k] for p in prof])), 4) for k in prof[0]},
+                          "kernel_ms_count": {k: round(float(v), 4) for k, v in pk.items() if v > 0},
+                          "stats": {k: v for k, v in st.items() if isinstance(v, int)}}), flush=True)
+        dt.dt_graph_free(h)
+        dt.dt_ctx_destroy(ctx)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return
 
     # the one-shot path: ordering, orientation and enumeration that counts as it goes (no stored
     # triangle list); it drops the build, which is made again afterwards

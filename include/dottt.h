@@ -13,6 +13,11 @@
  *   - Outputs go to caller-owned buffers.  Handles (dt_ctx, dt_graph, dt_server) own the device
  *     memory they allocate until the matching *_destroy / *_free / *_stop call.
  *   - Counts are exact int64.  out[k] is the count of type T(k+1) of Figure 2 (Section 1.1).
+ *     A graph whose sum over static triangles of the product of the three pairs' multiplicities
+ *     (sum_sigma3 in dt_stats, the count of every type together at infinite deltas) reaches
+ *     2^63 is counted in 128 bits by dt_count, dt_count_visits and dt_count_oneshot, which
+ *     return DT_EOVERFLOW (output untouched) only when a type's count reaches 2^63; the other
+ *     count calls refuse such a graph with DT_EOVERFLOW before any work.
  *   - A dt_ctx and the graphs made from it are used by one host thread at a time; the dt_server_*
  *     calls are safe to call from any number of threads.
  *
@@ -36,7 +41,7 @@ extern "C" {
 #define DT_OK         0
 #define DT_EINVAL   (-22)   /* bad argument: null pointer, node id >= n, negative delta, t_lo > t_hi */
 #define DT_ENOMEM   (-12)   /* device allocation failed or would exceed the context's HBM budget   */
-#define DT_EOVERFLOW (-75)  /* a size limit of this version, or a count that may not fit in int64   */
+#define DT_EOVERFLOW (-75)  /* a size limit of this version, or a count that does not fit in int64  */
 #define DT_EBUSY    (-16)   /* server full / graph busy                                             */
 #define DT_ETIMEDOUT (-110) /* dt_server_wait timed out                                             */
 #define DT_EDEVICE   (-5)   /* a HIP runtime error                                                  */
@@ -174,10 +179,13 @@ int dt_graph_stats(const dt_graph *g, dt_stats *out);
 /* Per-type counts of (d13, d12, d23)-temporal triangles (Algorithm 4, Section 5): for every
  * static triangle <u, v, w> with u first in the ordering, every temporal ordering (Figure 3) and
  * orientation (Figure 4) is counted (Algorithms 1-3) and added to the type given by Table 2.
- * out: host int64[8].  Synchronous on the context's stream. */
+ * out: host int64[8].  Synchronous on the context's stream.  Counts in 128 bits when the graph's
+ * sum_sigma3 reaches 2^63; DT_EOVERFLOW if a type's count reaches 2^63. */
 int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]);
 /* The same, enqueued on `hip_stream` (a hipStream_t; NULL = the context's stream).  out8 is
- * device memory or pinned host memory that stays valid until the stream reaches the work. */
+ * device memory or pinned host memory that stays valid until the stream reaches the work.  A graph
+ * whose sum_sigma3 reaches 2^63 is refused (DT_EOVERFLOW): the result is never read back, so there
+ * is no point at which a type count beyond int64 could be reported. */
 int dt_count_async(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_stream);
 /* dt_count_async without any allocation, for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same counts,
@@ -194,7 +202,7 @@ int dt_count_noalloc(dt_graph *g, const dt_query *q, int64_t *out8, void *hip_st
  * uw edge) pair evaluated on the light and medium paths, per outer edge of the medium path and per
  * source edge in each of the two passes of the prefix procedures.  With at most one cost-model
  * constant per triangle, visits stay within 2 * 48 * degeneracy * m', m' the temporal edges in the
- * window, for every d13.  out: host int64[8], equal to dt_count's. */
+ * window, for every d13.  out: host int64[8], equal to dt_count's (128-bit sums as dt_count). */
 int dt_count_visits(dt_graph *g, const dt_query *q, int64_t out[8], uint64_t *visits);
 /* Diagnostic: the 48 per-(ordering, orientation) counts, out[(pi-1)*8 + (rho-1)], with u, v, w
  * named by the degeneracy ordering (u first).  Sums of cells by Table 2 give dt_count's result. */
@@ -207,7 +215,10 @@ int dt_count_cells(dt_graph *g, const dt_query *q, int64_t out[48]);
  * the few others are kept for the medium and heavy paths.  For graphs whose triangle list would
  * not fit and for single queries.  The result equals dt_count's.  Any earlier build is dropped
  * (dt_count then returns DT_ENOTBUILT until dt_graph_build); the graph's ordering is replaced.
- * out: host int64[8].  Synchronous on the context's stream. */
+ * out: host int64[8].  Synchronous on the context's stream.  The triangles kept for the medium
+ * and heavy paths are counted in 128 bits when their sum_sigma3 reaches 2^63 (DT_EOVERFLOW if a
+ * type's count reaches 2^63); the others are summed in int64, and a graph with so many triangles
+ * that those sums could overflow (triangles * light_pair_cap * 64 >= 2^63) is refused. */
 int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]);
 
 /* A delta sweep on one graph (the parameter sweeps of Section 6, Figures 1 and 5): the counts of

@@ -360,11 +360,28 @@ int dt_graph_stats(const dt_graph *g, dt_stats *out) {
     return DT_OK;
 }
 
-static int count_guarded(dt_graph *g, const dt_query *q, DQuery *dq, bool *empty) {
+// Checks the graph and normalises the query.  A graph whose sum of multiplicity products reaches
+// 2^63 may have counts beyond int64: only the calls that count in 128 bits (allow_wide) take it.
+static int count_guarded(dt_graph *g, const dt_query *q, DQuery *dq, bool *empty, bool allow_wide = false) {
     DT_TRY(check_graph(g, true));
     DT_TRY(normalise_query(g, q, dq, empty));
-    if ((g->sum_sigma3 >> 63) != 0)
-        return fail(DT_EOVERFLOW, "the sum of multiplicity products exceeds 2^63; counts may not fit int64");
+    if (!allow_wide && (g->sum_sigma3 >> 63) != 0)
+        return fail(DT_EOVERFLOW, "the sum of multiplicity products exceeds 2^63; counts may not fit int64 "
+                                  "(dt_count and dt_count_visits count such graphs in 128 bits)");
+    return DT_OK;
+}
+
+// The 128-bit result of a wide count, (low, high) word pairs per type, into int64 counts; a type
+// whose count reaches 2^63 is refused and out is left as it was.
+static int narrow_counts(const int64_t *w16, const int64_t *add8, int64_t out[8]) {
+    int64_t r[8];
+    for (int i = 0; i < 8; ++i) {
+        unsigned __int128 v = ((unsigned __int128)(uint64_t)w16[2 * i + 1] << 64) | (uint64_t)w16[2 * i];
+        if (add8) v += (uint64_t)add8[i];
+        if ((v >> 63) != 0) return fail(DT_EOVERFLOW, "the count of type T%d reaches 2^63", i + 1);
+        r[i] = (int64_t)(uint64_t)v;
+    }
+    memcpy(out, r, sizeof(r));
     return DT_OK;
 }
 
@@ -373,16 +390,20 @@ int dt_count(dt_graph *g, const dt_query *q, int64_t out[8]) {
     if (!out) return fail(DT_EINVAL, "null output");
     DQuery dq;
     bool empty = false;
-    DT_TRY(count_guarded(g, q, &dq, &empty));
+    DT_TRY(count_guarded(g, q, &dq, &empty, true));
     if (empty || g->n_tri == 0) {
         for (int i = 0; i < 8; ++i) out[i] = 0;
         return DT_OK;
     }
     dt_ctx *ctx = g->ctx;
     DeviceGuard dg(ctx->device);
+    const bool wide = (g->sum_sigma3 >> 63) != 0;
+    const size_t words = wide ? 16 : 8;
     DT_TRY(count_enqueue(g, dq, ctx->out8.as<int64_t>(), ctx->stream, false, nullptr, ctx->scratch));
-    DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    DT_HIP(hipMemcpyAsync(ctx->pinned_out, ctx->out8.ptr, words * sizeof(int64_t), hipMemcpyDeviceToHost,
+                          ctx->stream));
     DT_HIP(hipStreamSynchronize(ctx->stream));
+    if (wide) return narrow_counts(ctx->pinned_out, nullptr, out);
     memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
     return DT_OK;
 }
@@ -417,22 +438,36 @@ int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]) {
     uint64_t n_rest = 0, ntri = 0, cand = 0;
     DT_TRY(fused_count(g, dq, o, rest, &n_rest, &ntri, &cand));
     g->tri_candidates = cand;
+    const unsigned __int128 s3_all = g->sum_sigma3;   // of every triangle (the schedule's is the rest's)
     int rc = DT_OK;
-    if (n_rest) {
+    // the light triangles are summed in int64: each adds at most light_pair_cap * 64 triples
+    if (((unsigned __int128)ntri * g->light_cap_used * 64) >> 63)
+        rc = fail(DT_EOVERFLOW, "the one-pass count's int64 sums of %llu light triangles may overflow; "
+                                "build the graph and count with dt_count", (unsigned long long)ntri);
+    if (rc == DT_OK && n_rest) {
         // the triangles for the medium and heavy paths: a schedule of their own, then a count
+        // (the rest is counted in 128 bits when its sum of multiplicity products reaches 2^63, 16
+        // words at o + 8)
         g->n_tri = n_rest;
         rc = make_schedule(g, rest);
         if (rc == DT_OK) rc = count_enqueue(g, dq, o + 8, ctx->stream, false, nullptr, ctx->scratch);
-    } else {
+    } else if (rc == DT_OK) {
         DT_HIP(hipMemsetAsync(o + 8, 0, 8 * sizeof(int64_t), ctx->stream));
     }
     if (rc == DT_OK) {
-        DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+        const bool wide = n_rest && (g->sum_sigma3 >> 63) != 0;
+        DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, (wide ? 24 : 16) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
         DT_HIP(hipStreamSynchronize(ctx->stream));
-        for (int i = 0; i < 8; ++i) out[i] = ctx->pinned_out[i] + ctx->pinned_out[8 + i];
+        if (wide) {
+            rc = narrow_counts(ctx->pinned_out + 8, ctx->pinned_out, out);
+        } else {
+            for (int i = 0; i < 8; ++i) out[i] = ctx->pinned_out[i] + ctx->pinned_out[8 + i];
+        }
     }
     g->sched = Schedule();
     g->n_tri = ntri;
+    g->sum_sigma3 = s3_all;
     g->ms_peel = t1 - t0;
     g->ms_orient = t2 - t1;
     g->ms_tri = now_ms() - t2;
@@ -499,7 +534,7 @@ int dt_count_visits(dt_graph *g, const dt_query *q, int64_t out[8], uint64_t *vi
     if (!out || !visits) return fail(DT_EINVAL, "null output");
     DQuery dq;
     bool empty = false;
-    DT_TRY(count_guarded(g, q, &dq, &empty));
+    DT_TRY(count_guarded(g, q, &dq, &empty, true));
     *visits = 0;
     if (empty || g->n_tri == 0) {
         for (int i = 0; i < 8; ++i) out[i] = 0;
@@ -507,15 +542,17 @@ int dt_count_visits(dt_graph *g, const dt_query *q, int64_t out[8], uint64_t *vi
     }
     dt_ctx *ctx = g->ctx;
     DeviceGuard dg(ctx->device);
-    // the counts in out8[0..8), the visits in out8[8]
+    // the counts in out8[0..8) (or [0..16) in 128 bits), the visits in out8[16]
+    const bool wide = (g->sum_sigma3 >> 63) != 0;
     int64_t *o = ctx->out8.as<int64_t>();
-    unsigned long long *v = reinterpret_cast<unsigned long long *>(o + 8);
+    unsigned long long *v = reinterpret_cast<unsigned long long *>(o + 16);
     DT_HIP(hipMemsetAsync(v, 0, 8, ctx->stream));
     DT_TRY(count_enqueue(g, dq, o, ctx->stream, false, nullptr, ctx->scratch, 15, v));
-    DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    DT_HIP(hipMemcpyAsync(ctx->pinned_out, o, 17 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     DT_HIP(hipStreamSynchronize(ctx->stream));
+    *visits = (uint64_t)ctx->pinned_out[16];
+    if (wide) return narrow_counts(ctx->pinned_out, nullptr, out);
     memcpy(out, ctx->pinned_out, 8 * sizeof(int64_t));
-    *visits = (uint64_t)ctx->pinned_out[8];
     return DT_OK;
 }
 

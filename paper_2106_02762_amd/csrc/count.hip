@@ -32,6 +32,8 @@
 //
 // Counts are int64 and summed per lane, per wave, per block, then per launch, with no atomics on
 // the result (cells mode, a diagnostic, uses atomics).
+#include <type_traits>
+
 #include "count_dev.h"
 
 namespace dt {
@@ -40,12 +42,16 @@ using namespace cdev;
 
 namespace {
 
-template <bool CELLS, unsigned BLOCK>
+// ACC: Acc<false> (int64 type counts), Acc<true> (the 48 cells by atomics, no partials) or AccW
+// (128-bit type counts, 16-word partial slots)
+template <class ACC> constexpr bool kCells = std::is_same<ACC, Acc<true>>::value;
+
+template <class ACC, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff,
         const uint64_t *__restrict__ key, DQuery q, int64_t *__restrict__ partial,
         int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
-    Acc<CELLS> acc;
+    ACC acc;
     acc.cells = cells;
     const uint64_t n_tri = R.pre[R.n];
     const uint32_t nblk = gridDim.x;
@@ -57,17 +63,17 @@ k_light(Ranges R, const uint32_t *__restrict__ tri, const uint32_t *__restrict__
     for (uint64_t i = beg + threadIdx.x; i < end; i += BLOCK)
         light_tri(tri, range_at(R, r, i), eoff, key, q, acc);
     add_visits(visits, acc.visits);
-    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+    if (!kCells<ACC>) acc_store<BLOCK>(acc, partial, blockIdx.x);
 }
 
 // medium path: wave w takes the 64 entries from 64 w on, then those from 64 (w + W) on, ...;
 // with lev (windowed copies) entries of triangles below the query's level are skipped
-template <bool CELLS, unsigned BLOCK>
+template <class ACC, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict__ ent,
          const uint8_t *__restrict__ lev, const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
          DQuery q, int64_t *__restrict__ partial, int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
-    Acc<CELLS> acc;
+    ACC acc;
     acc.cells = cells;
     const unsigned lane = threadIdx.x & 63;
     const uint64_t n_ent = R.pre[R.n];
@@ -82,14 +88,15 @@ k_medium(Ranges R, const uint32_t *__restrict__ med, const uint32_t *__restrict_
         vis += (active ? 1u : 0u) + (lane == 0 ? pairs : 0u);
     }
     add_visits(visits, vis);
-    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+    if (!kCells<ACC>) acc_store<BLOCK>(acc, partial, blockIdx.x);
 }
 
 // unit path: block b takes a contiguous run of the records [beg, end)
-template <bool CELLS, unsigned BLOCK>
+template <class ACC, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_unit(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, UQuery u, int64_t *__restrict__ partial,
        int64_t *__restrict__ cells, unsigned long long *__restrict__ visits) {
+    constexpr bool CELLS = kCells<ACC>;
     const uint64_t n = end - beg;
     const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t b = beg + (uint64_t)blockIdx.x * per;
@@ -98,10 +105,10 @@ k_unit(uint64_t beg, uint64_t end, const uint4 *__restrict__ rec, UQuery u, int6
     if (b < e) unit_run<CELLS, BLOCK>(rec, b, e, u, c, cells);
     if (visits && threadIdx.x == 0 && e > b) atomicAdd(visits, (unsigned long long)(e - b));
     if (!CELLS) {
-        int64_t t[8];
+        ACC acc;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) t[j] = c[j];
-        block_store<BLOCK>(t, partial + 8 * (uint64_t)blockIdx.x);
+        for (int j = 0; j < 8; ++j) acc.t[j] = c[j];
+        acc_store<BLOCK>(acc, partial, blockIdx.x);
     }
 }
 
@@ -135,15 +142,15 @@ k_heavy_prefix_add(HeavyArgs A, uint64_t pe) {
 }
 
 // the count pass: chunks [cb, ce) of 256 source edges (of the four lists in a row) each
-template <bool CELLS, unsigned BLOCK>
+template <class ACC, unsigned BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_heavy_count(HeavyArgs A, uint64_t cb, uint64_t ce, int64_t *__restrict__ partial, int64_t *__restrict__ cells,
               unsigned long long *__restrict__ visits) {
-    Acc<CELLS> acc;
+    ACC acc;
     acc.cells = cells;
     for (uint64_t ch = cb + blockIdx.x; ch < ce; ch += gridDim.x) heavy_count_chunk(A, ch, acc);
     add_visits(visits, acc.visits);
-    if (!CELLS) block_store<BLOCK>(acc.t, partial + 8 * (uint64_t)blockIdx.x);
+    if (!kCells<ACC>) acc_store<BLOCK>(acc, partial, blockIdx.x);
 }
 
 // final reduction of the per-block partials into out8 (deterministic order)
@@ -155,6 +162,18 @@ k_reduce(uint64_t n_part, const int64_t *__restrict__ partial, int64_t *__restri
         for (int j = 0; j < 8; ++j) t[j] += partial[8 * i + j];
     }
     block_store<256>(t, out8);
+}
+
+// the 128-bit form: 16-word partials into 16 words (low, high per type)
+__global__ void __launch_bounds__(256)
+k_reduce_w(uint64_t n_part, const int64_t *__restrict__ partial, int64_t *__restrict__ out16) {
+    AccW acc;
+    for (uint64_t i = threadIdx.x; i < n_part; i += 256) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            acc.t[j] += ((unsigned __int128)(uint64_t)partial[16 * i + 2 * j + 1] << 64) | (uint64_t)partial[16 * i + 2 * j];
+    }
+    block_store_w<256>(acc.t, out16);
 }
 
 __global__ void k_zero(uint64_t n, int64_t *__restrict__ p) {
@@ -489,8 +508,71 @@ void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p
     p.ug = p.ue > p.ub ? (unsigned)std::min<uint64_t>((p.ue - p.ub + kUnitPerBlock - 1) / kUnitPerBlock,
                                                       (uint64_t)ctx->num_cus * 8) : 0;
     p.n_part = (uint64_t)p.lg + p.hg + p.mg + p.ug;
-    p.part_bytes = (p.n_part + 1) * 8 * sizeof(int64_t);
+    // graphs whose counts may pass 2^63 are counted in 128 bits (16-word partials, 16-word result)
+    p.wide = (g->sum_sigma3 >> 63) != 0;
+    p.part_bytes = (p.n_part + 1) * (p.wide ? 16 : 8) * sizeof(int64_t);
     p.heavy_bytes = p.hr.n ? p.hr.scratch_bytes : 0;
+}
+
+// The four paths' kernels of a planned count with accumulator ACC: the light and heavy ones on sl,
+// the medium one on sm, the unit one on s; partial slots of 8 words (16 for AccW) in the order
+// light, heavy, medium, unit.
+template <class ACC>
+int launch_paths(dt_graph *g, const DQuery &q, const CountPlan &p, const ScratchView &sv, hipStream_t s,
+                 hipStream_t sl, hipStream_t sm, int64_t *cells_dev, unsigned long long *visits) {
+    dt_ctx *ctx = g->ctx;
+    Schedule &S = g->sched;
+    constexpr uint64_t W = std::is_same<ACC, AccW>::value ? 16 : 8;
+    const unsigned lg = p.lg, hg = p.hg, mg = p.mg, ug = p.ug;
+    int64_t *part = sv.part;
+    const uint32_t *eoff = g->eoff.as<uint32_t>();
+    const uint64_t *key = g->key.as<uint64_t>();
+    if (lg) {
+        prof_begin(ctx, kProfLight, sl);
+        k_light<ACC, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light, eoff, key, q, part, cells_dev, visits);
+        prof_end(ctx, kProfLight, sl);
+        DT_HIP(hipGetLastError());
+    }
+    if (mg) {
+        int64_t *mp = part + W * ((uint64_t)lg + hg);
+        prof_begin(ctx, kProfMedium, sm);
+        k_medium<ACC, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems, p.mlev, eoff, key, q, mp, cells_dev, visits);
+        prof_end(ctx, kProfMedium, sm);
+        DT_HIP(hipGetLastError());
+    }
+    if (ug) {
+        const UQuery u = unit_query(q);
+        int64_t *up = part + W * ((uint64_t)lg + hg + mg);
+        prof_begin(ctx, kProfUnit, s);
+        k_unit<ACC, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, cells_dev, visits);
+        prof_end(ctx, kProfUnit, s);
+        DT_HIP(hipGetLastError());
+    }
+    if (p.hr.n) {
+        const HeavyRange &hr = p.hr;
+        const uint64_t npc = S.n_pchunks - hr.pb;
+        HeavyArgs A;
+        heavy_args(g, q, hr, sv.heavy, A);
+        k_heavy_clip<<<grid_for(hr.n, 256), 256, 0, sl>>>(A, hr.n);
+        DT_HIP(hipGetLastError());
+        const unsigned pgrid = (unsigned)std::min<uint64_t>(npc, (uint64_t)ctx->num_cus * 16);
+        prof_begin(ctx, kProfHeavyPrefix, sl);
+        k_heavy_prefix_local<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks, visits);
+        DT_HIP(hipGetLastError());
+        k_heavy_prefix_scan<<<grid_for(npc, 256), 256, 0, sl>>>(A, S.n_pchunks);
+        DT_HIP(hipGetLastError());
+        k_heavy_prefix_add<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks);
+        prof_end(ctx, kProfHeavyPrefix, sl);
+        DT_HIP(hipGetLastError());
+        const unsigned cb = g->tuning.heavy_chunk;
+        if (cb != 256) return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
+        int64_t *hp = part + W * (uint64_t)lg;
+        prof_begin(ctx, kProfHeavyCount, sl);
+        k_heavy_count<ACC, 256><<<hg, 256, 0, sl>>>(A, hr.cb, S.n_chunks, hp, cells_dev, visits);
+        prof_end(ctx, kProfHeavyCount, sl);
+        DT_HIP(hipGetLastError());
+    }
+    return DT_OK;
 }
 
 // Enqueue one planned count on stream s: partials -> out8_dev (int64[8]); cells mode accumulates the
@@ -499,7 +581,6 @@ void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p
 int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
                  int64_t *cells_dev, const ScratchView &sv, unsigned long long *visits) {
     dt_ctx *ctx = g->ctx;
-    Schedule &S = g->sched;
     if (sv.part_bytes < p.part_bytes || sv.heavy_bytes < p.heavy_bytes)
         return fail(DT_EINVAL, "count scratch too small (%zu of %zu, %zu of %zu bytes)", sv.part_bytes, p.part_bytes,
                     sv.heavy_bytes, p.heavy_bytes);
@@ -527,66 +608,12 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
             sm = ctx->side[1];
         }
     }
-    const uint32_t *eoff = g->eoff.as<uint32_t>();
-    const uint64_t *key = g->key.as<uint64_t>();
-    if (lg) {
-        prof_begin(ctx, kProfLight, sl);
-        if (cells)
-            k_light<true, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light, eoff, key, q, part, cells_dev, visits);
-        else
-            k_light<false, kLightBlock><<<lg, kLightBlock, 0, sl>>>(p.lr, p.light, eoff, key, q, part, nullptr, visits);
-        prof_end(ctx, kProfLight, sl);
-        DT_HIP(hipGetLastError());
-    }
-    if (mg) {
-        int64_t *mp = part + 8 * ((uint64_t)lg + hg);
-        prof_begin(ctx, kProfMedium, sm);
-        if (cells)
-            k_medium<true, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems, p.mlev, eoff, key, q, mp, cells_dev,
-                                                    visits);
-        else
-            k_medium<false, 256><<<mg, 256, 0, sm>>>(p.mr, p.medium, p.mitems, p.mlev, eoff, key, q, mp, nullptr,
-                                                     visits);
-        prof_end(ctx, kProfMedium, sm);
-        DT_HIP(hipGetLastError());
-    }
-    if (ug) {
-        const UQuery u = unit_query(q);
-        int64_t *up = part + 8 * ((uint64_t)lg + hg + mg);
-        prof_begin(ctx, kProfUnit, s);
-        if (cells)
-            k_unit<true, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, cells_dev, visits);
-        else
-            k_unit<false, kUnitBlock><<<ug, kUnitBlock, 0, s>>>(p.ub, p.ue, S.unit.as<uint4>(), u, up, nullptr, visits);
-        prof_end(ctx, kProfUnit, s);
-        DT_HIP(hipGetLastError());
-    }
-    if (p.hr.n) {
-        const HeavyRange &hr = p.hr;
-        const uint64_t npc = S.n_pchunks - hr.pb;
-        HeavyArgs A;
-        heavy_args(g, q, hr, sv.heavy, A);
-        k_heavy_clip<<<grid_for(hr.n, 256), 256, 0, sl>>>(A, hr.n);
-        DT_HIP(hipGetLastError());
-        const unsigned pgrid = (unsigned)std::min<uint64_t>(npc, (uint64_t)ctx->num_cus * 16);
-        prof_begin(ctx, kProfHeavyPrefix, sl);
-        k_heavy_prefix_local<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks, visits);
-        DT_HIP(hipGetLastError());
-        k_heavy_prefix_scan<<<grid_for(npc, 256), 256, 0, sl>>>(A, S.n_pchunks);
-        DT_HIP(hipGetLastError());
-        k_heavy_prefix_add<<<pgrid, kPrefixBlock, 0, sl>>>(A, S.n_pchunks);
-        prof_end(ctx, kProfHeavyPrefix, sl);
-        DT_HIP(hipGetLastError());
-        const unsigned cb = g->tuning.heavy_chunk;
-        if (cb != 256) return fail(DT_EINVAL, "heavy_chunk %u not compiled", cb);
-        int64_t *hp = part + 8 * (uint64_t)lg;
-        prof_begin(ctx, kProfHeavyCount, sl);
-        if (cells)
-            k_heavy_count<true, 256><<<hg, 256, 0, sl>>>(A, hr.cb, S.n_chunks, hp, cells_dev, visits);
-        else
-            k_heavy_count<false, 256><<<hg, 256, 0, sl>>>(A, hr.cb, S.n_chunks, hp, nullptr, visits);
-        prof_end(ctx, kProfHeavyCount, sl);
-        DT_HIP(hipGetLastError());
+    if (cells) {
+        DT_TRY(launch_paths<Acc<true>>(g, q, p, sv, s, sl, sm, cells_dev, visits));
+    } else if (p.wide) {
+        DT_TRY(launch_paths<AccW>(g, q, p, sv, s, sl, sm, nullptr, visits));
+    } else {
+        DT_TRY(launch_paths<Acc<false>>(g, q, p, sv, s, sl, sm, nullptr, visits));
     }
     if (fork) {
         if (lg || hg) {
@@ -600,7 +627,8 @@ int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8
     }
     if (!cells) {
         prof_begin(ctx, kProfReduce, s);
-        k_reduce<<<1, 256, 0, s>>>(n_part, part, out8_dev);
+        if (p.wide) k_reduce_w<<<1, 256, 0, s>>>(n_part, part, out8_dev);
+        else k_reduce<<<1, 256, 0, s>>>(n_part, part, out8_dev);
         prof_end(ctx, kProfReduce, s);
         DT_HIP(hipGetLastError());
     }

@@ -65,6 +65,19 @@ template <> struct Acc<true> {
     }
 };
 
+// 128-bit per-lane type counts, for graphs whose sum of multiplicity products reaches 2^63 (every
+// contribution is non-negative, so the sums only need more bits, never a sign)
+struct AccW {
+    unsigned __int128 t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t *cells = nullptr;
+    uint64_t visits = 0;
+    template <class CA, class CB> __device__ __forceinline__ void add2(bool first, int64_t v) {
+        t[CA::type] += first ? (unsigned __int128)(uint64_t)v : 0;
+        t[CB::type] += first ? 0 : (unsigned __int128)(uint64_t)v;
+    }
+    template <class C> __device__ __forceinline__ void add(int64_t v) { t[C::type] += (uint64_t)v; }
+};
+
 // position of element j of the ranges R (j < R.pre[R.n]); the cursor r only moves forward, so a
 // thread walking increasing j finds each range once
 __device__ __forceinline__ uint64_t range_at(const Ranges &R, uint32_t &r, uint64_t j) {
@@ -461,6 +474,47 @@ __device__ __forceinline__ void block_store(const int64_t (&t)[8], int64_t *__re
     }
 }
 
+// the 128-bit form: 16 words per block slot, (low, high) per type
+template <unsigned BLOCK>
+__device__ __forceinline__ void block_store_w(const unsigned __int128 (&t)[8], int64_t *__restrict__ out16) {
+    __shared__ unsigned long long s[BLOCK / 64][16];
+    const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        unsigned long long lo = (unsigned long long)t[i], hi = (unsigned long long)(t[i] >> 64);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+            const unsigned long long sum = lo + lo2;
+            hi += hi2 + (sum < lo ? 1ull : 0ull);
+            lo = sum;
+        }
+        if (lane == 0) {
+            s[wave][2 * i] = lo;
+            s[wave][2 * i + 1] = hi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        unsigned __int128 v = 0;
+#pragma unroll
+        for (unsigned w = 0; w < BLOCK / 64; ++w)
+            v += ((unsigned __int128)s[w][2 * threadIdx.x + 1] << 64) | s[w][2 * threadIdx.x];
+        out16[2 * threadIdx.x] = (int64_t)(uint64_t)v;
+        out16[2 * threadIdx.x + 1] = (int64_t)(uint64_t)(v >> 64);
+    }
+}
+
+// a block's accumulator to its partial slot: 8 words, or 16 in the 128-bit form
+template <unsigned BLOCK, class ACC> __device__ __forceinline__ void acc_store(const ACC &acc, int64_t *__restrict__ part,
+                                                                              uint64_t slot) {
+    block_store<BLOCK>(acc.t, part + 8 * slot);
+}
+template <unsigned BLOCK> __device__ __forceinline__ void acc_store(const AccW &acc, int64_t *__restrict__ part,
+                                                                   uint64_t slot) {
+    block_store_w<BLOCK>(acc.t, part + 16 * slot);
+}
+
 // add a lane's visits to *visits (when instrumented); every lane of the wavefront must call this
 __device__ __forceinline__ void add_visits(unsigned long long *visits, uint64_t v) {
     if (!visits) return;
@@ -651,9 +705,9 @@ struct HeavyCtx {
     uint32_t lo[6], hi[6];     // clipped bounds
 };
 
-template <bool CELLS, int X, int B, int C>
+template <class ACC, int X, int B, int C>
 __device__ __forceinline__ void heavy_cell(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
-                                           Acc<CELLS> &acc, const uint32_t (&o)[8]) {
+                                           ACC &acc, const uint32_t (&o)[8]) {
     // element's pair: uv for X = 0, 1 and uw for X = 2, 3; direction a = X & 1
     constexpr bool kUv = X < 2;
     constexpr int a = X & 1;
@@ -712,9 +766,9 @@ __device__ __forceinline__ void heavy_cell(const HeavyCtx &H, const DQuery &q, u
     }
 }
 
-template <bool CELLS, int X, int B>
+template <class ACC, int X, int B>
 __device__ __forceinline__ void heavy_other(const HeavyCtx &H, const DQuery &q, uint64_t k, int64_t t,
-                                            Acc<CELLS> &acc) {
+                                            ACC &acc) {
     constexpr int OL = X < 2 ? 2 + B : B;
     const uint32_t ob = H.lo[OL], oe = H.hi[OL];
     const uint64_t *key = H.key;
@@ -727,23 +781,22 @@ __device__ __forceinline__ void heavy_other(const HeavyCtx &H, const DQuery &q, 
     o[5] = lower(key, ob, oe, before_time(t + q.d13 + 1, q));         // t <= t + d13
     o[6] = lower(key, ob, oe, before_time(t + q.d13 - q.d12 + 1, q)); // t <= t + d13 - d12
     o[7] = 0;
-    heavy_cell<CELLS, X, B, 0>(H, q, k, t, acc, o);
-    heavy_cell<CELLS, X, B, 1>(H, q, k, t, acc, o);
+    heavy_cell<ACC, X, B, 0>(H, q, k, t, acc, o);
+    heavy_cell<ACC, X, B, 1>(H, q, k, t, acc, o);
 }
 
-template <bool CELLS, int X>
-__device__ __forceinline__ void heavy_elem(const HeavyCtx &H, const DQuery &q, uint32_t p,
-                                           Acc<CELLS> &acc) {
+template <class ACC, int X>
+__device__ __forceinline__ void heavy_elem(const HeavyCtx &H, const DQuery &q, uint32_t p, ACC &acc) {
     const uint64_t k = H.key[p];
     const int64_t t = (int64_t)(k >> q.shift);
-    heavy_other<CELLS, X, 0>(H, q, k, t, acc);
-    heavy_other<CELLS, X, 1>(H, q, k, t, acc);
+    heavy_other<ACC, X, 0>(H, q, k, t, acc);
+    heavy_other<ACC, X, 1>(H, q, k, t, acc);
 }
 
 // The count pass for one chunk ch (256 source edges of the four lists in a row), one edge per
 // thread of a 256-thread workgroup, into acc.
-template <bool CELLS>
-__device__ __forceinline__ void heavy_count_chunk(const HeavyArgs &A, uint64_t ch, Acc<CELLS> &acc) {
+template <class ACC>
+__device__ __forceinline__ void heavy_count_chunk(const HeavyArgs &A, uint64_t ch, ACC &acc) {
     const uint32_t h = A.chunks[2 * ch], first = A.chunks[2 * ch + 1];
     const uint64_t hl = h - A.hb;
     const uint32_t *t3 = A.heavy + 3 * (uint64_t)h;
@@ -779,10 +832,10 @@ __device__ __forceinline__ void heavy_count_chunk(const HeavyArgs &A, uint64_t c
         if (p >= H.lo[X] && p < H.hi[X]) {
             ++acc.visits;
             switch (X) {
-                case 0: heavy_elem<CELLS, 0>(H, A.q, p, acc); break;
-                case 1: heavy_elem<CELLS, 1>(H, A.q, p, acc); break;
-                case 2: heavy_elem<CELLS, 2>(H, A.q, p, acc); break;
-                default: heavy_elem<CELLS, 3>(H, A.q, p, acc); break;
+                case 0: heavy_elem<ACC, 0>(H, A.q, p, acc); break;
+                case 1: heavy_elem<ACC, 1>(H, A.q, p, acc); break;
+                case 2: heavy_elem<ACC, 2>(H, A.q, p, acc); break;
+                default: heavy_elem<ACC, 3>(H, A.q, p, acc); break;
             }
         }
     }

@@ -291,7 +291,8 @@ int make_schedule(dt_graph *g, DevMem &tri);
 int relayout_join(dt_graph *g);
 // One-shot pass: enumerate the triangles of the oriented graph and count the unit and light ones
 // for query q as they are found (sum to out8_dev); the others go to `rest` (*n_rest triangles,
-// three DAG edge ids each).  *ntri: all static triangles; *cand: candidates tested.
+// three DAG edge ids each).  *ntri: all static triangles; *cand: candidates tested; g->sum_sigma3:
+// the sum of multiplicity products over all of them.
 int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, uint64_t *n_rest, uint64_t *ntri,
                 uint64_t *cand);
 // unit records [*b, *e) that can hold triangles inside the query's window (all when unwindowed)
@@ -335,6 +336,7 @@ struct CountPlan {
     uint64_t n_part = 0;                         // partial slots
     size_t part_bytes = 0, heavy_bytes = 0;
     unsigned parts = 15;
+    bool wide = false;   // 128-bit counts: the result is 16 words, (low, high) per type
 };
 void count_plan(const dt_graph *g, const DQuery &q, unsigned parts, CountPlan &p);
 // Enqueue a planned count on stream s with scratch sv (which must hold the plan's needs).

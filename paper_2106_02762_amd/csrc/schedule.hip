@@ -37,7 +37,7 @@ enum : int { kClsLight = 0, kClsMedium = 1, kClsHeavy = 2, kClsUnit = 3, kClsCon
 constexpr int kClasses = 5;
 // the medium path's per-lane counts are 32-bit sums over a wavefront: inner pairs stay below 2^25
 constexpr uint64_t kMediumMaxInner = 1ull << 25;
-constexpr uint32_t kCrossSample = 512;   // outer edges sampled by the level search
+constexpr uint32_t kCrossSample = 128;   // outer edges sampled by the level search
 
 struct SplitRule {
     uint64_t cap_l, cap_m;

@@ -668,7 +668,7 @@ int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, u
             *ntri_out = h[0];
             *cand_out = h[1];
             *n_rest = h[2];
-            if (h[4] != 0 || (h[3] >> 63)) return fail(DT_EOVERFLOW, "the sum of multiplicity products exceeds 2^63; counts may not fit int64");
+            g->sum_sigma3 = ((unsigned __int128)h[4] << 64) | h[3];
             count_reduce(n_part, part.as<int64_t>(), out8_dev, st);
             return DT_OK;
         }

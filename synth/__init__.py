@@ -18,4 +18,6 @@ from .graphs import (  # noqa: F401
     clique_graph,
     contested_graph,
     long_lists_graph,
+    replicated,
+    disjoint_union,
 )

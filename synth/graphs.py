@@ -437,3 +437,18 @@ def long_lists_graph(seed: int, sizes=(5000, 3000, 700), t_range: int = 40000):
     t = rng.integers(0, t_range, src.shape[0]).astype(np.int64)
     perm = rng.permutation(src.shape[0])
     return TemporalGraph(5, src[perm], dst[perm], t[perm], name=f"long_lists(seed={seed})")
+
+
+def replicated(g: TemporalGraph, r: int) -> TemporalGraph:
+    """Every temporal edge of g repeated r times, the copies adjacent in input order and sharing
+    their timestamp.  The copies' keys (t, input index) keep the original edges' order, so every
+    temporal triangle of g becomes exactly r^3 triangles here, for any deltas and window."""
+    return TemporalGraph(g.n, np.repeat(g.src, r), np.repeat(g.dst, r), np.repeat(g.t, r),
+                         name=f"{g.name}x{r}")
+
+
+def disjoint_union(a: TemporalGraph, b: TemporalGraph) -> TemporalGraph:
+    """a's edges then b's, b's nodes renumbered after a's (their triangles stay apart)."""
+    return TemporalGraph(a.n + b.n, np.concatenate([a.src, b.src + np.uint32(a.n)]),
+                         np.concatenate([a.dst, b.dst + np.uint32(a.n)]), np.concatenate([a.t, b.t]),
+                         name=f"{a.name}+{b.name}")
