@@ -271,16 +271,38 @@ typedef struct {
     uint32_t max_inflight_queries; /* queries admitted to the device at once (0 = 4096)            */
     uint32_t max_batch;            /* queries per device launch (0 = 512)                          */
     int64_t  deadline_ns;          /* per-query deadline; 0 = none                                 */
+    uint32_t swap_to_host;         /* 1: graphs beyond the budget wait in host memory (below)      */
+    uint32_t reserved;             /* 0                                                            */
 } dt_server_cfg;
 
 int dt_server_start(dt_ctx *ctx, const dt_server_cfg *cfg, dt_server **out);
-/* Admit a built graph; DT_ENOMEM if it does not fit the server's budget.  The server does not
- * take ownership: free the graph only after dt_server_stop. */
+/* Admit a built graph.  A graph's device bytes are its arrays plus the heavy path's scratch of one
+ * query (dt_server_graph_info).  Without swap_to_host, DT_ENOMEM if it does not fit the budget
+ * next to the graphs already admitted.  With swap_to_host, any graph that fits the budget alone
+ * is admitted: if there is no room, its arrays are copied to host memory (pageable, owned by the
+ * graph) and its HBM freed at once; when a query needs a graph that is in host memory, the server
+ * moves the least recently used resident graphs that no batch on the device is using out to host
+ * memory until it fits, then copies it back (byte for byte: its ordering and schedule are kept).
+ * While such a server holds a graph, every other call that touches its device memory returns
+ * DT_EBUSY (dt_graph_stats still answers); after dt_server_stop a graph left in host memory
+ * returns to HBM on its next use.  The server does not take ownership: free the graph only after
+ * dt_server_stop. */
 int dt_server_add_graph(dt_server *s, dt_graph *g, uint32_t *graph_id);
 int dt_server_submit(dt_server *s, uint32_t graph_id, const dt_query *q, uint64_t *ticket);
 /* Wait for a ticket's counts; timeout_ns < 0 waits forever.  DT_ETIMEDOUT leaves the ticket
  * pending.  Each ticket can be waited for once. */
 int dt_server_wait(dt_server *s, uint64_t ticket, int64_t out[8], int64_t timeout_ns);
+/* Diagnostics of a server, host output: admitted graphs, those in HBM and their bytes (counted
+ * against budget_bytes), graphs moved to host memory and back so far with their bytes, and the
+ * queries answered (with any result code). */
+typedef struct {
+    uint64_t graphs, resident_graphs, resident_bytes, budget_bytes;
+    uint64_t swap_outs, swap_ins, swap_out_bytes, swap_in_bytes;
+    uint64_t queries_done;
+} dt_server_info;
+int dt_server_stats(dt_server *s, dt_server_info *out);
+/* Whether graph_id's arrays are in HBM now (*resident 1) and its device bytes as admitted. */
+int dt_server_graph_info(dt_server *s, uint32_t graph_id, int *resident, uint64_t *bytes);
 int dt_server_stop(dt_server *s);
 
 #ifdef __cplusplus

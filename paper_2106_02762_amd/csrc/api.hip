@@ -11,18 +11,6 @@ namespace {
 
 constexpr unsigned kBlock = 256;
 
-struct DeviceGuard {   // make the context's device current for the duration of a call
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 // node ids (a < b < c) of every resident triangle
 __global__ void k_tri_vertices(uint64_t nt, const uint32_t *__restrict__ tri, uint32_t n,
                                const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
@@ -72,11 +60,6 @@ int resolve_split(dt_graph *g, DevMem *tri) {
     return DT_OK;
 }
 
-int check_graph(const dt_graph *g, bool need_built) {
-    if (!g) return fail(DT_EINVAL, "null graph");
-    if (need_built && !g->built) return fail(DT_ENOTBUILT, "graph not built (call dt_graph_build)");
-    return DT_OK;
-}
 
 int load_common(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst,
                 const int64_t *t, bool on_device, dt_graph **out) {
@@ -118,6 +101,21 @@ int load_common(dt_ctx *ctx, uint32_t n, uint64_t m, const uint32_t *src, const 
 }
 
 }  // namespace
+
+int check_graph(const dt_graph *g, bool need_built, bool device) {
+    if (!g) return fail(DT_EINVAL, "null graph");
+    if (need_built && !g->built) return fail(DT_ENOTBUILT, "graph not built (call dt_graph_build)");
+    if (device && g->held_by)
+        return fail(DT_EBUSY, "the graph is held by a server that swaps graphs to host memory; "
+                              "count it through the server until dt_server_stop");
+    if (device && g->swapped) {
+        dt_graph *w = const_cast<dt_graph *>(g);   // the arrays come back unchanged
+        DeviceGuard dg(w->ctx->device);
+        DT_TRY(graph_swap_in(w, w->ctx->stream));
+    }
+    return DT_OK;
+}
+
 }  // namespace dt
 
 using namespace dt;
@@ -315,7 +313,7 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
 
 int dt_graph_stats(const dt_graph *g, dt_stats *out) {
     clear_error();
-    DT_TRY(check_graph(g, false));
+    DT_TRY(check_graph(g, false, false));
     if (!out) return fail(DT_EINVAL, "null output");
     memset(out, 0, sizeof(*out));
     out->n = g->n;

@@ -509,7 +509,7 @@ int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query
     for (uint64_t i = 0; i < k; ++i) {
         dt_graph *g = graphs[i];
         if (!g || g->ctx != ctx) return fail(DT_EINVAL, "batch entry %llu: graph of another context", (unsigned long long)i);
-        if (!g->built) return fail(DT_ENOTBUILT, "batch entry %llu: graph not built", (unsigned long long)i);
+        DT_TRY(check_graph(g, true));
         bool e = false;
         DT_TRY(normalise_query(g, &queries[i], &qs[i], &e));
         if ((g->sum_sigma3 >> 63) != 0) return fail(DT_EOVERFLOW, "batch entry %llu may overflow", (unsigned long long)i);

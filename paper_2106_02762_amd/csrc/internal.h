@@ -263,6 +263,11 @@ struct dt_graph {
     uint32_t light_cap_used = 0, cost_pct_used = 0;
     int tuned = 0;              // 1: the build's split and geometry came from the autotuner
     double ms_load = 0, ms_peel = 0, ms_orient = 0, ms_tri = 0, ms_sched = 0;
+    // host copies of the device arrays (in graph_arrays order) while the graph is out of HBM
+    std::vector<std::unique_ptr<uint8_t[]>> swap_host;
+    std::vector<size_t> swap_bytes;
+    bool swapped = false;
+    dt_server *held_by = nullptr;   // a server that swaps graphs holds its graphs until it stops
 };
 
 namespace dt {
@@ -370,7 +375,28 @@ int batch_tuned(dt_ctx *ctx, BatchRunner *r, uint64_t k, dt_graph *const *graphs
 int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]);
 bool batch_ready(BatchRunner *r);
 int batch_sync(BatchRunner *r);
+struct DeviceGuard {   // make the context's device current for the duration of a call
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
 uint64_t graph_device_bytes(const dt_graph *g);
+// Moves every device array of g to host memory (copies on stream st, then frees the device
+// memory) or back into HBM; g must have no device work outstanding.  On failure g is left as it
+// was.  graph_swap_in of a resident graph does nothing.
+int graph_swap_out(dt_graph *g, hipStream_t st);
+int graph_swap_in(dt_graph *g, hipStream_t st);
+// The checks every call on a graph makes: not null; built if need_built; and, when the call
+// touches device memory (device), not held by a swapping server, and in HBM (a graph left in host
+// memory by a stopped server is brought back here).
+int check_graph(const dt_graph *g, bool need_built, bool device = true);
 int count_batch(dt_ctx *ctx, uint64_t k, dt_graph *const *graphs, const dt_query *queries,
                 int64_t (*out)[8]);
 

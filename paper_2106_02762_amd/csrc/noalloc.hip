@@ -56,6 +56,8 @@ extern "C" int dt_count_noalloc(dt_graph *g, const dt_query *q, int64_t *out8, v
     if (!g) return fail(DT_EINVAL, "null graph");
     if (!g->built) return fail(DT_ENOTBUILT, "graph not built (call dt_graph_build)");
     if (!out8) return fail(DT_EINVAL, "null output");
+    if (g->held_by || g->swapped)   // (bringing it back would allocate)
+        return fail(DT_EBUSY, "the graph's arrays are in host memory or held by a swapping server");
     DQuery dq;
     bool empty = false;
     DT_TRY(normalise_query(g, q, &dq, &empty));

@@ -8,6 +8,11 @@
 // query its counts and wake its waiter.  Graphs are admitted against the server's HBM budget;
 // a query past its deadline before it reaches the device completes with DT_ETIMEDOUT; an invalid
 // query is refused at submission without touching the others.
+//
+// With host swapping, more graphs may be admitted than the budget holds: a graph that does not fit
+// waits in host memory, and when a query needs it the worker moves the least recently used
+// resident graphs that no batch on the device is using out to host memory until it fits, then
+// copies it back in (a query whose graph cannot be brought in yet waits for batches to finish).
 #include <chrono>
 #include <unordered_map>
 
@@ -15,18 +20,75 @@
 
 namespace dt {
 
+namespace {
+
+// every device array of a graph, in a fixed order (the order of its host copies while swapped)
+std::vector<DevMem *> graph_arrays(dt_graph *g) {
+    return {&g->sx, &g->sy, &g->row, &g->col, &g->ceid, &g->psid, &g->pdir, &g->pkey,
+            &g->pstart, &g->c1, &g->core, &g->rank, &g->order, &g->dag_row, &g->dag_col,
+            &g->eoff, &g->key, &g->sched.light, &g->sched.medium, &g->sched.mitems,
+            &g->sched.light_w, &g->sched.medium_w, &g->sched.mitems_w, &g->sched.heavy,
+            &g->sched.hslot, &g->sched.chunks, &g->sched.pchunks, &g->sched.mlev_w,
+            &g->sched.unit};
+}
+
+}  // namespace
+
 uint64_t graph_device_bytes(const dt_graph *g) {
-    const DevMem *ms[] = {&g->sx, &g->sy, &g->row, &g->col, &g->ceid, &g->psid, &g->pdir, &g->pkey,
-                          &g->pstart, &g->c1, &g->core, &g->rank, &g->order, &g->dag_row, &g->dag_col,
-                          &g->eoff, &g->key, &g->sched.light, &g->sched.medium, &g->sched.mitems,
-                          &g->sched.light_w, &g->sched.medium_w, &g->sched.mitems_w, &g->sched.heavy,
-                          &g->sched.hslot, &g->sched.chunks, &g->sched.pchunks, &g->sched.mlev_w,
-                          &g->sched.unit};
     uint64_t b = 0;
-    for (const DevMem *m : ms) b += m->bytes;
+    if (g->swapped) {
+        for (size_t x : g->swap_bytes) b += x;
+    } else {
+        for (const DevMem *m : graph_arrays(const_cast<dt_graph *>(g))) b += m->bytes;
+    }
     // scratch of the heavy path, taken per query in flight
     b += g->sched.n_slots * 8 * sizeof(int64_t) + g->sched.n_pchunks * 8 * sizeof(int64_t) + 48 * g->sched.n_heavy;
     return b;
+}
+
+int graph_swap_out(dt_graph *g, hipStream_t st) {
+    if (g->swapped) return DT_OK;
+    std::vector<DevMem *> arrs = graph_arrays(g);
+    std::vector<std::unique_ptr<uint8_t[]>> host(arrs.size());
+    std::vector<size_t> bytes(arrs.size(), 0);
+    for (size_t i = 0; i < arrs.size(); ++i) {
+        if (!arrs[i]->ptr) continue;
+        bytes[i] = arrs[i]->bytes;
+        host[i].reset(new (std::nothrow) uint8_t[bytes[i]]);
+        if (!host[i]) return fail(DT_ENOMEM, "no host memory for %zu bytes of a swapped graph", bytes[i]);
+        DT_HIP(hipMemcpyAsync(host[i].get(), arrs[i]->ptr, bytes[i], hipMemcpyDeviceToHost, st));
+    }
+    DT_HIP(hipStreamSynchronize(st));
+    for (DevMem *m : arrs) m->reset();
+    g->swap_host = std::move(host);
+    g->swap_bytes = std::move(bytes);
+    g->swapped = true;
+    return DT_OK;
+}
+
+int graph_swap_in(dt_graph *g, hipStream_t st) {
+    if (!g->swapped) return DT_OK;
+    std::vector<DevMem *> arrs = graph_arrays(g);
+    int rc = DT_OK;
+    for (size_t i = 0; i < arrs.size() && rc == DT_OK; ++i) {
+        if (!g->swap_bytes[i]) continue;
+        rc = dev_alloc(g->ctx, *arrs[i], g->swap_bytes[i], false);
+        if (rc == DT_OK && hipMemcpyAsync(arrs[i]->ptr, g->swap_host[i].get(), g->swap_bytes[i],
+                                          hipMemcpyHostToDevice, st) != hipSuccess)
+            rc = fail(DT_EDEVICE, "copy of a swapped graph back to the device failed");
+    }
+    if (rc == DT_OK && hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(DT_EDEVICE, "copy of a swapped graph back to the device failed");
+    if (rc != DT_OK) {
+        // the host copies stay: the graph is still swapped out
+        (void)hipStreamSynchronize(st);
+        for (DevMem *m : arrs) m->reset();
+        return rc;
+    }
+    g->swap_host.clear();
+    g->swap_bytes.clear();
+    g->swapped = false;
+    return DT_OK;
 }
 
 namespace {
@@ -47,11 +109,24 @@ struct Slot {
     BatchRunner *runner = nullptr;
     bool busy = false;
     std::vector<uint64_t> tickets;
+    std::vector<uint32_t> gids;
     std::vector<dt_graph *> graphs;
     std::vector<DQuery> qs;
     std::unique_ptr<bool[]> empty;
     size_t cap = 0;
 };
+
+// an admitted graph: its device bytes (with the heavy path's scratch), whether its arrays are in
+// HBM, the batches on the device that use it, and when a batch last took it
+struct Served {
+    dt_graph *g = nullptr;
+    uint64_t bytes = 0;
+    bool resident = true;
+    uint32_t users = 0;
+    uint64_t last_use = 0;
+};
+
+constexpr int kNoRoom = 1;   // make_resident: every graph that could move out is in use
 
 }  // namespace
 }  // namespace dt
@@ -62,7 +137,7 @@ struct dt_server {
     uint64_t budget = 0, used = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::vector<dt_graph *> graphs;
+    std::vector<dt::Served> graphs;
     std::deque<uint64_t> pending;
     std::unordered_map<uint64_t, dt::Ticket> tickets;
     uint64_t next_ticket = 1;
@@ -71,10 +146,18 @@ struct dt_server {
     int worker_rc = DT_OK;
     dt::Slot slots[dt::kSlots];
     std::thread worker;
+    hipStream_t copy = nullptr;   // the worker's swap copies
+    uint64_t clock = 0, swap_outs = 0, swap_ins = 0, swap_out_bytes = 0, swap_in_bytes = 0, done = 0;
 };
 
 namespace dt {
 namespace {
+
+// the slot's graphs are no longer used by a batch on the device (lock held)
+void release_graphs(dt_server *s, Slot &sl) {
+    for (uint32_t gid : sl.gids) s->graphs[gid].users--;
+    sl.gids.clear();
+}
 
 void complete_slot(dt_server *s, Slot &sl) {
     // called without the lock: results are in the runner's pinned buffer once `done` fired
@@ -91,8 +174,63 @@ void complete_slot(dt_server *s, Slot &sl) {
         t.done = true;
     }
     s->inflight -= (uint32_t)k;
+    s->done += k;
+    release_graphs(s, sl);
     sl.busy = false;
     sl.tickets.clear();
+    s->cv_done.notify_all();
+}
+
+// Brings graph gid into HBM, first moving least recently used resident graphs that no batch uses
+// out to host memory until it fits the budget.  Called by the worker with the lock held; releases
+// it during copies (only the worker moves graphs, and the graphs it moves are in no batch).
+// Returns DT_OK, kNoRoom (every graph that could move out is in use: wait for batches), or an error.
+int make_resident(dt_server *s, std::unique_lock<std::mutex> &lk, uint32_t gid) {
+    const uint64_t need = s->graphs[gid].bytes;
+    while (s->budget && s->used + need > s->budget) {
+        int victim = -1;
+        for (size_t i = 0; i < s->graphs.size(); ++i) {
+            const Served &e = s->graphs[i];
+            if (i == gid || !e.resident || e.users) continue;
+            if (victim < 0 || e.last_use < s->graphs[victim].last_use) victim = (int)i;
+        }
+        if (victim < 0) return kNoRoom;
+        dt_graph *vg = s->graphs[victim].g;
+        const uint64_t vb = s->graphs[victim].bytes;
+        s->graphs[victim].resident = false;
+        s->used -= vb;
+        lk.unlock();
+        const int rc = graph_swap_out(vg, s->copy);
+        lk.lock();
+        if (rc != DT_OK) {
+            s->graphs[victim].resident = true;
+            s->used += vb;
+            return rc;
+        }
+        s->swap_outs++;
+        s->swap_out_bytes += vb;
+    }
+    dt_graph *g = s->graphs[gid].g;
+    s->graphs[gid].resident = true;
+    s->used += need;
+    lk.unlock();
+    const int rc = graph_swap_in(g, s->copy);
+    lk.lock();
+    if (rc != DT_OK) {
+        s->graphs[gid].resident = false;
+        s->used -= need;
+        return rc;
+    }
+    s->swap_ins++;
+    s->swap_in_bytes += need;
+    return DT_OK;
+}
+
+void finish_ticket(dt_server *s, Ticket &t, int rc) {
+    t.rc = rc;
+    t.done = true;
+    s->inflight--;
+    s->done++;
     s->cv_done.notify_all();
 }
 
@@ -119,23 +257,38 @@ void worker_main(dt_server *s) {
         if (free_slot && !s->pending.empty()) {
             Slot &sl = *free_slot;
             sl.tickets.clear();
+            sl.gids.clear();
             sl.graphs.clear();
             sl.qs.clear();
             const auto now = std::chrono::steady_clock::now();
             while (!s->pending.empty() && sl.tickets.size() < max_batch) {
-                uint64_t id = s->pending.front();
-                s->pending.pop_front();
-                Ticket &t = s->tickets[id];
+                const uint64_t id = s->pending.front();
+                Ticket &t = s->tickets[id];   // (references into the map survive its rehashing)
                 if (deadline > 0 &&
                     std::chrono::duration_cast<std::chrono::nanoseconds>(now - t.submitted).count() > deadline) {
-                    t.rc = fail(DT_ETIMEDOUT, "query passed its deadline before reaching the device");
-                    t.done = true;
-                    s->inflight--;
-                    s->cv_done.notify_all();
+                    s->pending.pop_front();
+                    finish_ticket(s, t, fail(DT_ETIMEDOUT, "query passed its deadline before reaching the device"));
+                    progressed = true;
                     continue;
                 }
+                const uint32_t gid = t.gid;
+                if (!s->graphs[gid].resident) {
+                    const int rc = make_resident(s, lk, gid);
+                    if (rc == kNoRoom) break;   // run what is taken; the rest waits for room
+                    if (rc != DT_OK) {
+                        s->pending.pop_front();
+                        finish_ticket(s, t, rc);
+                        progressed = true;
+                        continue;
+                    }
+                }
+                s->pending.pop_front();
+                Served &e = s->graphs[gid];
+                e.users++;
+                e.last_use = ++s->clock;
                 sl.tickets.push_back(id);
-                sl.graphs.push_back(s->graphs[t.gid]);
+                sl.gids.push_back(gid);
+                sl.graphs.push_back(e.g);
                 sl.qs.push_back(t.q);
             }
             const size_t k = sl.tickets.size();
@@ -160,12 +313,14 @@ void worker_main(dt_server *s) {
                         t.done = true;
                     }
                     s->inflight -= (uint32_t)k;
+                    s->done += k;
+                    release_graphs(s, sl);
                     sl.busy = false;
                     sl.tickets.clear();
                     s->cv_done.notify_all();
                 }
+                progressed = true;
             }
-            progressed = true;
         }
         bool any_busy = false;
         for (Slot &sl : s->slots) any_busy |= sl.busy;
@@ -174,8 +329,9 @@ void worker_main(dt_server *s) {
         if (any_busy) {
             bool all_busy = true;
             for (Slot &sl : s->slots) all_busy &= sl.busy;
-            if (all_busy) {
-                // nothing can start until a runner frees: wait for the oldest on the device
+            if (all_busy || !s->pending.empty()) {
+                // nothing can start until a batch ends (no runner free, or the waiting queries'
+                // graphs need room that batches on the device hold): wait for the oldest
                 Slot *first = nullptr;
                 for (Slot &sl : s->slots)
                     if (sl.busy) { first = &sl; break; }
@@ -202,6 +358,7 @@ int dt_server_start(dt_ctx *ctx, const dt_server_cfg *cfg, dt_server **out) {
     clear_error();
     if (!ctx || !out) return fail(DT_EINVAL, "null context or output handle");
     *out = nullptr;
+    if (cfg && cfg->swap_to_host > 1) return fail(DT_EINVAL, "swap_to_host is 0 or 1");
     dt_server *s = new dt_server();
     s->ctx = ctx;
     if (cfg) s->cfg = *cfg;
@@ -209,14 +366,17 @@ int dt_server_start(dt_ctx *ctx, const dt_server_cfg *cfg, dt_server **out) {
     if (!s->cfg.max_batch) s->cfg.max_batch = 512;
     s->budget = s->cfg.hbm_budget_bytes ? s->cfg.hbm_budget_bytes : ctx->budget;
     (void)hipSetDevice(ctx->device);
-    for (Slot &sl : s->slots) {
-        int rc = make_batch_runner(ctx, &sl.runner);
-        if (rc != DT_OK) {
-            for (Slot &x : s->slots)
-                if (x.runner) destroy_batch_runner(x.runner);
-            delete s;
-            return rc;
-        }
+    int rc = DT_OK;
+    if (hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(DT_EDEVICE, "hipStreamCreateWithFlags failed");
+    for (Slot &sl : s->slots)
+        if (rc == DT_OK) rc = make_batch_runner(ctx, &sl.runner);
+    if (rc != DT_OK) {
+        for (Slot &x : s->slots)
+            if (x.runner) destroy_batch_runner(x.runner);
+        if (s->copy) (void)hipStreamDestroy(s->copy);
+        delete s;
+        return rc;
     }
     s->worker = std::thread(worker_main, s);
     *out = s;
@@ -227,14 +387,38 @@ int dt_server_add_graph(dt_server *s, dt_graph *g, uint32_t *graph_id) {
     clear_error();
     if (!s || !g || !graph_id) return fail(DT_EINVAL, "null argument");
     if (g->ctx != s->ctx) return fail(DT_EINVAL, "graph belongs to another context");
-    if (!g->built) return fail(DT_ENOTBUILT, "graph not built");
+    if (g->held_by) return fail(DT_EBUSY, "graph is already held by a server that swaps graphs");
+    DT_TRY(check_graph(g, true));   // (a graph a stopped server left in host memory comes back)
     const uint64_t bytes = graph_device_bytes(g);
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->budget && s->used + bytes > s->budget)
+    const bool swap = s->cfg.swap_to_host != 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (swap)
+        for (const Served &e : s->graphs)
+            if (e.g == g) return fail(DT_EINVAL, "graph already admitted");
+    const bool fits = !s->budget || s->used + bytes <= s->budget;
+    if (!fits && (!swap || bytes > s->budget))
         return fail(DT_ENOMEM, "graph needs %llu bytes; %llu of the server's %llu are in use",
                     (unsigned long long)bytes, (unsigned long long)s->used, (unsigned long long)s->budget);
-    s->used += bytes;
-    s->graphs.push_back(g);
+    Served e;
+    e.g = g;
+    e.bytes = bytes;
+    e.resident = fits;
+    if (!fits) {
+        // the graph waits in host memory until a query needs it (it is in no batch yet, and the
+        // caller's work on it is finished once the context's stream is)
+        lk.unlock();
+        DeviceGuard dg(s->ctx->device);
+        DT_TRY(relayout_join(g));
+        DT_HIP(hipStreamSynchronize(s->ctx->stream));
+        DT_TRY(graph_swap_out(g, s->ctx->stream));
+        lk.lock();
+        s->swap_outs++;
+        s->swap_out_bytes += bytes;
+    } else {
+        s->used += bytes;
+    }
+    if (swap) g->held_by = s;
+    s->graphs.push_back(e);
     *graph_id = (uint32_t)(s->graphs.size() - 1);
     return DT_OK;
 }
@@ -246,10 +430,10 @@ int dt_server_submit(dt_server *s, uint32_t graph_id, const dt_query *q, uint64_
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (graph_id >= s->graphs.size()) return fail(DT_EINVAL, "unknown graph id %u", graph_id);
-        g = s->graphs[graph_id];
+        g = s->graphs[graph_id].g;
     }
     Ticket t;
-    DT_TRY(normalise_query(g, q, &t.q, &t.empty));
+    DT_TRY(normalise_query(g, q, &t.q, &t.empty));   // (host fields only)
     if ((g->sum_sigma3 >> 63) != 0) return fail(DT_EOVERFLOW, "counts of this graph may not fit int64");
     t.empty = t.empty || g->n_tri == 0;
     t.gid = graph_id;
@@ -287,6 +471,34 @@ int dt_server_wait(dt_server *s, uint64_t ticket, int64_t out[8], int64_t timeou
     return DT_OK;
 }
 
+int dt_server_stats(dt_server *s, dt_server_info *out) {
+    clear_error();
+    if (!s || !out) return fail(DT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    dt_server_info r{};
+    r.graphs = s->graphs.size();
+    for (const Served &e : s->graphs) r.resident_graphs += e.resident ? 1 : 0;
+    r.resident_bytes = s->used;
+    r.budget_bytes = s->budget;
+    r.swap_outs = s->swap_outs;
+    r.swap_ins = s->swap_ins;
+    r.swap_out_bytes = s->swap_out_bytes;
+    r.swap_in_bytes = s->swap_in_bytes;
+    r.queries_done = s->done;
+    *out = r;
+    return DT_OK;
+}
+
+int dt_server_graph_info(dt_server *s, uint32_t graph_id, int *resident, uint64_t *bytes) {
+    clear_error();
+    if (!s || !resident || !bytes) return fail(DT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id >= s->graphs.size()) return fail(DT_EINVAL, "unknown graph id %u", graph_id);
+    *resident = s->graphs[graph_id].resident ? 1 : 0;
+    *bytes = s->graphs[graph_id].bytes;
+    return DT_OK;
+}
+
 int dt_server_stop(dt_server *s) {
     clear_error();
     if (!s) return fail(DT_EINVAL, "null server");
@@ -298,6 +510,10 @@ int dt_server_stop(dt_server *s) {
     if (s->worker.joinable()) s->worker.join();
     for (Slot &sl : s->slots)
         if (sl.runner) destroy_batch_runner(sl.runner);
+    // the graphs go back to the caller; one left in host memory returns to HBM on its next use
+    for (Served &e : s->graphs)
+        if (e.g->held_by == s) e.g->held_by = nullptr;
+    if (s->copy) (void)hipStreamDestroy(s->copy);
     delete s;
     return DT_OK;
 }

@@ -32,8 +32,8 @@ ENTRY_POINTS = (
     "dt_graph_load", "dt_graph_load_device", "dt_graph_build", "dt_graph_set_tuning",
     "dt_graph_stats", "dt_count", "dt_count_async", "dt_count_noalloc", "dt_count_visits", "dt_count_cells", "dt_count_oneshot", "dt_count_sweep", "dt_count_batch",
     "dt_graph_order", "dt_graph_triangles", "dt_graph_free", "dt_server_start",
-    "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stop",
-    "dt_ctx_set_profiling", "dt_ctx_last_profile", "dt_ctx_batch_tuning",
+    "dt_server_add_graph", "dt_server_submit", "dt_server_wait", "dt_server_stats",
+    "dt_server_graph_info", "dt_server_stop", "dt_ctx_set_profiling", "dt_ctx_last_profile", "dt_ctx_batch_tuning",
 )
 PROFILE_SLOTS = ("peel", "relayout", "tri_count", "tri_fill", "light", "heavy_prefix",
                  "heavy_count", "reduce", "medium", "unit", "peel_adj", "peel_tail", "core")
@@ -83,7 +83,14 @@ class dt_tuning(ctypes.Structure):
 
 class dt_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight_queries", ctypes.c_uint32),
-                ("max_batch", ctypes.c_uint32), ("deadline_ns", ctypes.c_int64)]
+                ("max_batch", ctypes.c_uint32), ("deadline_ns", ctypes.c_int64),
+                ("swap_to_host", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class dt_server_info(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "graphs", "resident_graphs", "resident_bytes", "budget_bytes", "swap_outs", "swap_ins",
+        "swap_out_bytes", "swap_in_bytes", "queries_done")]
 
 
 _lib = None
@@ -132,6 +139,8 @@ def library():
         "dt_server_add_graph": (I, [P, P, ctypes.POINTER(U32)]),
         "dt_server_submit": (I, [P, U32, ctypes.POINTER(dt_query), ctypes.POINTER(U64)]),
         "dt_server_wait": (I, [P, U64, P, I64]),
+        "dt_server_stats": (I, [P, ctypes.POINTER(dt_server_info)]),
+        "dt_server_graph_info": (I, [P, U32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(U64)]),
         "dt_server_stop": (I, [P]),
         "dt_ctx_set_profiling": (I, [P, I]),
         "dt_ctx_last_profile": (I, [P, P]),
@@ -342,9 +351,10 @@ def dt_ctx_last_profile(ctx):
     return {k: float(v) for k, v in zip(PROFILE_SLOTS, ms)}
 
 
-def dt_server_start(ctx, hbm_budget_bytes=0, max_inflight_queries=0, max_batch=0, deadline_ns=0):
+def dt_server_start(ctx, hbm_budget_bytes=0, max_inflight_queries=0, max_batch=0, deadline_ns=0,
+                    swap_to_host=0):
     cfg = dt_server_cfg(int(hbm_budget_bytes), int(max_inflight_queries), int(max_batch),
-                        int(deadline_ns))
+                        int(deadline_ns), int(swap_to_host), 0)
     h = ctypes.c_void_p()
     _check(library().dt_server_start(ctx, ctypes.byref(cfg), ctypes.byref(h)), "dt_server_start")
     return h
@@ -369,6 +379,21 @@ def dt_server_wait(server, ticket, timeout_ns=-1):
     _check(library().dt_server_wait(server, int(ticket), out.ctypes.data, int(timeout_ns)),
            "dt_server_wait")
     return out
+
+
+def dt_server_stats(server):
+    st = dt_server_info()
+    _check(library().dt_server_stats(server, ctypes.byref(st)), "dt_server_stats")
+    return {k: getattr(st, k) for k, _ in dt_server_info._fields_}
+
+
+def dt_server_graph_info(server, graph_id):
+    """(resident, device bytes) of an admitted graph."""
+    r = ctypes.c_int()
+    b = ctypes.c_uint64()
+    _check(library().dt_server_graph_info(server, int(graph_id), ctypes.byref(r), ctypes.byref(b)),
+           "dt_server_graph_info")
+    return bool(r.value), b.value
 
 
 def dt_server_stop(server):
