@@ -129,7 +129,7 @@ typedef struct {
                                       2: every triangle heavy; 3: every triangle medium
                                       (diagnostics and tests)                                     */
     uint32_t peel_tail;            /* the level peel hands the last peel_tail vertices to one
-                                      workgroup (default and at most 16384; 1 keeps every level
+                                      workgroup (default and at most 16320; 1 keeps every level
                                       on the whole grid); read by the next dt_graph_build        */
     uint32_t order_method;         /* 0: the level-by-level core peel (default); 1: core numbers
                                       by h-index iteration, then every shell peeled at once.

@@ -292,7 +292,7 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     if (tu->medium_pair_cap) nt.medium_pair_cap = tu->medium_pair_cap;
     if (tu->force_path > 3) return fail(DT_EINVAL, "force_path must be 0, 1, 2 or 3");
     nt.force_path = tu->force_path;
-    if (tu->peel_tail > 16384) return fail(DT_EINVAL, "peel_tail must be at most 16384");
+    if (tu->peel_tail > kPeelTailMax) return fail(DT_EINVAL, "peel_tail must be at most %u", kPeelTailMax);
     if (tu->peel_tail) nt.peel_tail = tu->peel_tail;
     if (tu->order_method > 1) return fail(DT_EINVAL, "order_method must be 0 or 1");
     nt.order_method = tu->order_method;

@@ -375,6 +375,10 @@ int batch_tuned(dt_ctx *ctx, BatchRunner *r, uint64_t k, dt_graph *const *graphs
 int batch_wait(BatchRunner *r, uint64_t k, const bool *empty, int64_t (*out)[8]);
 bool batch_ready(BatchRunner *r);
 int batch_sync(BatchRunner *r);
+// the most vertices the level peel hands to its one-workgroup finish (the LDS of one workgroup
+// holds their local CSR rows, degrees, queue and live list)
+constexpr uint32_t kPeelTailMax = 16320;
+
 struct DeviceGuard {   // make the context's device current for the duration of a call
     int prev = -1;
     explicit DeviceGuard(int dev) {

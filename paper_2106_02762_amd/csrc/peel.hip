@@ -42,12 +42,13 @@ constexpr unsigned kGridWide = 256;    // blocks while at least kWideUntil verti
 constexpr uint32_t kWideUntil = 1000000;   // measured best on the 61M-edge graph (0.3M: +0.5 ms)
 constexpr unsigned kGridMid = 64;      // blocks while at least kMidUntil vertices remain
 constexpr uint32_t kMidUntil = 200000;   // 0.1M-0.4M and 128 blocks measured alike
-constexpr uint32_t kTail = 16384;   // most vertices the one-workgroup finish takes (16-bit ids)
+constexpr uint32_t kTail = kPeelTailMax;   // most vertices the one-workgroup finish takes (16-bit ids)
 // LDS of a peel block.  The one-workgroup finish keeps there the local CSR rows (kTail + 1
-// words), the degrees (16-bit, two per word), the queue of local ids (16-bit) and a removed-vertex
-// bitmap; on the grid the same words stage the vertices a block queues in one round.
-constexpr uint32_t kRowWords = kTail + 1, kDegWords = kTail / 2, kQWords = kTail / 2, kRemWords = kTail / 32;
-constexpr uint32_t kLdsWords = kRowWords + kDegWords + kQWords + kRemWords;
+// words), the degrees (16-bit, two per word), the removal queue and the list of vertices not yet
+// queued (16-bit local ids); on the grid the same words stage the vertices a block queues in one
+// round.
+constexpr uint32_t kRowWords = kTail + 1, kDegWords = kTail / 2, kQWords = kTail / 2, kLiveWords = kTail / 2;
+constexpr uint32_t kLdsWords = kRowWords + kDegWords + kQWords + kLiveWords;
 // on the grid the words hold two staging halves: the vertices a block is removing and those their
 // removal queues
 constexpr uint32_t kStage = kLdsWords / 2;
@@ -165,12 +166,19 @@ __device__ __forceinline__ void remove_edges(uint32_t v, uint32_t first, uint32_
 }
 
 // The last vertices: one workgroup finishes the peel on the subgraph they induce, with local
-// (16-bit) vertex ids.  The local CSR rows, the degrees, the removal queue and a removed bitmap
-// live in LDS, so a round touches global memory only to read adjacency (lcol); workgroup barriers
-// separate rounds.  rlist maps local ids to vertices.  Degrees count the neighbours not yet
-// removed, so a decrement never takes one below zero and two 16-bit degrees share a word safely.
-// The queue positions (continuing from qbase) and the core numbers are written at the end, from
-// the queue and the level boundaries recorded in lvl (pairs: first queue position, level).
+// (16-bit) vertex ids.  The local CSR rows, the degrees, the removal queue and the list of vertices
+// not yet queued live in LDS, so a round touches global memory only to read adjacency (lcol);
+// workgroup barriers separate rounds.  rlist maps local ids to vertices.  A degree counts the
+// neighbours not yet removed (so it never falls below zero, and two 16-bit degrees share a word
+// safely) until the vertex is queued; queuing adds kMark - degree, which puts it at kMark, and
+// the at most kTail later decrements leave it at least kMark - kTail, above every level.  Each
+// wavefront keeps its own segment of the live list and compacts it in place at every level scan,
+// so a scan reads only the vertices still live, and takes one atomic per wavefront for the
+// survivors' count and smallest degree.  The queue positions (continuing from qbase) and the core
+// numbers are written at the end, from the queue and the level boundaries recorded in lvl (pairs:
+// first queue position, level).
+constexpr uint32_t kMark = 0xC000u, kMarked = 0x8000u;
+static_assert(kMark - kTail > kMarked && kMarked > kTail, "queued degrees stay above every level");
 __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t rounds,
                           const uint32_t *__restrict__ rlist, const uint32_t *__restrict__ lrow,
                           const uint16_t *__restrict__ lcol, uint32_t *__restrict__ lvl,
@@ -178,15 +186,15 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
                           uint32_t *s_mem) {
     uint32_t *s_row = s_mem;                                              // kRowWords
     uint32_t *s_deg = s_mem + kRowWords;                                  // kDegWords
-    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_mem + kRowWords + kDegWords);   // kTail
-    uint32_t *s_rem = s_mem + kRowWords + kDegWords + kQWords;            // kRemWords
+    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_mem + kRowWords + kDegWords);               // kTail
+    uint16_t *s_live = reinterpret_cast<uint16_t *>(s_mem + kRowWords + kDegWords + kQWords);  // kTail
     __shared__ unsigned s_qt, s_keep, s_min, s_nlvl;
     const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid / 64;
     constexpr unsigned kWaves = kBlock / 64;
     const uint64_t below = (1ull << lane) - 1;
     for (uint32_t l = tid; l <= R; l += kBlock) s_row[l] = lrow[l];
     for (uint32_t w = tid; w < kDegWords; w += kBlock) s_deg[w] = 0;
-    for (uint32_t w = tid; w < kRemWords; w += kBlock) s_rem[w] = 0;
+    for (uint32_t l = tid; l < R; l += kBlock) s_live[l] = (uint16_t)l;
     __syncthreads();
     for (uint32_t l = tid; l < R; l += kBlock)
         atomicAdd(&s_deg[l >> 1], (s_row[l + 1] - s_row[l]) << ((l & 1) * 16));
@@ -194,14 +202,20 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
         s_qt = 0;
         s_nlvl = 0;
     }
+    // this wavefront's segment of the live list: [lb, lb + lc)
+    const uint32_t seg = (R + kWaves - 1) / kWaves;
+    const uint32_t lb = wave * seg < R ? wave * seg : R;
+    uint32_t lc = (lb + seg < R ? lb + seg : R) - lb;
     uint32_t h = 0, t = 0;
     auto deg_of = [&](uint32_t l) { return (s_deg[l >> 1] >> ((l & 1) * 16)) & 0xffffu; };
+    // queue y, whose degree is d (no decrement of y runs between reading d and this)
+    auto mark = [&](uint32_t y, uint32_t d) { atomicAdd(&s_deg[y >> 1], (kMark - d) << ((y & 1) * 16)); };
     // remove one edge end at y; a degree taken from k + 1 to k queues y
     auto dec = [&](uint32_t y, uint32_t kk) {
         const uint32_t sh = (y & 1) * 16;
         const uint32_t old = (atomicSub(&s_deg[y >> 1], 1u << sh) >> sh) & 0xffffu;
         if (old == kk + 1) {
-            atomicOr(&s_rem[y >> 5], 1u << (y & 31));
+            atomicAdd(&s_deg[y >> 1], (kMark - kk) << sh);
             const uint32_t p = atomicAdd(&s_qt, 1u);
             if (p < R) s_q[p] = (uint16_t)y;
         }
@@ -214,24 +228,41 @@ __device__ void peel_tail(uint32_t R, uint32_t qbase, uint32_t k, uint32_t round
         }
         __syncthreads();
         const uint32_t level_start = t;
-        // level scan over all local vertices not yet removed
-        for (uint32_t b0 = wave * 64; b0 < R; b0 += kWaves * 64) {
-            const uint32_t l = b0 + lane;
-            const bool live = l < R && !((s_rem[l >> 5] >> (l & 31)) & 1u);
-            const uint32_t d = live ? deg_of(l) : 0u;
-            const bool tk = live && d <= k, kp = live && d > k;
-            const uint64_t mt = __ballot(tk), mk = __ballot(kp);
-            uint32_t qb = 0;
-            if (lane == 0 && mt) qb = atomicAdd(&s_qt, (unsigned)__popcll(mt));
-            qb = __shfl(qb, 0, 64);
-            if (tk) {
-                const uint32_t p = qb + (uint32_t)__popcll(mt & below);
-                atomicOr(&s_rem[l >> 5], 1u << (l & 31));
-                if (p < R) s_q[p] = (uint16_t)l;
+        // level scan over this wavefront's live vertices: queue those of degree <= k, keep the
+        // others (written back in place: a survivor's new slot is never after its old one, and
+        // the wavefront reads a chunk before it writes any of it)
+        {
+            uint32_t nk = 0;
+            unsigned md = 0xffffffffu;
+            for (uint32_t i0 = 0; i0 < lc; i0 += 64) {
+                const uint32_t i = i0 + lane;
+                uint32_t l = 0, d = kMark;
+                if (i < lc) {
+                    l = s_live[lb + i];
+                    d = deg_of(l);
+                }
+                const bool tk = d <= k, kp = d > k && d < kMarked;
+                const uint64_t mt = __ballot(tk), mk = __ballot(kp);
+                if (mt) {
+                    uint32_t qb = 0;
+                    if (lane == 0) qb = atomicAdd(&s_qt, (unsigned)__popcll(mt));
+                    qb = __shfl(qb, 0, 64);
+                    if (tk) {
+                        const uint32_t p = qb + (uint32_t)__popcll(mt & below);
+                        mark(l, d);
+                        if (p < R) s_q[p] = (uint16_t)l;
+                    }
+                }
+                if (kp) {
+                    s_live[lb + nk + (uint32_t)__popcll(mk & below)] = (uint16_t)l;
+                    md = d < md ? d : md;
+                }
+                nk += (uint32_t)__popcll(mk);
             }
-            const unsigned md = wave_min(kp ? d : 0xffffffffu);
-            if (lane == 0 && mk) {
-                atomicAdd(&s_keep, (unsigned)__popcll(mk));
+            lc = nk;
+            md = wave_min(md);
+            if (lane == 0 && nk) {
+                atomicAdd(&s_keep, nk);
                 atomicMin(&s_min, md);
             }
         }
@@ -329,6 +360,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     unsigned btarget = 0;   // arrivals that complete the next barrier, less its participants
     __shared__ __attribute__((aligned(16))) uint32_t s_mem[kLdsWords];
     __shared__ unsigned s_cnt, s_base;
+    __shared__ unsigned s_wct[kBlock / 64], s_wck[kBlock / 64], s_wmd[kBlock / 64], s_bq, s_bk;
 
     // the host cleared the control block; initialise per-vertex state
     for (uint32_t v = gtid; v < n; v += gsize) {
@@ -350,10 +382,11 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
     // here every queued vertex has been removed: n - tail vertices remain
     while (n - tail > tail_cap) {
         // level scan: queue every remaining vertex of degree <= k, keep the others.  Each
-        // wavefront takes a contiguous segment, counts its picks, reserves room in both lists with
-        // one atomic each, then writes its picks in order (no degree changes during a scan), so
-        // both lists keep the roughly ascending vertex order of the previous one and the degree
-        // reads of the next scan stay coalesced.
+        // wavefront takes a contiguous segment and counts its picks and survivors; its block
+        // reserves room for all of them in both lists (one atomic each), and each wavefront then
+        // writes its picks in order (no degree changes during a scan), so both lists keep the
+        // roughly ascending vertex order of the previous one and the degree reads of the next scan
+        // stay coalesced.
         {
             const uint32_t seg = ((n_alive + nwaves - 1) / nwaves + 63) & ~63u;
             const uint32_t sb = gwave * seg < n_alive ? gwave * seg : n_alive;
@@ -369,14 +402,32 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
                 mdl = keep && (unsigned)d < mdl ? (unsigned)d : mdl;
             }
             mdl = wave_min(mdl);
-            uint32_t qb = 0, kb = 0;
+            // one reservation per block (the wavefronts' segments are consecutive, so a prefix
+            // over them keeps the order): thousands of wavefronts meeting at the same counters
+            // would serialise there
+            const unsigned wv = threadIdx.x / 64;
             if (lane == 0) {
-                if (ct) qb = tail + atomicAdd(&ctl->qc[ph % 3], ct);
-                if (ck) kb = atomicAdd(&ctl->scan[lv % 3][0], ck);
-                if (mdl != 0xffffffffu) atomicMin(&ctl->scan[lv % 3][1], mdl);
+                s_wct[wv] = ct;
+                s_wck[wv] = ck;
+                s_wmd[wv] = mdl;
             }
-            qb = __shfl(qb, 0, 64);
-            kb = __shfl(kb, 0, 64);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned tct = 0, tck = 0, bmd = 0xffffffffu;
+                for (unsigned w = 0; w < kBlock / 64; ++w) {
+                    const unsigned a = s_wct[w], b = s_wck[w];
+                    s_wct[w] = tct;
+                    s_wck[w] = tck;
+                    tct += a;
+                    tck += b;
+                    bmd = s_wmd[w] < bmd ? s_wmd[w] : bmd;
+                }
+                s_bq = tct ? tail + atomicAdd(&ctl->qc[ph % 3], tct) : 0u;
+                s_bk = tck ? atomicAdd(&ctl->scan[lv % 3][0], tck) : 0u;
+                if (bmd != 0xffffffffu) atomicMin(&ctl->scan[lv % 3][1], bmd);
+            }
+            __syncthreads();
+            uint32_t qb = s_bq + s_wct[wv], kb = s_bk + s_wck[wv];
             if (ct | ck) {
                 for (uint32_t b0 = sb; b0 < se; b0 += 64) {
                     const uint32_t i = b0 + lane;

@@ -2,7 +2,7 @@
 numbers, then every shell peeled at once) on the graph of shapes and one power-law graph; the
 default level-by-level peel in its regimes:
 the whole peel on the cooperative grid (peel_tail = 1), the whole peel in one workgroup (graphs of
-at most 16384 vertices), the grid handing its last vertices to one workgroup, and (on a 600K-vertex
+at most 16320 vertices), the grid handing its last vertices to one workgroup, and (on a 600K-vertex
 graph) the full-width grid for the first levels before the narrow one.  A graph of shapes covers
 the second method's row kinds and histogram passes (hubs of 2,000 and 20,000 neighbours, a clique,
 a long path whose bounds and removals travel one hop per phase, isolated vertices).  Core numbers
@@ -114,7 +114,7 @@ def test_peel_regimes_match_oracle(ctx, name):
         q = (3600, 3600, 3600, dt.INT64_MIN, INF)
     elif name == "scaled":
         g = synth.plain_full(n=60_000, ms=800_000)       # grid, then one workgroup
-        tails = [0, 1, 100, 16384]
+        tails = [0, 1, 100, 16320]
         q = (3600, 3600, 3600, dt.INT64_MIN, INF)
     elif name == "batch5":
         g = synth.batch_graph(5)                          # n = 48,229
@@ -144,7 +144,7 @@ def test_peel_tail_is_validated(ctx):
     h = dt.dt_graph_load(ctx, g.n, g.src, g.dst, g.t)
     try:
         with pytest.raises(dt.DtError) as e:
-            dt.dt_graph_set_tuning(h, peel_tail=16385)
+            dt.dt_graph_set_tuning(h, peel_tail=16321)
         assert e.value.code == dt.DT_EINVAL
         with pytest.raises(dt.DtError) as e:
             dt.dt_graph_set_tuning(h, order_method=2)
