@@ -335,6 +335,9 @@ def main():
                           "count_ms": round(statistics.median(ts[1:]), 4),
                           "kernel_ms_step": {k: round(float(np.mean([p[k] for p in prof])), 4) for k in prof[0]},
                           "kernel_ms_count": {k: round(float(v), 4) for k, v in pk.items() if v > 0},
+                          "build_ms": {"peel": round(st["ms_peel"], 3), "orient": round(st["ms_orient"], 3),
+                                       "triangles": round(st["ms_triangles"], 3),
+                                       "schedule": round(st["ms_schedule"], 3)},
                           "stats": {k: v for k, v in st.items() if isinstance(v, int)}}), flush=True)
         dt.dt_graph_free(h)
         dt.dt_ctx_destroy(ctx)

@@ -18,8 +18,8 @@
 // barriers only), so a grid round usually ends a level; only vertices queued past a full staging
 // list wait for another round.  The first levels remove most of the graph and are bound by work,
 // the later ones by latency, and a barrier's cost grows with the number of blocks that meet at it:
-// the grid starts with one block of 1024 threads per CU and narrows to 64, then 32 blocks as
-// vertices run out.  The barrier is a monotonic arrival counter that every block polls.  Counters
+// the grid starts with one block of 1024 threads per CU and narrows to 128, 64, then 32 blocks
+// as vertices run out.  The barrier is a monotonic arrival counter that every block polls.  Counters
 // that decide the next step (queue positions taken in a phase, survivors of a level scan) rotate
 // over three slots, so a fast block starting the next phase never changes what a slow block reads,
 // and every block takes the same branch.  A vertex is queued at most
@@ -37,11 +37,15 @@ namespace dt {
 namespace {
 
 constexpr unsigned kBlock = 1024;
-constexpr unsigned kGridBlocks = 32;   // blocks of the latency-bound levels
-constexpr unsigned kGridWide = 256;    // blocks while at least kWideUntil vertices remain
-constexpr uint32_t kWideUntil = 1000000;   // measured best on the 61M-edge graph (0.3M: +0.5 ms)
-constexpr unsigned kGridMid = 64;      // blocks while at least kMidUntil vertices remain
-constexpr uint32_t kMidUntil = 200000;   // 0.1M-0.4M and 128 blocks measured alike
+constexpr unsigned kGridWide = 256;    // blocks of the first levels
+// the grid narrows as vertices run out: blocks while at least `from` vertices remain (timed per
+// phase on the 61M-edge graph: one width for all of them below 200,000 vertices, 16 or 8 blocks
+// there, and 256 blocks down to 16,000 vertices were all slower)
+struct Width {
+    uint32_t from;
+    unsigned blocks;
+};
+constexpr Width kWidths[4] = {{1000000, kGridWide}, {200000, 128}, {50000, 64}, {0, 32}};
 constexpr uint32_t kTail = kPeelTailMax;   // most vertices the one-workgroup finish takes (16-bit ids)
 // LDS of a peel block.  The one-workgroup finish keeps there the local CSR rows (kTail + 1
 // words), the degrees (16-bit, two per word), the removal queue and the list of vertices not yet
@@ -349,8 +353,7 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
        uint32_t *__restrict__ rlist, uint32_t *__restrict__ lrow, uint32_t *__restrict__ lvl,
        uint16_t *__restrict__ lcol, uint64_t lcol_cap, uint32_t tail_cap, uint32_t *__restrict__ ovf0,
        uint32_t *__restrict__ ovf1, PeelCtl *__restrict__ ctl) {
-    // the whole grid takes part while many vertices remain, then the first kGridMid blocks, then
-    // the first kGridBlocks
+    // the whole grid takes part while many vertices remain, then ever fewer of its first blocks
     unsigned nblk = gridDim.x;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     uint32_t gsize = nblk * kBlock;
@@ -464,9 +467,14 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
         ++lv;
         ++ph;
         // few vertices left: the later levels are latency-bound, and a barrier costs more the
-        // more blocks meet at it, so the grid narrows in two steps (only ever narrows)
+        // more blocks meet at it, so the grid narrows in steps (only ever narrows)
         {
-            const unsigned want = na2 >= kWideUntil ? kGridWide : (na2 >= kMidUntil ? kGridMid : kGridBlocks);
+            unsigned want = kWidths[3].blocks;
+            for (const Width &w : kWidths)
+                if (na2 >= w.from) {
+                    want = w.blocks;
+                    break;
+                }
             if (want < nblk) {
                 if (blockIdx.x >= want) return;
                 nblk = want;
