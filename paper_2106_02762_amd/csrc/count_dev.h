@@ -364,18 +364,8 @@ constexpr uint64_t kLightVw = 64;
 // The unit record of triangle (e_uv, e_uw, e_vw), each pair holding one temporal edge: the edge's
 // key sits at eoff[2e] whichever its direction; the direction bit is 1 (towards the earlier vertex
 // of u < v < w) when the pair's forward part [eoff[2e], eoff[2e+1]) is empty.
-__device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint32_t e_vw,
-                                             const uint32_t *__restrict__ eoff,
-                                             const uint64_t *__restrict__ key, int shift) {
-    const uint32_t es[3] = {e_uv, e_uw, e_vw};
-    uint64_t k[3];
-    int dir[3];
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1];
-        k[p] = key[a];
-        dir[p] = a == b ? 1 : 0;
-    }
+// the record from the three edges' keys and directions (1: head -> tail), pairs uv, uw, vw
+__device__ __forceinline__ uint4 unit_record_of(const uint64_t (&k)[3], const int (&dir)[3], int shift) {
     // pairs in key order: first, second, third (0 = uv, 1 = uw, 2 = vw)
     int o0 = 0, o1 = 1, o2 = 2;
     if (k[o1] < k[o0]) { int x = o0; o0 = o1; o1 = x; }
@@ -389,6 +379,21 @@ __device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint3
     const uint32_t t1 = (uint32_t)(k[o0] >> shift), t2 = (uint32_t)(k[o1] >> shift),
                    t3 = (uint32_t)(k[o2] >> shift);
     return make_uint4(t1, t2 - t1, t3 - t2, (uint32_t)(((pi - 1) * 8 + (rho - 1)) << 8) | (uint32_t)(type - 1));
+}
+
+__device__ __forceinline__ uint4 unit_record(uint32_t e_uv, uint32_t e_uw, uint32_t e_vw,
+                                             const uint32_t *__restrict__ eoff,
+                                             const uint64_t *__restrict__ key, int shift) {
+    const uint32_t es[3] = {e_uv, e_uw, e_vw};
+    uint64_t k[3];
+    int dir[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const uint32_t a = eoff[2 * es[p]], b = eoff[2 * es[p] + 1];
+        k[p] = key[a];
+        dir[p] = a == b ? 1 : 0;
+    }
+    return unit_record_of(k, dir, shift);
 }
 
 // ---------------------------------------------------------------------------------------------

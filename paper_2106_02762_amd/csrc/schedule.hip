@@ -244,6 +244,18 @@ __device__ __forceinline__ uint16_t window_cell(uint32_t e_uv, uint32_t e_uw, ui
     return (uint16_t)((f < kSlices - 1 ? f : kSlices - 1) * kSlices + (l < kSlices - 1 ? l : kSlices - 1));
 }
 
+// Per DAG edge with one temporal edge: that edge's key, with its direction (1: head -> tail) in
+// bit 63, which is free while unit records are built (spans below 2^31 and fewer than 2^31 edges
+// keep keys below 2^62); all ones for other edges.  The partition then builds a unit record from
+// three independent loads instead of three offset-then-key chains.
+__global__ void k_unit_keys(uint64_t ms, const uint32_t *__restrict__ eoff, const uint64_t *__restrict__ key,
+                            uint64_t *__restrict__ ukey) {
+    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= ms) return;
+    const uint32_t a = eoff[2 * e], b = eoff[2 * e + 1], c = eoff[2 * e + 2];
+    ukey[e] = c - a == 1 ? key[a] | (uint64_t)(a == b ? 1u : 0u) << 63 : ~0ull;
+}
+
 // Every triangle to its class's list at base[class][block] + its rank in the block's walk: unit
 // triangles become records (in triangle order) with their t1 bucket as a sort key; light and
 // always-medium triangles also go, with their window cell as a sort key, to the windowed copies'
@@ -252,7 +264,8 @@ __device__ __forceinline__ uint16_t window_cell(uint32_t e_uv, uint32_t e_uw, ui
 __global__ void __launch_bounds__(kBlock)
 k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__restrict__ cls,
             const uint64_t *__restrict__ base, const uint32_t *__restrict__ eoff,
-            const uint64_t *__restrict__ key, int shift, int bshift, int cshift, uint64_t n_c,
+            const uint64_t *__restrict__ key, const uint64_t *__restrict__ ukey, int shift, int bshift,
+            int cshift, uint64_t n_c,
             uint32_t *__restrict__ light, uint32_t *__restrict__ medium, uint32_t *__restrict__ heavy,
             uint4 *__restrict__ crec, uint4 *__restrict__ lrec, uint16_t *__restrict__ lkey,
             uint4 *__restrict__ mrec, uint16_t *__restrict__ mkey, uint4 *__restrict__ urec,
@@ -286,7 +299,10 @@ k_partition(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint8_t *__r
             const uint64_t pos = run[k] + (((before + x - f) >> (12 * k)) & 0xfffull);
             const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
             if (k == kClsUnit) {
-                const uint4 r = cdev::unit_record(e_uv, e_uw, e_vw, eoff, key, shift);
+                const uint64_t k3[3] = {ukey[e_uv] & ~(1ull << 63), ukey[e_uw] & ~(1ull << 63),
+                                        ukey[e_vw] & ~(1ull << 63)};
+                const int d3[3] = {(int)(ukey[e_uv] >> 63), (int)(ukey[e_uw] >> 63), (int)(ukey[e_vw] >> 63)};
+                const uint4 r = cdev::unit_record_of(k3, d3, shift);
                 urec[pos] = r;
                 ubkt[pos] = (uint16_t)(r.x >> bshift);
             } else if (k == kClsContest) {
@@ -626,14 +642,22 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     DT_TRY(dev_alloc(ctx, mkey, nm * 2));
     DT_TRY(dev_alloc(ctx, crec, nc * sizeof(uint4)));
     DT_TRY(dev_alloc(ctx, ckey, nc * 2));
+    DevMem ukey;
+    DT_TRY(dev_alloc(ctx, ukey, (nu ? g->m_s : 0) * 8));
+    if (nu) {
+        k_unit_keys<<<grid_for(g->m_s, kBlock), kBlock, 0, st>>>(g->m_s, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
+                                                                 ukey.as<uint64_t>());
+        DT_HIP(hipGetLastError());
+    }
     if (nt) {
         k_partition<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), cls.as<uint8_t>(), base.as<uint64_t>(),
-            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), g->shift, S.unit_shift, S.cell_shift, nc,
+            g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), ukey.as<uint64_t>(), g->shift, S.unit_shift, S.cell_shift, nc,
             S.light.as<uint32_t>(), S.medium.as<uint32_t>(), S.heavy.as<uint32_t>(), crec.as<uint4>(), lrec.as<uint4>(),
             lkey.as<uint16_t>(), mrec.as<uint4>(), mkey.as<uint16_t>(), urec.as<uint4>(), ubkt.as<uint16_t>());
         DT_HIP(hipGetLastError());
     }
     cls.reset();
+    ukey.reset();
     // unit records ordered by t1 bucket (a stable two-pass radix sort on the 16-bit bucket) on the
     // first side stream, while this stream builds the other lists; the host keeps the bucket starts
     // (read back through the pinned staging buffer from byte kStageUnit; the cell starts, level
