@@ -69,6 +69,29 @@ def measured_traffic(kernel):
         return None
 
 
+def count_roofline(st, count_ms, kernels_ms):
+    """The count's HBM fraction (wall time of dt_count at the headline delta) under two byte counts:
+    the library's (16 bytes per unit triangle: its record is all a unit triangle's count reads) and
+    the per-triangle formula that charges every triangle 12 + 36 + 8 (s_uv + s_uw) + 8 min(s_vw,
+    probe) bytes (72 for a unit triangle); and beside them the HBM bytes the counters measured for
+    the count's kernels (per launch, from the committed summary), when recorded for this source."""
+    t = count_ms / 1e3
+    n_unit = st["n_unit_triangles"]
+    survey = st["alg_bytes"] - st["alg_bytes_unit"] + 72 * n_unit
+    parts = ("unit", "light", "medium", "heavy_prefix", "heavy_count")
+    measured = {k: measured_traffic(k) for k in parts}
+    counter = sum(v for v in measured.values() if v is not None) if all(
+        measured[k] is not None for k in ("unit", "light", "medium")) else None
+    out = {"kernels_ms": kernels_ms, "count_ms": count_ms,
+           "alg_bytes": st["alg_bytes"], "frac": round(st["alg_bytes"] / t / (HBM_PEAK_GBS * 1e9), 4),
+           "alg_bytes_per_triangle_formula": survey,
+           "frac_per_triangle_formula": round(survey / t / (HBM_PEAK_GBS * 1e9), 4),
+           "counter_bytes": counter, "counter_bytes_by_kernel": measured,
+           "frac_counter": round(counter / t / (HBM_PEAK_GBS * 1e9), 4) if counter else None,
+           "achieved_GBs": round(st["alg_bytes"] / t / 1e9, 2)}
+    return out
+
+
 def run_batched(dt, ctx, k, with_cpu):
     """The batched workload: k independent graphs, each with its own deltas, in one call; every
     result is compared with the same query alone, and every 32nd with the oracle."""
@@ -335,6 +358,10 @@ def main():
                           "count_ms": round(statistics.median(ts[1:]), 4),
                           "kernel_ms_step": {k: round(float(np.mean([p[k] for p in prof])), 4) for k in prof[0]},
                           "kernel_ms_count": {k: round(float(v), 4) for k, v in pk.items() if v > 0},
+                          "count_roofline": count_roofline(st, statistics.median(ts[1:]),
+                                                           {k: round(float(pk[k]), 4) for k in (
+                                                               "unit", "light", "medium", "heavy_prefix",
+                                                               "heavy_count", "reduce")}),
                           "build_ms": {"peel": round(st["ms_peel"], 3), "orient": round(st["ms_orient"], 3),
                                        "triangles": round(st["ms_triangles"], 3),
                                        "schedule": round(st["ms_schedule"], 3)},
@@ -518,9 +545,7 @@ def main():
                   "tri_candidates": st["tri_candidates"],
                   "alg_bytes_count": st["alg_bytes"]},
         "roofline": roofline,
-        "count_roofline": {"kernels_ms": count_kernels,
-                           "alg_bytes": st["alg_bytes"],
-                           "achieved_GBs": round(st["alg_bytes"] / (count_ms[str(d)] / 1e3) / 1e9, 2)},
+        "count_roofline": count_roofline(st, count_ms[str(d)], count_kernels),
         "cpu_baseline": cpu,
         "parity_whole_span": parity,
         "medium": medium,

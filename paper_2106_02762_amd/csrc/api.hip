@@ -247,6 +247,7 @@ int dt_graph_build(dt_graph *g) {
     clear_error();
     DT_TRY(check_graph(g, false));
     DeviceGuard dg(g->ctx->device);
+    prof_clear(g->ctx, true);
     g->built = false;
     double t0 = now_ms();
     DT_TRY(order_vertices(g));

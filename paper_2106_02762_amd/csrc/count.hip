@@ -581,6 +581,7 @@ int launch_paths(dt_graph *g, const DQuery &q, const CountPlan &p, const Scratch
 int count_launch(dt_graph *g, const DQuery &q, const CountPlan &p, int64_t *out8_dev, hipStream_t s, bool cells,
                  int64_t *cells_dev, const ScratchView &sv, unsigned long long *visits) {
     dt_ctx *ctx = g->ctx;
+    prof_clear(ctx, false);
     if (sv.part_bytes < p.part_bytes || sv.heavy_bytes < p.heavy_bytes)
         return fail(DT_EINVAL, "count scratch too small (%zu of %zu, %zu of %zu bytes)", sv.part_bytes, p.part_bytes,
                     sv.heavy_bytes, p.heavy_bytes);

@@ -124,6 +124,17 @@ inline void prof_begin(dt_ctx *c, int slot, hipStream_t s) {
 inline void prof_end(dt_ctx *c, int slot, hipStream_t s) {
     if (c->prof) (void)hipEventRecord(c->prof_ev[2 * slot + 1], s);
 }
+// a new build or count: its slots report 0 until its kernels record them
+inline void prof_clear(dt_ctx *c, bool build) {
+    static constexpr int kBuild[] = {kProfPeel, kProfRelayout, kProfTriCount, kProfTriFill, kProfPeelAdj,
+                                     kProfPeelTail, kProfCore};
+    static constexpr int kCount[] = {kProfLight, kProfHeavyPrefix, kProfHeavyCount, kProfReduce, kProfMedium,
+                                     kProfUnit};
+    if (build)
+        for (int s : kBuild) c->prof_used[s] = false;
+    else
+        for (int s : kCount) c->prof_used[s] = false;
+}
 int ensure(dt_ctx *ctx, DevMem &m, size_t bytes);   // grow-only, not pooled
 
 // ------------------------------------------------------------------------------------------------
