@@ -18,6 +18,10 @@ __global__ void k_tri_vertices(uint64_t nt, const uint32_t *__restrict__ tri, ui
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nt) return;
     const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1];
+    if (e_uv == kNoEdge) {   // an empty list entry stays empty
+        out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = kNoEdge;
+        return;
+    }
     // tail of e_uv: the last u with dag_row[u] <= e_uv
     uint32_t lo = 0, len = n;
     while (len > 0) {
@@ -255,17 +259,18 @@ int dt_graph_build(dt_graph *g) {
     DT_TRY(orient(g, true));
     double t2 = now_ms();
     DevMem tri;
-    uint64_t ntri = 0, cand = 0;
+    uint64_t ntri = 0, cand = 0, nlist = 0;
     {
         // the store's re-layout runs beside the enumeration, which does not read it
         struct Join {
             dt_graph *g;
             ~Join() { (void)relayout_join(g); }
         } join{g};
-        DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+        DT_TRY(enumerate_triangles(g, tri, &ntri, &cand, &nlist));
         DT_TRY(relayout_join(g));
     }
     g->n_tri = ntri;
+    g->n_tri_list = nlist;
     g->tri_candidates = cand;
     g->alg_bytes_tri = 4 * (g->m_s + cand) + 12 * ntri;
     double t3 = now_ms();
@@ -305,9 +310,10 @@ int dt_graph_set_tuning(dt_graph *g, const dt_tuning *tu) {
     // enumeration pass runs again; it yields the same triangles)
     DeviceGuard dg(g->ctx->device);
     DevMem tri;
-    uint64_t ntri = 0, cand = 0;
-    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    uint64_t ntri = 0, cand = 0, nlist = 0;
+    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand, &nlist));
     if (ntri != g->n_tri) return fail(DT_EDEVICE, "triangle enumeration changed between passes");
+    g->n_tri_list = nlist;
     DT_TRY(resolve_split(g, g->tuning.autotune == 2 ? &tri : nullptr));
     return make_schedule(g, tri);
 }
@@ -448,6 +454,7 @@ int dt_count_oneshot(dt_graph *g, const dt_query *q, int64_t out[8]) {
         // (the rest is counted in 128 bits when its sum of multiplicity products reaches 2^63, 16
         // words at o + 8)
         g->n_tri = n_rest;
+        g->n_tri_list = n_rest;
         rc = make_schedule(g, rest);
         if (rc == DT_OK) rc = count_enqueue(g, dq, o + 8, ctx->stream, false, nullptr, ctx->scratch);
     } else if (rc == DT_OK) {
@@ -633,17 +640,24 @@ int dt_graph_triangles(const dt_graph *g, uint32_t *out, uint64_t cap, uint64_t 
     if (!out || cap == 0 || g->n_tri == 0) return DT_OK;
     DeviceGuard dg(g->ctx->device);
     DevMem tri, buf;
-    uint64_t ntri = 0, cand = 0;
-    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand));
+    uint64_t ntri = 0, cand = 0, nlist = 0;
+    DT_TRY(enumerate_triangles(g, tri, &ntri, &cand, &nlist));
     if (ntri != g->n_tri) return fail(DT_EDEVICE, "triangle enumeration changed between passes");
-    DT_TRY(dev_alloc(g->ctx, buf, ntri * 12));
+    DT_TRY(dev_alloc(g->ctx, buf, nlist * 12));
     hipStream_t st = g->ctx->stream;
-    k_tri_vertices<<<grid_for(ntri, kBlock), kBlock, 0, st>>>(ntri, tri.as<uint32_t>(), g->n,
+    k_tri_vertices<<<grid_for(nlist, kBlock), kBlock, 0, st>>>(nlist, tri.as<uint32_t>(), g->n,
         g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), g->order.as<uint32_t>(), buf.as<uint32_t>());
     DT_HIP(hipGetLastError());
-    uint64_t k = cap < ntri ? cap : ntri;
-    DT_HIP(hipMemcpyAsync(out, buf.ptr, k * 12, hipMemcpyDeviceToHost, st));
+    // the list's triangles without its empty entries
+    std::vector<uint32_t> all(3 * nlist);
+    DT_HIP(hipMemcpyAsync(all.data(), buf.ptr, nlist * 12, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < nlist && k < cap; ++i) {
+        if (all[3 * i] == kNoEdge) continue;
+        memcpy(out + 3 * k, &all[3 * i], 12);
+        ++k;
+    }
     return DT_OK;
 }
 

@@ -263,6 +263,7 @@ struct dt_graph {
     bool relay_pending = false; // key is still being written on the context's side[0] stream
     dt::DevMem relay_tmp[2];    // inputs of that re-layout, held until it is joined
     uint64_t n_tri = 0;
+    uint64_t n_tri_list = 0;    // entries of the triangle list the last schedule was made from (with empty ones)
     unsigned __int128 sum_sigma3 = 0;
     uint64_t alg_bytes = 0, alg_bytes_light = 0, alg_bytes_medium = 0, alg_bytes_peel = 0, alg_bytes_tri = 0;
     uint64_t alg_bytes_unit = 0;
@@ -299,8 +300,13 @@ int peel(dt_graph *g);         // level-by-level core peel (order_method 0)
 int core_order(dt_graph *g);   // h-index core numbers, then shell rounds (order_method 1)
 int order_vertices(dt_graph *g);   // the ordering by the graph's order_method
 int orient(dt_graph *g, bool overlap = false);   // overlap: re-layout on side[0], see relayout_join
-// every static triangle as (e_uv, e_uw, e_vw) DAG edge ids; *ntri and *cand (candidates tested)
-int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand);
+// an empty entry of a triangle list (all three DAG edge ids): the enumeration leaves some, the
+// schedule skips them
+constexpr uint32_t kNoEdge = 0xffffffffu;
+// every static triangle as (e_uv, e_uw, e_vw) DAG edge ids, in a list of *nlist entries of which
+// *ntri are triangles and the others empty; *cand: candidates tested
+int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri, uint64_t *cand, uint64_t *nlist);
+// the schedule of g's count from its triangle list tri (g->n_tri_list entries, g->n_tri triangles)
 int make_schedule(dt_graph *g, DevMem &tri);
 // orders the context's stream after a re-layout that orient(g, true) left running on side[0]
 // (no-op otherwise) and releases its temporaries; to be called before anything reads g->key

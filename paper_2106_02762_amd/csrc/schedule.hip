@@ -78,9 +78,10 @@ constexpr int kPartWords = 6;   // per block: sum_sigma3 lo, hi, bytes, light, m
 constexpr unsigned kClsGrid = 4096;   // blocks of the classify and partition passes (grid-stride)
 constexpr int kTotWords = kClasses + kPartWords;   // class sizes, then the partial words
 
-// Per triangle its class (one byte); per block the triangles of each class and the sum of sigma
-// products (128-bit) and byte totals.  The partition pass walks the triangles in the same
-// block / iteration order, so per-block class counts give every triangle its place.
+// Per list entry its class (one byte; kClasses for an empty entry); per block the triangles of
+// each class and the sum of sigma products (128-bit) and byte totals.  The partition pass walks the
+// entries in the same block / iteration order, so per-block class counts give every triangle its
+// place.
 __global__ void __launch_bounds__(kBlock)
 k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__restrict__ eoff, SplitRule R,
            uint8_t *__restrict__ cls, uint32_t *__restrict__ bcnt, uint64_t *__restrict__ part) {
@@ -93,6 +94,10 @@ k_classify(uint64_t n_tri, const uint32_t *__restrict__ tri, const uint32_t *__r
     unsigned c[kClasses] = {0, 0, 0, 0, 0};
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n_tri; i += (uint64_t)gridDim.x * kBlock) {
         const uint32_t e_uv = tri[3 * i], e_uw = tri[3 * i + 1], e_vw = tri[3 * i + 2];
+        if (e_uv == kNoEdge) {   // an empty entry: no class
+            cls[i] = (uint8_t)kClasses;
+            continue;
+        }
         const uint64_t s_uv = eoff[2 * e_uv + 2] - eoff[2 * e_uv];
         const uint64_t s_uw = eoff[2 * e_uw + 2] - eoff[2 * e_uw];
         const uint32_t s_vw = eoff[2 * e_vw + 2] - eoff[2 * e_vw];
@@ -577,7 +582,7 @@ int medium_fill(dt_ctx *ctx, uint64_t nm, DevMem &nch, DevMem &base, uint64_t ni
 int make_schedule(dt_graph *g, DevMem &tri) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
-    const uint64_t nt = g->n_tri;
+    const uint64_t nt = g->n_tri_list;   // list entries (empty ones have no class)
     Schedule &S = g->sched;
     S = Schedule();
     SplitRule R;
@@ -613,7 +618,8 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     g->alg_bytes_medium = hs[kClasses + 4];
     g->alg_bytes_unit = hs[kClasses + 5];
     const uint64_t na = ncls[kClsMedium], nh_always = ncls[kClsHeavy], nu = ncls[kClsUnit], nc = ncls[kClsContest];
-    if (ncls[kClsLight] + na + nh_always + nu + nc != nt) return fail(DT_EDEVICE, "triangle classes do not add up");
+    if (ncls[kClsLight] + na + nh_always + nu + nc != g->n_tri)
+        return fail(DT_EDEVICE, "triangle classes do not add up");
     S.n_light = ncls[kClsLight];
     S.n_always_medium = na;
     S.n_contested = nc;

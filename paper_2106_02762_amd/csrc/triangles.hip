@@ -41,6 +41,10 @@ constexpr uint32_t kSplitU = 8192, kParts = 8;   // kSplitU 4096: +0.5 ms; 16384
 constexpr uint32_t kSingles = 16384;
 constexpr uint32_t kChunk = 16;
 constexpr uint32_t kOut = 192;    // triangles a wavefront buffers in LDS before appending them
+// list positions a wavefront reserves at once (one atomic on the shared counter per kChunkTri
+// triangles instead of one per buffer: thousands of wavefronts meeting at one counter serialise)
+constexpr uint32_t kChunkTri = 2048;
+static_assert(kChunkTri >= kOut, "a buffer fits a fresh chunk");
 constexpr int kBatchBuild = 4;    // blocks of 64 flattened candidates a lane works on at once
 constexpr int kBatchFused = 1;    // (one in the one-shot pass: its counting holds the registers)
 constexpr uint32_t kBmMin = 16;      // heads of N+(v) at least for a bitmap
@@ -178,8 +182,13 @@ struct FusedArgs {
     unsigned long long *s3;        // sum of sigma_uv sigma_uw sigma_vw, 128 bits (low, high)
 };
 
-// Buffered output: a wavefront collects its triangles in LDS and appends them to the list with one
-// atomic per kOut triangles.  Positions past `cap` are counted but not written.  In the one-shot
+// Buffered output: a wavefront collects its triangles in LDS and copies each full buffer into a
+// stretch of list positions it reserved with one atomic per kChunkTri positions; when the stretch
+// lacks room for a buffer, its rest is filled with empty triangles (all three ids kNoEdge) and a new
+// stretch is taken, and at the end the unused rest of the last one is filled the same way.  The
+// list therefore holds every triangle once and some empty entries, which the schedule skips; the
+// wavefronts also add up the triangles they found.  Positions past `cap` are counted but not
+// written.  In the one-shot
 // pass (FUSED) a full buffer is counted instead: each lane takes every 64th buffered triangle;
 // one with a single temporal edge per pair is tested as a unit record, a light one is counted
 // pairwise in the lane, and the others go to the rest list for the medium and heavy paths (one
@@ -192,7 +201,10 @@ struct TriSink {
     uint64_t cap;
     unsigned long long *total;
     const FusedArgs *fa;
-    unsigned long long found = 0;   // triangles this wavefront counted (one-shot pass)
+    unsigned long long *found_total;   // triangles found (stored pass)
+    unsigned long long found = 0;   // triangles this wavefront found (counted, in the one-shot pass)
+    unsigned long long cb = 0, ce = 0;   // the reserved positions [cb, ce) not yet used (stored pass)
+    bool chunked = true;                 // stretches of kChunkTri positions, else one per buffer
     int64_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned long long s3lo = 0, s3hi = 0;
     // counts one triangle; false when it belongs to the medium or heavy paths (the rest list)
@@ -259,9 +271,19 @@ struct TriSink {
                 }
             }
         } else {
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
-            base = __shfl(base, 0, 64);
+            found += n;
+            if (ce - cb < n) {
+                // a new stretch: kChunkTri positions, or exactly this buffer's (chunked = false)
+                fill_empty(lane);
+                const unsigned long long want = chunked ? kChunkTri : n;
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(total, want);
+                b = __shfl(b, 0, 64);
+                cb = b;
+                ce = b + want;
+            }
+            const unsigned long long base = cb;
+            cb += n;
             for (uint32_t x = lane; x < 3 * n; x += 64)
                 if (base + x / 3 < cap) tri[3 * base + x] = buf[x];
         }
@@ -269,10 +291,27 @@ struct TriSink {
         n = 0;
     }
 
-    // at the end: the buffer out, and in the one-shot pass the wavefront's count added
+    // the reserved positions [cb, ce) become empty triangles
+    __device__ __forceinline__ void fill_empty(unsigned lane) {
+        for (unsigned long long q = cb + lane; q < ce; q += 64)
+            if (q < cap) {
+                tri[3 * q] = kNoEdge;
+                tri[3 * q + 1] = kNoEdge;
+                tri[3 * q + 2] = kNoEdge;
+            }
+        cb = ce;
+    }
+
+    // at the end: the buffer out, the rest of the stretch emptied, and the wavefront's triangles
+    // added up (to the found counter, or in the one-shot pass to the total)
     __device__ __forceinline__ void finish(unsigned lane) {
         flush(lane);
-        if (FUSED && lane == 0 && found) atomicAdd(total, found);
+        if (FUSED) {
+            if (lane == 0 && found) atomicAdd(total, found);
+        } else {
+            fill_empty(lane);
+            if (lane == 0 && found) atomicAdd(found_total, found);
+        }
     }
 
     // the lanes with hit set hold one triangle each; mask = the wave's ballot of hit
@@ -296,7 +335,8 @@ __global__ void __launch_bounds__(kBlock, 4)   // four wavefronts per SIMD (the 
 k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
       uint32_t *__restrict__ tri, uint64_t cap, unsigned long long *__restrict__ total,
       unsigned int *__restrict__ next_u, unsigned long long *__restrict__ cand, FusedArgs fa,
-      const uint4 *__restrict__ binfo, const uint64_t *__restrict__ bslots) {
+      const uint4 *__restrict__ binfo, const uint64_t *__restrict__ bslots,
+      unsigned long long *__restrict__ found_total, int chunked) {
     // per wavefront: N+(u), the run starts and (16-bit) lengths of each N+(v), and one slice that
     // holds the prefix of walk lengths during the flattened walks and then a staged N+(v) copy
     __shared__ uint32_t s_nbr[kWaves][kCap];
@@ -307,7 +347,8 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
     const unsigned wave = threadIdx.x / 64, lane = threadIdx.x & 63;
     uint32_t *nbr_lds = s_nbr[wave], *pre_lds = s_pre[wave], *vb_lds = s_vb[wave], *vn_lds = s_pre[wave];
     uint16_t *dv_lds = s_dv[wave];
-    TriSink<FUSED> out{s_out[wave], 0, tri, cap, total, &fa};
+    TriSink<FUSED> out{s_out[wave], 0, tri, cap, total, &fa, found_total};
+    out.chunked = chunked != 0;
     unsigned long long wave_cand = 0;   // candidates tested, added once per wave
     for (;;) {
         uint32_t ticket = 0;
@@ -585,36 +626,47 @@ int build_bitmaps(const dt_graph *g, DevMem &info, DevMem &slots) {
 
 }  // namespace
 
-int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint64_t *cand_out) {
+int enumerate_triangles(const dt_graph *g, DevMem &tri, uint64_t *ntri_out, uint64_t *cand_out,
+                        uint64_t *nlist_out) {
     dt_ctx *ctx = g->ctx;
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
     *ntri_out = 0;
     *cand_out = 0;
+    *nlist_out = 0;
     if (n == 0) return DT_OK;
     DevMem ctr, binfo, bslots;
     DT_TRY(dev_alloc(ctx, ctr, 256));
     DT_TRY(build_bitmaps(g, binfo, bslots));
-    // room for 4 triangles per static pair; a graph with more runs the pass again at its size
+    // room for 4 triangles per static pair.  Wavefronts reserve stretches of kChunkTri positions
+    // when that room is at least four times what the last stretches of all wavefronts can leave
+    // empty, else exactly each buffer's positions (no empty entries).  A graph with more triangles
+    // runs the pass again, with room for its triangles and, with stretches, the most empty entries
+    // they can leave: below kOut per stretch taken (at most one per kChunkTri - kOut triangles, and
+    // one more per wavefront) and a last stretch per wavefront.
     uint64_t cap = std::max<uint64_t>(4ull * g->m_s, 1ull << 16);
     const unsigned grid = (unsigned)ctx->num_cus * 8;
+    const uint64_t waves = (uint64_t)grid * kWaves;
+    const int chunked = cap >= 4 * waves * kChunkTri ? 1 : 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         DT_TRY(dev_alloc(ctx, tri, cap * 12));
-        DT_HIP(hipMemsetAsync(ctr.ptr, 0, 32, st));
+        DT_HIP(hipMemsetAsync(ctr.ptr, 0, 40, st));
         unsigned long long *c64 = reinterpret_cast<unsigned long long *>(ctr.as<uint8_t>() + 8);
         prof_begin(ctx, kProfTriFill, st);
         k_tri<false><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(),
                                               tri.as<uint32_t>(), cap, c64, ctr.as<unsigned>(), c64 + 1, FusedArgs{},
-                                              binfo.as<uint4>(), bslots.as<uint64_t>());
+                                              binfo.as<uint4>(), bslots.as<uint64_t>(), c64 + 2, chunked);
         prof_end(ctx, kProfTriFill, st);
         DT_HIP(hipGetLastError());
         uint64_t *h = reinterpret_cast<uint64_t *>(ctx->pinned_stage);
-        DT_HIP(hipMemcpyAsync(h, c64, 16, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(h, c64, 24, hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
-        *ntri_out = h[0];
+        *nlist_out = h[0];
         *cand_out = h[1];
+        *ntri_out = h[2];
         if (h[0] <= cap) return DT_OK;
-        cap = h[0];
+        const uint64_t stretches = h[2] / (kChunkTri - kOut) + 2 * waves;
+        cap = chunked ? h[2] + stretches * kOut + waves * kChunkTri : h[2];
         tri.reset();
     }
     return fail(DT_EDEVICE, "triangle enumeration changed between passes");
@@ -656,7 +708,7 @@ int fused_count(dt_graph *g, const DQuery &q, int64_t *out8_dev, DevMem &rest, u
         if (n)
             k_tri<true><<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), g->dag_col.as<uint32_t>(), nullptr, 0,
                                                  c64, ctr.as<unsigned>(), c64 + 1, fa, binfo.as<uint4>(),
-                                                 bslots.as<uint64_t>());
+                                                 bslots.as<uint64_t>(), nullptr, 0);
         else
             DT_HIP(hipMemsetAsync(part.ptr, 0, n_part * 8 * sizeof(int64_t), st));
         prof_end(ctx, kProfTriFill, st);

@@ -12,6 +12,8 @@
 - dt_count_async on the context's stream and on a foreign stream, into device and pinned memory.
 - Sixteen graphs of the 512-graph batched workload in one dt_count_batch call, each with its own
   delta triple, against the oracle.
+- The full-size workload, whose triangle list is written in reserved stretches with empty
+  entries between them: triangle count, statistics and whole-span counts against the oracle.
 """
 import numpy as np
 import pytest
@@ -158,3 +160,22 @@ def test_batched_workload_graphs_match_oracle(ctx):
         assert (got[i] == want).all(), (g.name, d, got[i], want)
     for h in hs:
         dt.dt_graph_free(h)
+
+
+def test_full_workload_list_written_in_stretches(ctx):
+    """The full-size workload (61M edges, 67M static triangles) is large enough that the
+    enumeration's wavefronts reserve list positions in stretches and leave empty entries: the
+    triangle count, the sum of multiplicity products and the degeneracy equal the oracle's, and the
+    whole-span counts at (3600, 3600, 3600) equal the oracle's (Definition 1)."""
+    g = synth.plain_full()
+    b = Built(ctx, g, g.name)
+    st = dt.dt_graph_stats(b.h)
+    say("oracle stats", g.name)
+    ost = oracle.stats(g.n, g.src, g.dst, g.t)
+    assert st["n_static_triangles"] == ost["n_triangles"]
+    assert st["sum_sigma3"] == ost["sum_sigma3"]
+    assert st["degeneracy"] == ost["degeneracy"]
+    say("oracle count", g.name)
+    want = oracle.count(g.n, g.src, g.dst, g.t, 3600, 3600, 3600)
+    assert (b.count(3600, 3600, 3600) == want).all()
+    b.free()
