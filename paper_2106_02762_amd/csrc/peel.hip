@@ -396,13 +396,27 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             const uint32_t se = sb + seg < n_alive ? sb + seg : n_alive;
             uint32_t ct = 0, ck = 0;
             unsigned mdl = 0xffffffffu;
-            for (uint32_t b0 = sb; b0 < se; b0 += 64) {
-                const uint32_t i = b0 + lane;
-                const int d = i < se ? ld_relaxed(&deg[cur[i]]) : -1;
-                const bool keep = d > (int)k;
-                ct += (uint32_t)__popcll(__ballot(d >= 0 && d <= (int)k));   // d < 0: queued
-                ck += (uint32_t)__popcll(__ballot(keep));
-                mdl = keep && (unsigned)d < mdl ? (unsigned)d : mdl;
+            // four chunks of 64 at a time: their list reads, then their degree reads, in flight
+            // together
+            for (uint32_t b0 = sb; b0 < se; b0 += 4 * 64) {
+                uint32_t vv[4];
+                int dd[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = b0 + q * 64 + lane;
+                    vv[q] = i < se ? cur[i] : 0u;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    dd[q] = b0 + q * 64 + lane < se ? ld_relaxed(&deg[vv[q]]) : -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = dd[q];
+                    const bool keep = d > (int)k;
+                    ct += (uint32_t)__popcll(__ballot(d >= 0 && d <= (int)k));   // d < 0: queued
+                    ck += (uint32_t)__popcll(__ballot(keep));
+                    mdl = keep && (unsigned)d < mdl ? (unsigned)d : mdl;
+                }
             }
             mdl = wave_min(mdl);
             // one reservation per block (the wavefronts' segments are consecutive, so a prefix
@@ -432,24 +446,32 @@ k_peel(uint32_t n, const uint32_t *__restrict__ row, const uint32_t *__restrict_
             __syncthreads();
             uint32_t qb = s_bq + s_wct[wv], kb = s_bk + s_wck[wv];
             if (ct | ck) {
-                for (uint32_t b0 = sb; b0 < se; b0 += 64) {
-                    const uint32_t i = b0 + lane;
-                    uint32_t v = 0;
-                    int d = -1;
-                    if (i < se) {
-                        v = cur[i];
-                        d = ld_relaxed(&deg[v]);
+                for (uint32_t b0 = sb; b0 < se; b0 += 4 * 64) {
+                    uint32_t vv[4];
+                    int dd[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t i = b0 + q * 64 + lane;
+                        vv[q] = i < se ? cur[i] : 0u;
                     }
-                    const bool take = d >= 0 && d <= (int)k, keep = d > (int)k;
-                    const uint64_t mt = __ballot(take), mk = __ballot(keep);
-                    if (take) {
-                        level[v] = k;
-                        const uint32_t p = qb + (uint32_t)__popcll(mt & below);
-                        if (p < n) queue[p] = v;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        dd[q] = b0 + q * 64 + lane < se ? ld_relaxed(&deg[vv[q]]) : -1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t v = vv[q];
+                        const int d = dd[q];
+                        const bool take = d >= 0 && d <= (int)k, keep = d > (int)k;
+                        const uint64_t mt = __ballot(take), mk = __ballot(keep);
+                        if (take) {
+                            level[v] = k;
+                            const uint32_t p = qb + (uint32_t)__popcll(mt & below);
+                            if (p < n) queue[p] = v;
+                        }
+                        if (keep) nxt[kb + (uint32_t)__popcll(mk & below)] = v;
+                        qb += (uint32_t)__popcll(mt);
+                        kb += (uint32_t)__popcll(mk);
                     }
-                    if (keep) nxt[kb + (uint32_t)__popcll(mk & below)] = v;
-                    qb += (uint32_t)__popcll(mt);
-                    kb += (uint32_t)__popcll(mk);
                 }
             }
         }
