@@ -223,6 +223,21 @@ __device__ __forceinline__ void medium_pair(const uint64_t *__restrict__ key, co
 // (uv on a tie); the medium path has one entry per outer edge
 __host__ __device__ __forceinline__ bool medium_outer_is_uv(uint32_t s_uv, uint32_t s_uw) { return s_uv <= s_uw; }
 
+// A medium entry is one outer edge and, when the inner pair is long, one chunk of kInnerChunk of
+// the inner pair's edges (indices over its direction-0 run followed by its direction-1 run): no
+// entry then has more than kInnerChunk close pairs at any delta, and the wavefronts that take the
+// consecutive entries of a triangle with a short and a long source pair share its pairs instead of
+// one of them walking all of them.  Only triangles with at most kChunkMaxPairs pairs are split
+// (each chunk is an entry, searched at every delta); the triangle's entries are its outer edges
+// times its chunks, entry j' standing for outer edge j' / chunks and chunk j' % chunks.
+constexpr uint32_t kInnerChunk = 512;
+constexpr uint64_t kChunkMaxPairs = 1ull << 20;
+__host__ __device__ __forceinline__ uint32_t medium_inner_chunks(uint32_t s_outer, uint32_t s_inner) {
+    return s_inner > kInnerChunk && (uint64_t)s_outer * s_inner <= kChunkMaxPairs
+               ? (s_inner + kInnerChunk - 1) / kInnerChunk
+               : 1u;
+}
+
 // first indices in [lo, hi) whose keys are >= K1 and >= K2 (two searches in one loop)
 __device__ __forceinline__ void lower2(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi, uint64_t K1,
                                        uint64_t K2, uint32_t &r1, uint32_t &r2) {
@@ -239,12 +254,12 @@ __device__ __forceinline__ void lower2(const uint64_t *__restrict__ key, uint32_
     r2 = l2;
 }
 
-// Medium entries: entry e = (triangle index into med, outer edge offset).  Lane l takes entry
-// `e` (when `active`): edge x of the triangle's outer pair (its direction-0 run, then its
-// direction-1 run).  A pair (x, y) with y on the other source-incident pair (the inner one) can only
-// complete a triangle when |t_y - t_x| <= d13 (d12, d23 <= d13 after normalisation), and on each
-// inner direction list those y form one key range (clipped to the window too), found by binary
-// search.  The wavefront then spreads the (x, y) pairs of all its lanes evenly over the lanes
+// Medium entries: entry e = (triangle index into med, outer edge and inner chunk, as in
+// medium_inner_chunks).  Lane l takes entry `e` (when `active`): edge x of the triangle's outer pair
+// (its direction-0 run, then its direction-1 run).  A pair (x, y) with y on the other
+// source-incident pair (the inner one, or the entry's chunk of it) can only complete a triangle
+// when |t_y - t_x| <= d13 (d12, d23 <= d13 after normalisation), and on each inner direction list
+// those y form one key range (clipped to the window too), found by binary search.  The wavefront then spreads the (x, y) pairs of all its lanes evenly over the lanes
 // (pair j belongs to the last lane whose exclusive prefix of pair counts is <= j), so one outer edge
 // with many close partners does not stall the others.  Every lane of the wavefront must call this.
 // Each pair goes to eval(direction combination 2 d_uv + d_uw, its {v,w} lists, uv key, uw key);
@@ -261,13 +276,21 @@ __device__ __forceinline__ uint32_t medium_lanes_eval(const uint32_t *__restrict
     uint32_t lo0 = 0, c0 = 0, lo1 = 0, c1 = 0, zb0 = 0, ze0 = 0, zb1 = 0, ze1 = 0, flags = 0;
     if (active && lev && lev[ent[2 * e]] < q.qlev) active = false;
     if (active) {
-        const uint32_t t = ent[2 * e], j = ent[2 * e + 1];
+        const uint32_t t = ent[2 * e], jc = ent[2 * e + 1];
         const uint32_t e_uv = med[3 * (uint64_t)t], e_uw = med[3 * (uint64_t)t + 1], e_vw = med[3 * (uint64_t)t + 2];
         const uint32_t a0 = eoff[2 * e_uv], a1 = eoff[2 * e_uv + 1], a2 = eoff[2 * e_uv + 2];
         const uint32_t b0 = eoff[2 * e_uw], b1 = eoff[2 * e_uw + 1], b2 = eoff[2 * e_uw + 2];
         const bool outer_uv = medium_outer_is_uv(a2 - a0, b2 - b0);
-        const uint32_t o0 = outer_uv ? a0 : b0, o1 = outer_uv ? a1 : b1;
+        const uint32_t o0 = outer_uv ? a0 : b0, o1 = outer_uv ? a1 : b1, o2 = outer_uv ? a2 : b2;
         const uint32_t i0 = outer_uv ? b0 : a0, i1 = outer_uv ? b1 : a1, i2 = outer_uv ? b2 : a2;
+        // this entry's outer edge and inner chunk [cb, ce): the inner direction runs [i0, i1) and
+        // [i1, i2) clipped to it
+        const uint32_t nc = medium_inner_chunks(o2 - o0, i2 - i0);
+        const uint32_t j = jc / nc, ch = jc - j * nc;
+        const uint32_t cb = nc > 1 ? i0 + ch * kInnerChunk : i0;
+        const uint32_t ce = nc > 1 && cb + kInnerChunk < i2 ? cb + kInnerChunk : i2;
+        const uint32_t r0b = cb < i1 ? cb : i1, r0e = ce < i1 ? ce : i1;
+        const uint32_t r1b = cb > i1 ? cb : i1, r1e = ce > i1 ? ce : i1;
         const uint32_t ox = o0 + j;
         flags = (outer_uv ? 1u : 0u) | (ox >= o1 ? 2u : 0u);
         kx = key[ox];
@@ -277,8 +300,8 @@ __device__ __forceinline__ uint32_t medium_lanes_eval(const uint32_t *__restrict
             klo = klo > q.klo ? klo : q.klo;
             khi = khi < q.khi ? khi : q.khi;
             uint32_t hi0, hi1;
-            lower2(key, i0, i1, klo, khi, lo0, hi0);
-            lower2(key, i1, i2, klo, khi, lo1, hi1);
+            lower2(key, r0b, r0e, klo, khi, lo0, hi0);
+            lower2(key, r1b, r1e, klo, khi, lo1, hi1);
             c0 = hi0 - lo0;
             c1 = hi1 - lo1;
             if (c0 + c1) {   // the {v,w} lists, clipped to the window

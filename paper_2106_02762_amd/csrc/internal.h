@@ -205,7 +205,7 @@ struct Schedule {
     std::vector<uint32_t> unit_index;   // host: first record of each t1 bucket, then n_unit
     DevMem light;       // uint32[3 * n_light]: (e_uv, e_uw, e_vw) DAG edge ids
     DevMem medium;      // uint32[3 * n_medium]
-    DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, outer edge) entries
+    DevMem mitems;      // uint32[2 * n_mitems]: (medium triangle, outer edge and inner chunk) entries
     uint64_t n_mitems = 0;
     // windowed copies of light, medium and mitems in window-cell order (the originals keep the
     // enumeration order, whose locality the whole-span count needs)

@@ -10,7 +10,8 @@
 // level l such that its pairs within D(l) = 2^(l-1) - 1 of each other fit, by binary search over
 // the levels with exact close-pair counts.  Contested triangles are sorted by descending level, so
 // that a whole-span query walks a prefix of the medium list and a suffix of the heavy list.  A
-// medium triangle becomes one entry per edge of its smaller source-incident pair; a heavy one
+// medium triangle becomes one entry per edge of its smaller source-incident pair (times the chunks
+// of its other one, when that one is long and the triangle not too large); a heavy one gets
 // count chunks of 256 source edges and prefix chunks of 256 edges of one list.  Unit records are
 // grouped by their first time and the light and medium lists copied in window-cell order (a
 // necessary condition on the pairs' first and last edge times), so that a query with a time
@@ -47,15 +48,17 @@ struct SplitRule {
 // The pair budget of a triangle outside the light rule: how many (uv edge, uw edge) pairs the
 // medium path may evaluate before its cost passes the prefix procedures' cost times cost_pct / 100.
 // Costs are counted in binary-search steps of the searches each path makes: the medium path pays 4
-// searches into the inner source pair per outer edge plus a fixed overhead, then about 10 searches
-// into the {v,w} lists per close pair; the prefix procedures pay per source edge 14 searches into
+// searches into the inner source pair (or into each chunk of it) per outer edge plus a fixed
+// overhead, then about 10 searches into the {v,w} lists per close pair; the prefix procedures pay per source edge 14 searches into
 // the other source pair and 24 into the {v,w} lists (prefix and count passes) plus an overhead.
 __device__ __forceinline__ double pair_budget(uint64_t s_uv, uint64_t s_uw, uint64_t s_vw, uint32_t cost_pct) {
     const double luv = ceil_log2_1((uint32_t)s_uv) + 1.0, luw = ceil_log2_1((uint32_t)s_uw) + 1.0,
                  lvw = ceil_log2_1((uint32_t)s_vw) + 1.0;
     const double heavy = (double)s_uv * (14.0 * luw + 24.0 * lvw + 12.0) + (double)s_uw * (14.0 * luv + 24.0 * lvw + 12.0);
     const bool outer_uv = cdev::medium_outer_is_uv((uint32_t)s_uv, (uint32_t)s_uw);
-    const double outer = (double)(outer_uv ? s_uv : s_uw) * (4.0 * (outer_uv ? luw : luv) + 8.0);
+    const uint32_t chunks = cdev::medium_inner_chunks((uint32_t)(outer_uv ? s_uv : s_uw), (uint32_t)(outer_uv ? s_uw : s_uv));
+    const double lin = chunks > 1 ? ceil_log2_1(cdev::kInnerChunk) + 1.0 : (outer_uv ? luw : luv);
+    const double outer = (double)(outer_uv ? s_uv : s_uw) * chunks * (4.0 * lin + 8.0);
     return (heavy * cost_pct / 100.0 - outer) / (10.0 * lvw + 6.0);
 }
 
@@ -451,14 +454,16 @@ __global__ void k_cell_items(const uint64_t *__restrict__ tstart, const uint64_t
 }
 
 // entries of the medium path: one per edge of the outer pair (the source-incident pair with fewer
-// temporal edges)
+// temporal edges) and chunk of the inner pair
 __global__ void k_medium_sizes(uint64_t nm, const uint32_t *__restrict__ med, const uint32_t *__restrict__ eoff,
                                uint64_t *__restrict__ nch) {
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nm) return;
     const uint32_t e_uv = med[3 * i], e_uw = med[3 * i + 1];
     const uint32_t s_uv = eoff[2 * e_uv + 2] - eoff[2 * e_uv], s_uw = eoff[2 * e_uw + 2] - eoff[2 * e_uw];
-    nch[i] = cdev::medium_outer_is_uv(s_uv, s_uw) ? s_uv : s_uw;
+    const bool outer_uv = cdev::medium_outer_is_uv(s_uv, s_uw);
+    const uint32_t s_out = outer_uv ? s_uv : s_uw, s_in = outer_uv ? s_uw : s_uv;
+    nch[i] = (uint64_t)s_out * cdev::medium_inner_chunks(s_out, s_in);
 }
 
 __global__ void k_medium_fill(uint64_t nm, const uint64_t *__restrict__ nch, const uint64_t *__restrict__ base,

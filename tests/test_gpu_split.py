@@ -5,6 +5,7 @@
   the forced paths, and in sweeps and batches.
 - Long lists (5,000 / 3,000 / 700 edges, many equal timestamps): the prefix pass spans many chunks
   per list and carries between them; windows cut lists inside chunks.
+- A short and a long source pair: the medium path's entries split the long one into chunks.
 - Theorem 1's work bound (Section 5): the instrumented count's visits stay within
   2 * 48 * degeneracy * m' at every d13 up to infinity, with counts equal to dt_count's.
 - The autotuner: a graph of 2^20 static triangles or more is tuned on its first build and a
@@ -78,6 +79,33 @@ def test_long_lists_prefix_chunks(ctx, path):
         # infinite deltas: the product identity (the oracle would enumerate 10^10 triples)
         st = dt.dt_graph_stats(b.h)
         assert int(b.count(INF, INF, INF).sum()) == st["sum_sigma3"]
+    b.free()
+
+
+@pytest.mark.parametrize("path", [0, 3])
+@pytest.mark.parametrize("sizes", [(3, 700, 900), (1, 2000, 40), (2, 513, 1025)])
+def test_medium_inner_chunks(ctx, path, sizes):
+    """Triangles with a short and a long source pair: the medium path's entries cover chunks of 512
+    inner edges (a chunk may straddle the inner pair's two direction runs, and a list of 513 or
+    1025 edges ends in a one-edge chunk).  Counts equal the oracle's across d13, with windows, in a
+    sweep and in a batch."""
+    g = synth.long_lists_graph(3, sizes=sizes, t_range=5000)
+    b = Built(ctx, g, g.name, path)
+    for d in [0, 1, 30, 300, 2000, INF]:
+        want = oracle.count(g.n, g.src, g.dst, g.t, d, d, d)
+        assert (b.count(d, d, d) == want).all(), (path, sizes, d)
+    for d in [(4000, 100, 3900), (500, 400, 60)]:
+        for lo, hi in [(dt.INT64_MIN, INF), (700, 3100), (2500, 2600)]:
+            want = oracle.count(g.n, g.src, g.dst, g.t, *d, lo, hi)
+            assert (b.count(*d, lo, hi) == want).all(), (path, sizes, d, lo, hi)
+    deltas = [(d, d, d) for d in (5, 300, INF)]
+    got = dt.dt_count_sweep(b.h, deltas)
+    for j, d in enumerate(deltas):
+        assert (got[j] == b.count(*d)).all(), (path, sizes, d)
+    qs = [dt.make_query(d, d, d) for d in (5, 300, INF)] + [dt.make_query(300, 300, 300, 700, 3100)]
+    got = dt.dt_count_batch(ctx, [b.h] * len(qs), qs)
+    for i, q in enumerate(qs):
+        assert (got[i] == dt.dt_count(b.h, q.d13, q.d12, q.d23, q.t_lo, q.t_hi)).all(), (path, sizes, i)
     b.free()
 
 
