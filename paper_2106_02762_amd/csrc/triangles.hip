@@ -511,40 +511,54 @@ k_tri(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restri
                     out.put(hit, __ballot(hit), lane, r0 + ci[x], e_uw, e_vw);
                 }
             }
-            // long walks into a long N+(v): copy N+(v) into LDS, then search it there
-            for (uint32_t i = part; i + kStage < du; i += parts) {
-                const uint32_t after = du - i - 1, outv = dv_lds[i];   // 0xffff: longer than any stage
-                if (!(outv > after && after >= kStage && outv <= kCap)) continue;
-                const uint32_t vb = vb_lds[i];
-                wave_cand += after;
-                const uint4 bi = binfo[nbr_lds[i]];
-                if (bi.y) {
-                    // N+(v) has a bitmap: one lookup per head of N+(u) after v
+            // long walks into a long N+(v): 64 positions of N+(u) are tested at once and the
+            // bitmap infos of those taken here loaded together; then each in turn searches its
+            // N+(v) by bitmap lookups or on an LDS copy
+            for (uint32_t i0 = part; i0 + kStage < du; i0 += parts * 64) {
+                const uint32_t il = i0 + lane * parts;
+                bool take = false;
+                uint4 bil = make_uint4(0, 0, 0, 0);
+                if (il + kStage < du) {
+                    const uint32_t after = du - il - 1, outv = dv_lds[il];   // 0xffff: longer than any stage
+                    take = outv > after && after >= kStage && outv <= kCap;
+                    if (take) bil = binfo[nbr_lds[il]];
+                }
+                for (uint64_t m = __ballot(take); m; m &= m - 1) {
+                    const int src = __ffsll((unsigned long long)m) - 1;
+                    const uint32_t i = i0 + (uint32_t)src * parts;
+                    const uint32_t after = du - i - 1, outv = dv_lds[i];
+                    const uint32_t vb = vb_lds[i];
+                    wave_cand += after;
+                    const uint4 bi = make_uint4(__shfl(bil.x, src, 64), __shfl(bil.y, src, 64), __shfl(bil.z, src, 64),
+                                                __shfl(bil.w, src, 64));
+                    if (bi.y) {
+                        // N+(v) has a bitmap: one lookup per head of N+(u) after v
+                        for (uint32_t b = 0; b < after; b += 64) {
+                            const uint32_t j = b + lane;
+                            bool hit = false;
+                            uint32_t pos = 0;
+                            if (j < after) hit = bm_find(bi, bslots, nbr_lds[i + 1 + j], pos);
+                            out.put(hit, __ballot(hit), lane, r0 + i, r0 + i + 1 + j, vb + pos);
+                        }
+                        continue;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    for (uint32_t j = lane; j < outv; j += 64) vn_lds[j] = dag_col[vb + j];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
                     for (uint32_t b = 0; b < after; b += 64) {
                         const uint32_t j = b + lane;
                         bool hit = false;
                         uint32_t pos = 0;
-                        if (j < after) hit = bm_find(bi, bslots, nbr_lds[i + 1 + j], pos);
+                        if (j < after) {
+                            const uint32_t w = nbr_lds[i + 1 + j];
+                            pos = find_u32(vn_lds, 0, outv, w);
+                            hit = pos < outv && vn_lds[pos] == w;
+                        }
                         out.put(hit, __ballot(hit), lane, r0 + i, r0 + i + 1 + j, vb + pos);
                     }
-                    continue;
+                    __builtin_amdgcn_wave_barrier();
                 }
-                __builtin_amdgcn_wave_barrier();
-                for (uint32_t j = lane; j < outv; j += 64) vn_lds[j] = dag_col[vb + j];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                for (uint32_t b = 0; b < after; b += 64) {
-                    const uint32_t j = b + lane;
-                    bool hit = false;
-                    uint32_t pos = 0;
-                    if (j < after) {
-                        const uint32_t w = nbr_lds[i + 1 + j];
-                        pos = find_u32(vn_lds, 0, outv, w);
-                        hit = pos < outv && vn_lds[pos] == w;
-                    }
-                    out.put(hit, __ballot(hit), lane, r0 + i, r0 + i + 1 + j, vb + pos);
-                }
-                __builtin_amdgcn_wave_barrier();
             }
         } else {
             // N+(u) larger than the LDS slice: the same candidates, v by v, on global memory (the
