@@ -33,18 +33,32 @@ def log(*a):
 
 # source file of each event-timed kernel (the HBM traffic measured for a kernel is reported only
 # while its source is unchanged since the counters were taken)
-KERNEL_SOURCE = {"peel": "peel.hip", "peel_adj": "peel.hip", "peel_tail": "peel.hip", "core": "core.hip",
-                 "relayout": "orient.hip", "tri_count": "triangles.hip", "tri_fill": "triangles.hip",
-                 "light": "count.hip", "medium": "count.hip", "unit": "count.hip",
-                 "heavy_prefix": "count.hip", "heavy_count": "count.hip", "reduce": "count.hip"}
+# the source files each kernel is compiled from (its .hip file and the library headers it includes);
+# a counter record holds the sha256 of their concatenation in this order
+_HDR = ["internal.h", "count_dev.h"]
+KERNEL_SOURCE = {"peel": ["peel.hip", "internal.h"], "peel_adj": ["peel.hip", "internal.h"],
+                 "peel_tail": ["peel.hip", "internal.h"], "core": ["core.hip", "internal.h"],
+                 "relayout": ["orient.hip", "internal.h"], "tri_count": ["triangles.hip"] + _HDR,
+                 "tri_fill": ["triangles.hip"] + _HDR, "light": ["count.hip"] + _HDR,
+                 "medium": ["count.hip"] + _HDR, "unit": ["count.hip"] + _HDR,
+                 "heavy_prefix": ["count.hip"] + _HDR, "heavy_count": ["count.hip"] + _HDR,
+                 "reduce": ["count.hip"] + _HDR}
+
+
+def source_sha256(kernel):
+    """sha256 of the concatenated source files of `kernel` (KERNEL_SOURCE order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCE[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2106_02762_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_full_graph.md")
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE plus
     WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is none for this
-    kernel or its source has changed since."""
-    import hashlib
+    kernel or any of its source files has changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     # records of "- key: `value`" lines, each starting with its "- kernel:" line
@@ -60,8 +74,7 @@ def measured_traffic(kernel):
     fields = records.get(kernel, {})
     if not fields or kernel not in KERNEL_SOURCE:
         return None
-    src = os.path.join(ROOT, "paper_2106_02762_amd", "csrc", KERNEL_SOURCE[kernel])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+    if source_sha256(kernel) != fields.get("source_sha256"):
         return None
     try:
         return int(fields["fetch_bytes_per_launch"]) + int(fields["write_bytes_per_launch"])
