@@ -477,6 +477,15 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(dom), "alg_bytes": int(alg[dom]),
                 "avg_ms": round(mean[dom], 4)}
+    # the same figures for every build kernel of a millisecond or more (the peel's grid kernel and
+    # the enumeration take within a few percent of the same time)
+    roofline_by_kernel = {}
+    for k in sorted(mean, key=lambda k: -mean[k]):
+        if mean[k] >= 1.0 and alg.get(k):
+            a = alg[k] / (mean[k] / 1e3) / 1e9
+            roofline_by_kernel[k] = {"avg_ms": round(mean[k], 4), "alg_bytes": int(alg[k]),
+                                     "achieved": round(a, 2), "frac": round(a / HBM_PEAK_GBS, 5),
+                                     "traffic": measured_traffic(k)}
     count_kernels = {k: round(mean[k], 4) for k in ("unit", "light", "medium", "heavy_prefix",
                                                      "heavy_count", "reduce")}
 
@@ -583,6 +592,7 @@ def main():
                   "tri_candidates": st["tri_candidates"],
                   "alg_bytes_count": st["alg_bytes"]},
         "roofline": roofline,
+        "roofline_by_kernel": roofline_by_kernel,
         "count_roofline": count_roofline(st, count_ms[str(d)], count_kernels),
         "cpu_baseline": cpu,
         "parity_whole_span": parity,
