@@ -156,43 +156,59 @@ __global__ void k_long_runs(uint32_t n, const uint32_t *__restrict__ dag_row, un
     if (is_long) longs[base + (unsigned)__popcll(m & ((1ull << lane) - 1))] = t;
 }
 
-// Runs longer than 64: one workgroup per run, a bitonic sort of (head, index) keys in LDS (runs
-// past kLongCap entries, beyond any degeneracy met in practice, are ranked in global memory).
+// Runs longer than 64: one workgroup per run.  Heads within a run are distinct, so an entry's place
+// is the number of heads below its own: the run's heads are staged in LDS and every thread counts,
+// for each of its entries (held in registers), the heads below it in one pass over them (each LDS
+// read serves the whole wavefront; no barrier between compare steps).  Runs past kLongCap entries,
+// beyond any degeneracy met in practice, are ranked the same way in global memory.
 constexpr uint32_t kLongCap = 2048;
+constexpr uint32_t kLongPer = kLongCap / kBlock;   // entries of a run per thread
+
+// pos[e] += heads of sh[0, L) below rec[e].x, for the first M entries
+template <int M>
+__device__ __forceinline__ void count_below(const uint32_t *sh, uint32_t L, const uint4 (&rec)[kLongPer],
+                                            uint32_t (&pos)[kLongPer]) {
+    for (uint32_t j = 0; j < L; ++j) {
+        const uint32_t hj = sh[j];
+#pragma unroll
+        for (int e = 0; e < M; ++e) pos[e] += hj < rec[e].x ? 1u : 0u;
+    }
+}
 
 __global__ void __launch_bounds__(kBlock)
 k_dag_sort_long(const unsigned *__restrict__ n_long_p, const uint32_t *__restrict__ longs,
                 const uint32_t *__restrict__ dag_row, const uint4 *__restrict__ runs,
                 uint32_t *__restrict__ dag_col, uint32_t *__restrict__ dag_of, uint32_t *__restrict__ gsize) {
-    __shared__ uint64_t sk[kLongCap];
+    __shared__ uint32_t sh[kLongCap];
     const unsigned n_long = *n_long_p;
     for (unsigned li = blockIdx.x; li < n_long; li += gridDim.x) {
         const uint32_t r = longs[li];
         const uint32_t b = dag_row[r], L = dag_row[r + 1] - b;
         if (L <= kLongCap) {
-            uint32_t P = 64;
-            while (P < L) P <<= 1;
-            for (uint32_t i = threadIdx.x; i < P; i += kBlock)
-                sk[i] = i < L ? ((uint64_t)runs[b + i].x << 32) | i : ~0ull;
-            __syncthreads();
-            for (uint32_t k = 2; k <= P; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
-                        const uint32_t p = i ^ j;
-                        if (p > i) {
-                            const uint64_t x = sk[i], y = sk[p];
-                            const bool up = (i & k) == 0;
-                            if ((x > y) == up) {
-                                sk[i] = y;
-                                sk[p] = x;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
+            uint4 rec[kLongPer];
+            uint32_t pos[kLongPer];
+#pragma unroll
+            for (uint32_t e = 0; e < kLongPer; ++e) {
+                const uint32_t i = threadIdx.x + e * kBlock;
+                rec[e] = i < L ? runs[b + i] : make_uint4(0, 0, 0, 0);
+                if (i < L) sh[i] = rec[e].x;
+                pos[e] = 0;
             }
-            for (uint32_t i = threadIdx.x; i < L; i += kBlock)
-                dag_edge(b + i, runs[b + (uint32_t)sk[i]], dag_col, dag_of, gsize);
+            __syncthreads();
+            const uint32_t mine = (L > threadIdx.x ? L - threadIdx.x + kBlock - 1 : 0) / kBlock;   // entries held
+            switch ((L + kBlock - 1) / kBlock) {   // the most entries a thread holds (uniform)
+                case 1: count_below<1>(sh, L, rec, pos); break;
+                case 2: count_below<2>(sh, L, rec, pos); break;
+                case 3: count_below<3>(sh, L, rec, pos); break;
+                case 4: count_below<4>(sh, L, rec, pos); break;
+                case 5: count_below<5>(sh, L, rec, pos); break;
+                case 6: count_below<6>(sh, L, rec, pos); break;
+                case 7: count_below<7>(sh, L, rec, pos); break;
+                default: count_below<8>(sh, L, rec, pos); break;
+            }
+#pragma unroll
+            for (uint32_t e = 0; e < kLongPer; ++e)
+                if (e < mine) dag_edge(b + pos[e], rec[e], dag_col, dag_of, gsize);
             __syncthreads();
         } else {
             for (uint32_t i = threadIdx.x; i < L; i += kBlock) {

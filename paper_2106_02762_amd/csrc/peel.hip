@@ -802,9 +802,10 @@ int peel(dt_graph *g) {
     g->kappa = h.kappa;
     g->peel_rounds = h.rounds;
     g->alg_bytes_peel = 16ull * n + 16ull * g->m_s;
+    // the ranks (what the orientation reads next, on the same stream); the temporaries released on
+    // return were last used by kernels the read-back above waited for
     k_finish<<<grid_for(n, 256), 256, 0, st>>>(n, queue, g->rank.as<uint32_t>());
     DT_HIP(hipGetLastError());
-    DT_HIP(hipStreamSynchronize(st));
     return DT_OK;
 }
 
