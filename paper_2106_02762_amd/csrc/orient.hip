@@ -86,7 +86,8 @@ __device__ __forceinline__ void dag_edge(uint64_t d, uint4 r, uint32_t *__restri
 
 // Sort every run by head rank (heads are distinct).  Wavefronts take chunks of kTailChunk tails
 // from a work counter; runs that fit together in 64 lanes are loaded in one piece and sorted at
-// once by a bitonic network on (run, head).  Longer runs are left to k_dag_sort_long.
+// once: each entry placed at the number of (run, head) keys below its own, or, past 2^26
+// vertices, by a bitonic network on (run, head).  Longer runs are left to k_dag_sort_long.
 constexpr uint32_t kTailChunk = 64;
 
 __global__ void __launch_bounds__(kBlock)
@@ -120,6 +121,16 @@ k_dag_sort(uint32_t n, const uint32_t *__restrict__ dag_row, const uint4 *__rest
             if (lane < len) {
                 rec = runs[b + lane];
                 key = ((uint64_t)seg << 32) | rec.x;
+            }
+            if (n <= (1u << 26)) {
+                // (run, head) fits 32 bits and is distinct per lane: each entry's place is the number
+                // of lanes with a smaller one
+                const uint32_t k32 = lane < len ? (seg << 26) | rec.x : 0xffffffffu;
+                uint32_t pos = 0;
+                for (uint32_t q = 0; q < len; ++q) pos += __shfl(k32, q, 64) < k32 ? 1u : 0u;
+                if (lane < len) dag_edge(b + pos, rec, dag_col, dag_of, gsize);
+                r += cnt;
+                continue;
             }
 #pragma unroll
             for (unsigned k = 2; k <= 64; k <<= 1) {

@@ -416,13 +416,23 @@ __global__ void k_contest_place(uint64_t nc, const uint4 *__restrict__ crec, uin
 
 // bucket starts from the sorted bucket keys: start[x] for every x in (key[j - 1], key[j]] is j;
 // j = nu closes the array at nbk
+// first position of every bucket 0..nbk in the nu sorted bucket keys (a binary search per bucket;
+// nu for nbk and for buckets past the last key)
 __global__ void k_unit_starts(uint64_t nu, uint32_t nbk, const uint16_t *__restrict__ bkt,
                               uint32_t *__restrict__ start) {
-    uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j > nu) return;
-    const int64_t cur = j < nu ? (int64_t)bkt[j] : (int64_t)nbk;
-    const int64_t prev = j > 0 ? (int64_t)bkt[j - 1] : -1;
-    for (int64_t x = prev + 1; x <= cur; ++x) start[x] = (uint32_t)j;
+    const uint32_t x = blockIdx.x * kBlock + threadIdx.x;
+    if (x > nbk) return;
+    uint64_t lo = 0, len = nu;
+    while (len > 0) {
+        const uint64_t half = len >> 1;
+        if (bkt[lo + half] < x) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    start[x] = (uint32_t)lo;
 }
 
 // first position of every key value 0..nk-1 in a sorted key array (nk + 1 entries, the last = n)
@@ -603,6 +613,28 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     DT_TRY(dev_alloc(ctx, bcnt, (uint64_t)grid * kClasses * 4));
     DT_TRY(dev_alloc(ctx, part, (uint64_t)grid * kPartWords * 8));
     DT_TRY(dev_alloc(ctx, base, (uint64_t)grid * kClasses * 8));
+    // the per-edge unit keys (when unit records are allowed) on the first side stream, beside the
+    // classify pass; the partition pass waits for them
+    const bool units = R.force == 0 && R.unit_ok && g->m_s;
+    const hipStream_t ks = units && ctx->side[0] ? ctx->side[0] : st;
+    DevMem ukey;
+    DT_TRY(dev_alloc(ctx, ukey, (units ? g->m_s : 0) * 8));
+    struct KeyJoin {   // an early return must not release ukey while the side stream writes it
+        hipStream_t s, main;
+        ~KeyJoin() {
+            if (s != main) (void)hipStreamSynchronize(s);
+        }
+    } kjoin{ks, st};
+    if (units) {
+        if (ks != st) {
+            DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
+            DT_HIP(hipStreamWaitEvent(ks, ctx->ev_relay[0], 0));
+        }
+        k_unit_keys<<<grid_for(g->m_s, kBlock), kBlock, 0, ks>>>(g->m_s, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
+                                                                 ukey.as<uint64_t>());
+        DT_HIP(hipGetLastError());
+        if (ks != st) DT_HIP(hipEventRecord(ctx->ev_relay[1], ks));
+    }
     k_classify<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), g->eoff.as<uint32_t>(), R, cls.as<uint8_t>(),
                                         bcnt.as<uint32_t>(), part.as<uint64_t>());
     DT_HIP(hipGetLastError());
@@ -653,13 +685,7 @@ int make_schedule(dt_graph *g, DevMem &tri) {
     DT_TRY(dev_alloc(ctx, mkey, nm * 2));
     DT_TRY(dev_alloc(ctx, crec, nc * sizeof(uint4)));
     DT_TRY(dev_alloc(ctx, ckey, nc * 2));
-    DevMem ukey;
-    DT_TRY(dev_alloc(ctx, ukey, (nu ? g->m_s : 0) * 8));
-    if (nu) {
-        k_unit_keys<<<grid_for(g->m_s, kBlock), kBlock, 0, st>>>(g->m_s, g->eoff.as<uint32_t>(), g->key.as<uint64_t>(),
-                                                                 ukey.as<uint64_t>());
-        DT_HIP(hipGetLastError());
-    }
+    if (units && ks != st) DT_HIP(hipStreamWaitEvent(st, ctx->ev_relay[1], 0));
     if (nt) {
         k_partition<<<grid, kBlock, 0, st>>>(nt, tri.as<uint32_t>(), cls.as<uint8_t>(), base.as<uint64_t>(),
             g->eoff.as<uint32_t>(), g->key.as<uint64_t>(), ukey.as<uint64_t>(), g->shift, S.unit_shift, S.cell_shift, nc,
@@ -696,8 +722,8 @@ int make_schedule(dt_graph *g, DevMem &tri) {
         }
         DT_TRY(sort_pairs_u16_u4(ctx, ubkt.as<uint16_t>(), ubkt2.as<uint16_t>(), urec.as<uint4>(), S.unit.as<uint4>(),
                                  nu, 16, us, us != st ? &usort_tmp : nullptr));
-        k_unit_starts<<<grid_for(nu + 1, kBlock), kBlock, 0, us>>>(nu, (uint32_t)nbk, ubkt2.as<uint16_t>(),
-                                                                   ustart.as<uint32_t>());
+        k_unit_starts<<<grid_for(nbk + 1, kBlock), kBlock, 0, us>>>(nu, (uint32_t)nbk, ubkt2.as<uint16_t>(),
+                                                                    ustart.as<uint32_t>());
         DT_HIP(hipGetLastError());
         S.unit_index.resize(nbk + 1);
         DT_HIP(hipMemcpyAsync(ctx->pinned_stage + kStageUnit, ustart.ptr, (nbk + 1) * 4, hipMemcpyDeviceToHost, us));
