@@ -261,7 +261,7 @@ struct dt_graph {
                                 //                    head->tail edges [eoff[2d+1], eoff[2d+2])
     dt::DevMem key;             // uint64[m]: keys in that layout
     bool relay_pending = false; // key is still being written on the context's side[0] stream
-    dt::DevMem relay_tmp[2];    // inputs of that re-layout, held until it is joined
+    dt::DevMem relay_tmp[4];    // inputs and temporaries of that re-layout, held until it is joined
     uint64_t n_tri = 0;
     uint64_t n_tri_list = 0;    // entries of the triangle list the last schedule was made from (with empty ones)
     unsigned __int128 sum_sigma3 = 0;
@@ -433,7 +433,10 @@ int sort_pairs_u64_u64(dt_ctx *ctx, const uint64_t *kin, uint64_t *kout, const u
 // a side stream, whose caller releases it after the join
 int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const uint4 *vin, uint4 *vout,
                       size_t n, int end_bit, hipStream_t s, DevMem *keep = nullptr);
-int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s);
+// (keep: with a stream other than the context's, hand the temporary to the caller, who releases it
+// after joining that stream, instead of waiting for the stream here)
+int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s,
+                       DevMem *keep = nullptr);
 int exclusive_scan_u64(dt_ctx *ctx, const uint64_t *in, uint64_t *out, size_t n, hipStream_t s);
 
 // timing helper

@@ -273,8 +273,7 @@ int relayout_join(dt_graph *g) {
     g->relay_pending = false;
     const hipError_t e = hipStreamWaitEvent(g->ctx->stream, g->ctx->ev_relay[1], 0);
     // released in stream order on the context's stream, now behind the re-layout
-    g->relay_tmp[0].reset();
-    g->relay_tmp[1].reset();
+    for (DevMem &t : g->relay_tmp) t.reset();
     if (e != hipSuccess) return fail(DT_EDEVICE, "hipStreamWaitEvent failed: %s", hipGetErrorString(e));
     return DT_OK;
 }
@@ -343,15 +342,18 @@ int orient(dt_graph *g, bool overlap) {
         k_max_u32<<<grid, kBlock, 0, st>>>(n, g->dag_row.as<uint32_t>(), scal.as<unsigned>());
         DT_HIP(hipGetLastError());
     }
-    DT_TRY(exclusive_scan_u32(ctx, gsize.as<uint32_t>(), g->eoff.as<uint32_t>(), ngroups + 1, st));
+    // with overlap the store offsets' scan and the re-layout go to side[0] and keep their inputs
+    // and temporaries alive until relayout_join; nothing on the context's stream reads g->eoff or
+    // g->key before that (the enumeration reads only the DAG)
+    const hipStream_t rs = overlap && m && ctx->side[0] ? ctx->side[0] : st;
+    if (rs != st) {
+        DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
+        DT_HIP(hipStreamWaitEvent(rs, ctx->ev_relay[0], 0));
+    }
+    DevMem scan_tmp;
+    DT_TRY(exclusive_scan_u32(ctx, gsize.as<uint32_t>(), g->eoff.as<uint32_t>(), ngroups + 1, rs,
+                              rs != st ? &scan_tmp : nullptr));
     if (m) {
-        // with overlap the re-layout goes to side[0] and keeps its two temporaries alive until
-        // relayout_join; nothing on the context's stream reads g->key before that
-        hipStream_t rs = overlap && ctx->side[0] ? ctx->side[0] : st;
-        if (rs != st) {
-            DT_HIP(hipEventRecord(ctx->ev_relay[0], st));
-            DT_HIP(hipStreamWaitEvent(rs, ctx->ev_relay[0], 0));
-        }
         prof_begin(ctx, kProfRelayout, rs);
         k_relayout<<<grid_for(m, kBlock), kBlock, 0, rs>>>(m, g->psid.as<uint32_t>(), g->pdir.as<uint8_t>(),
             g->pstart.as<uint32_t>(), g->c1.as<uint32_t>(), dag_of.as<uint32_t>(), sflip.as<uint8_t>(),
@@ -362,6 +364,8 @@ int orient(dt_graph *g, bool overlap) {
             DT_HIP(hipEventRecord(ctx->ev_relay[1], rs));
             g->relay_tmp[0] = std::move(dag_of);
             g->relay_tmp[1] = std::move(sflip);
+            g->relay_tmp[2] = std::move(gsize);
+            g->relay_tmp[3] = std::move(scan_tmp);
             g->relay_pending = true;
         }
     }

@@ -187,7 +187,7 @@ int sort_pairs_u16_u4(dt_ctx *ctx, const uint16_t *kin, uint16_t *kout, const ui
     return DT_OK;
 }
 
-int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s) {
+int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n, hipStream_t s, DevMem *keep) {
     if (n == 0) return DT_OK;
     size_t bytes = 0;
     DT_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, 0u, n, rocprim::plus<uint32_t>(), s));
@@ -195,8 +195,11 @@ int exclusive_scan_u32(dt_ctx *ctx, const uint32_t *in, uint32_t *out, size_t n,
     DT_TRY(dev_alloc(ctx, tmp, bytes));
     DT_HIP(rocprim::exclusive_scan(tmp.ptr, bytes, in, out, 0u, n, rocprim::plus<uint32_t>(), s));
     // the temporary goes back to the context's cache, whose blocks are reused in stream order on
-    // the context's stream only: another stream must finish with it first
-    if (s != ctx->stream) DT_HIP(hipStreamSynchronize(s));
+    // the context's stream only: another stream must finish with it first (or the caller keeps it)
+    if (s != ctx->stream) {
+        if (keep) *keep = std::move(tmp);
+        else DT_HIP(hipStreamSynchronize(s));
+    }
     return DT_OK;
 }
 
