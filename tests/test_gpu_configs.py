@@ -9,6 +9,9 @@
 - A 100-clique with three temporal edges on every pair: 161,700 triangles on 4,950 pairs, all of
   them past the light rule, through the cached build (every path) and the one-shot pass (whose
   list of medium triangles overflows its first size).
+- Ranks past 2^26 (2^26 + 4096 vertices, the edges among the last ids): the orientation's runs of
+  at most 64 entries then take the bitonic network instead of 32-bit key counting; a 90-clique
+  gives runs longer than 64 as well.
 - dt_count_async on the context's stream and on a foreign stream, into device and pinned memory.
 - Sixteen graphs of the 512-graph batched workload in one dt_count_batch call, each with its own
   delta triple, against the oracle.
@@ -102,6 +105,37 @@ def test_dense_clique_more_triangles_than_pairs(ctx, path):
         dt.dt_graph_build(b.h)
         want = oracle.count(g.n, g.src, g.dst, g.t, 20000, 5000, 18000)
         assert (b.count(20000, 5000, 18000) == want).all()
+    b.free()
+
+
+def test_ranks_beyond_2_26(ctx):
+    n = (1 << 26) + 4096
+    rng = np.random.default_rng(5)
+    ids = n - 1 - rng.permutation(4096)[:200]
+    src, dst = [], []
+    for k, off in ((90, 0), (40, 90)):
+        c = ids[off:off + k]
+        a, b = np.triu_indices(k, 1)
+        src.append(c[a])
+        dst.append(c[b])
+    x, y = rng.choice(ids, 600), rng.choice(ids, 600)
+    src.append(x[x != y])
+    dst.append(y[x != y])
+    src, dst = np.concatenate(src).astype(np.uint32), np.concatenate(dst).astype(np.uint32)
+    flip = rng.random(src.shape[0]) < 0.5
+    src, dst = np.where(flip, dst, src), np.where(flip, src, dst)
+    t = rng.integers(0, 10000, src.shape[0]).astype(np.int64)
+    o = np.argsort(t, kind="stable")
+    g = synth.TemporalGraph(n, src[o], dst[o], t[o], name="ranks_past_2^26")
+    b = Built(ctx, g, g.name)
+    st = dt.dt_graph_stats(b.h)
+    assert st["max_out_degree"] > 64
+    for d in [(3000, 2000, 2500), (INF, INF, INF), (40, 30, 20)]:
+        want = oracle.count(g.n, g.src, g.dst, g.t, *d)
+        assert (b.count(*d) == want).all(), d
+    say("one-shot", g.name)
+    want = oracle.count(g.n, g.src, g.dst, g.t, 3000, 2000, 2500)
+    assert (dt.dt_count_oneshot(b.h, 3000, 2000, 2500) == want).all()
     b.free()
 
 
