@@ -48,9 +48,9 @@ static_assert(kChunkTri >= kOut, "a buffer fits a fresh chunk");
 constexpr int kBatchBuild = 4;    // blocks of 64 flattened candidates a lane works on at once
 constexpr int kBatchFused = 1;    // (one in the one-shot pass: its counting holds the registers)
 constexpr uint32_t kBmMin = 16;      // heads of N+(v) at least for a bitmap
-constexpr uint32_t kBmWin = 16384;   // ranks a bitmap spans at most (512 words)
+constexpr uint32_t kBmWin = 32768;   // ranks a bitmap spans at most (1024 words)
 constexpr uint32_t kBmWords = kBmWin / 32;
-constexpr uint64_t kBmBudgetSlots = 1ull << 27;   // bitmap words of one graph at most (1 GiB)
+constexpr uint64_t kBmBudgetSlots = 1ull << 28;   // bitmap words of one graph at most (2 GiB)
 
 // Bitmap of N+(v): info = (first head, words, slot base low, slot base high); words = 0: none.
 // Slot x holds (heads before word x) << 32 | word x.  Returns whether w is a head of v and its
@@ -90,8 +90,8 @@ __global__ void k_bm_info(uint32_t n, const uint32_t *__restrict__ dag_row, cons
     info[v] = make_uint4(nw ? dag_col[dag_row[v]] : 0u, nw, (uint32_t)b, (uint32_t)(b >> 32));
 }
 
-// the slots of every bitmap: one wavefront per vertex builds its words in LDS, then their prefix
-// popcounts (lane l owns words [8 l, 8 l + 8))
+// the slots of every bitmap: one wavefront per vertex builds its words in LDS, then writes them 64
+// at a time with the running count of heads before each (a wave scan per 64 words)
 __global__ void __launch_bounds__(256)
 k_bm_fill(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__restrict__ dag_col,
           const uint4 *__restrict__ info, uint64_t *__restrict__ slots) {
@@ -101,9 +101,10 @@ k_bm_fill(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__re
     const uint32_t nw_all = gridDim.x * 4;
     for (uint32_t v = blockIdx.x * 4 + wave; v < n; v += nw_all) {
         const uint4 in = info[v];
-        if (in.y == 0) continue;
+        const uint32_t nw = in.y;   // words of this bitmap (at most kBmWords)
+        if (nw == 0) continue;
         const uint32_t vb = dag_row[v], outv = dag_row[v + 1] - vb;
-        for (uint32_t x = lane; x < kBmWords; x += 64) bm[x] = 0;
+        for (uint32_t x = lane; x < nw; x += 64) bm[x] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         for (uint32_t j = lane; j < outv; j += 64) {
@@ -112,26 +113,20 @@ k_bm_fill(uint32_t n, const uint32_t *__restrict__ dag_row, const uint32_t *__re
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        constexpr uint32_t kPer = kBmWords / 64;
-        uint32_t c[kPer], sum = 0;
-#pragma unroll
-        for (uint32_t x = 0; x < kPer; ++x) {
-            c[x] = (uint32_t)__popc(bm[kPer * lane + x]);
-            sum += c[x];
-        }
-        uint32_t incl = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, 64);
-            if (lane >= (unsigned)o) incl += y;
-        }
-        uint32_t run = incl - sum;
         const uint64_t base = (uint64_t)in.w << 32 | in.z;
+        uint32_t carry = 0;
+        for (uint32_t w0 = 0; w0 < nw; w0 += 64) {
+            const uint32_t wx = w0 + lane;
+            const uint32_t word = wx < nw ? bm[wx] : 0u;
+            const uint32_t c = (uint32_t)__popc(word);
+            uint32_t incl = c;
 #pragma unroll
-        for (uint32_t x = 0; x < kPer; ++x) {
-            const uint32_t wx = kPer * lane + x;
-            if (wx < in.y) slots[base + wx] = (uint64_t)run << 32 | bm[wx];
-            run += c[x];
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= (unsigned)o) incl += y;
+            }
+            if (wx < nw) slots[base + wx] = (uint64_t)(carry + incl - c) << 32 | word;
+            carry += __shfl(incl, 63, 64);
         }
         __builtin_amdgcn_wave_barrier();
     }
